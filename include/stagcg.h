@@ -1,0 +1,268 @@
+/*
+ * stagcg — staggered-fermion D_slash and conjugate-gradient solves on MI355X
+ * (gfx950), C ABI.
+ *
+ * The library implements the hot path of P. Majumdar, "Lattice Simulations
+ * using OpenACC compilers" (LATTICE 2013, arXiv:1311.2719): the staggered
+ * matrix-vector routine of Sec. 3, called repeatedly inside the
+ * conjugate-gradient solve of the normal operator of Sec. 4.
+ *
+ * Conventions (fixed here because the paper elides the operator's body):
+ *   sites      lexicographic s = x + Lx*(y + Ly*(z + Lz*t)); mu = 0..3 = x,y,z,t;
+ *              every extent even and >= 2; parity(x) = (x+y+z+t) mod 2,
+ *              0 = even, 1 = odd;
+ *   operator   (D chi)(x) = 1/2 sum_mu eta_mu(x) [U_mu(x) chi(x+mu)
+ *                                             - U_mu(x-mu)^dagger chi(x-mu)],
+ *              eta_mu(x) = (-1)^(x_0 + ... + x_{mu-1}); periodic in x,y,z;
+ *              a hop across the t boundary carries -1 if the field is
+ *              antiperiodic in t.  D is anti-Hermitian and maps even <-> odd;
+ *   solve      (m^2 - D^2) x = b (= M^dagger M x = b with M = m + D), which
+ *              is block-diagonal in parity: each parity is an independent
+ *              system.  The paper's CG runs on one half of the lattice from
+ *              x = 0 and reconstructs y = D x on the other half (Sec. 4).
+ *
+ * Fermion-field layout ("even-odd layout", the paper's p(l,ic) indexing with
+ * the lattice split into halves, one colour column after another):
+ *   complex128 [parity 2][colour 3][Vh], Vh = V/2, interleaved (re, im);
+ *   within a parity the site index is cb = s >> 1 (s lexicographic).
+ *   A full-lattice field is the even half followed by the odd half.
+ *   stag_pack_fermion / stag_unpack_fermion convert from / to the
+ *   lexicographic [V][3] complex128 layout.
+ *
+ * Gauge-field input layout: complex128 [V][4][3][3], U_mu(x)[a][b] row-major.
+ *
+ * Memory: the caller supplies one device buffer (the arena) at stag_create;
+ * the library sub-allocates all device memory from it and never calls
+ * hipMalloc.  The arena size is the HBM budget used for admission.  Small
+ * pinned host buffers for status polling are allocated with hipHostMalloc.
+ *
+ * Streams: calls that take a `stream` argument enqueue work on that HIP
+ * stream (NULL = the context's stream) and are asynchronous unless stated.
+ *
+ * Errors: every function returns int32: 0 = OK, 1 = PENDING, negative =
+ * error (STAG_E*).  Nothing aborts or throws across the ABI.  The message of
+ * the last error on the calling thread is returned by stag_last_error.
+ *
+ * Threading: one context per device.  stag_submit / stag_poll / stag_wait
+ * are thread-safe; other calls on one context must not run concurrently.
+ */
+#ifndef STAGCG_H
+#define STAGCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define STAG_OK          0
+#define STAG_PENDING     1
+#define STAG_EINVAL     -1   /* bad argument (odd extent, m <= 0, bad parity, range) */
+#define STAG_ENOMEM     -2   /* arena exhausted */
+#define STAG_ENOENT     -3   /* unknown gauge id or ticket */
+#define STAG_EBUSY      -4   /* gauge field still in use by queued requests */
+#define STAG_EAGAIN     -5   /* request queue full */
+#define STAG_ENOCONV    -6   /* iteration limit reached; x holds the last iterate */
+#define STAG_EBREAKDOWN -7   /* <p,Ap> <= 0 or not finite */
+#define STAG_ENONFINITE -8   /* NaN / Inf in the input */
+#define STAG_EHIP       -9   /* HIP runtime error */
+#define STAG_ECANCELED -10   /* request cancelled (context destroyed) */
+
+/* ---- enumerations ---------------------------------------------------- */
+enum { STAG_EVEN = 0, STAG_ODD = 1, STAG_ALL = 2 };
+enum {
+    STAG_FP64 = 0,     /* plain FP64 CG (the paper's precision) */
+    STAG_FP32_RU = 1,  /* FP32 inner CG, FP64 reliable updates */
+    STAG_FP16_RU = 2   /* FP16 storage with per-site norm, FP32 arithmetic,
+                          FP64 reliable updates */
+};
+
+typedef struct stag_ctx stag_ctx;
+
+typedef struct {
+    double mass;           /* m > 0 */
+    double tol;            /* stop when ||b - A x|| <= tol ||b|| per parity system */
+    int32_t maxiter;       /* CG iteration limit (per parity system) */
+    int32_t precision;     /* STAG_FP64, STAG_FP32_RU, STAG_FP16_RU */
+    int32_t parity;        /* STAG_EVEN, STAG_ODD, STAG_ALL */
+    int32_t max_restarts;  /* FP64: restarts from the true residual (>= 0) */
+    double delta;          /* reliable-update threshold (mixed precision): update when
+                              ||r|| < delta * (largest ||r|| since the last update);
+                              <= 0 selects 0.1 */
+} stag_cg_params;
+
+typedef struct {
+    int32_t status;            /* STAG_OK or a negative STAG_E* code */
+    int32_t iters;             /* CG iterations (largest over the parity systems) */
+    int32_t reliable_updates;  /* FP64 residual recomputations (incl. the final check) */
+    int32_t restarts;          /* FP64 mode: restarts after a failed true-residual check */
+    double true_rel_resid;     /* ||b - A x|| / ||b|| in FP64 on the GPU, over the solved parities */
+    double seconds;            /* wall time of the solve (cg_solve) or submit->completion (serving) */
+    double queue_seconds;      /* serving: submit -> admission into a batch slot */
+} stag_cg_info;
+
+/* ---- context --------------------------------------------------------- */
+
+/*
+ * Create a context on HIP device `device`.  `arena_dev` / `arena_bytes`: a
+ * device buffer owned by the caller that must outlive the context; every
+ * device allocation of the library is carved out of it.  `stream`: default
+ * HIP stream for the context (NULL = the null stream).  On success *out
+ * receives the context.  Errors: EINVAL (NULL pointers, arena < 1 MiB),
+ * EHIP.
+ */
+int stag_create(int device, void *arena_dev, size_t arena_bytes, void *stream,
+                stag_ctx **out);
+
+/* Destroy the context: stops the serving thread (queued requests end with
+ * ECANCELED), waits for the device, releases host resources.  The arena is
+ * not freed (the caller owns it). */
+int stag_destroy(stag_ctx *ctx);
+
+/* Message of the last error raised on the calling thread ("" if none). */
+const char *stag_last_error(void);
+
+/* Bytes of the arena in use / total. */
+int stag_arena_usage(const stag_ctx *ctx, size_t *used, size_t *total);
+
+/* ---- gauge fields (Sec. 4: `linkc_acc` and the data region's copyin) -- */
+
+/*
+ * Register a gauge field.  dims = (Lx, Ly, Lz, Lt), each even and >= 2.
+ * links: complex128 [V][4][3][3] (layout above), on the host
+ * (links_on_device = 0; copied, the caller keeps ownership) or on the
+ * device (1; read once, the caller keeps ownership).  The library folds the
+ * staggered phases, the 1/2 and the t-boundary sign into its own copy,
+ * builds the daggered backward links (the paper's `ud`) stored at the site
+ * that uses them, reorders everything into a checkerboard
+ * structure-of-arrays layout, and keeps FP64, FP32 and FP16 copies plus the
+ * iup/idn neighbour tables resident in the arena.
+ * Errors: EINVAL (bad dims), ENOMEM, ENONFINITE (NaN/Inf in the links).
+ * Synchronous.
+ */
+int stag_set_gauge(stag_ctx *ctx, const int32_t dims[4], const double *links,
+                   int32_t links_on_device, int32_t t_antiperiodic,
+                   int32_t *gauge_id);
+
+/* Release a gauge field.  EBUSY while serving requests on it are pending. */
+int stag_free_gauge(stag_ctx *ctx, int32_t gauge_id);
+
+/* Lattice extents of a registered field. */
+int stag_gauge_dims(stag_ctx *ctx, int32_t gauge_id, int32_t dims[4]);
+
+/* ---- layout conversion ----------------------------------------------- */
+
+/* lex: device complex128 [V][3] -> eo: device complex128 [2][3][Vh]. */
+int stag_pack_fermion(stag_ctx *ctx, const int32_t dims[4], const double *lex,
+                      double *eo, void *stream);
+/* eo: device complex128 [2][3][Vh] -> lex: device complex128 [V][3]. */
+int stag_unpack_fermion(stag_ctx *ctx, const int32_t dims[4], const double *eo,
+                        double *lex, void *stream);
+
+/* ---- the matrix-vector routine (Sec. 3) ------------------------------- */
+
+/*
+ * out(x) = (accumulate ? out(x) : 0) + (D in)(x) for the output sites x of
+ * parity out_parity whose checkerboard index lies in [offset, offset+count)
+ * (count = -1: to the end of the parity).  This is the paper's
+ * matrix-vector(offset, local_length, v, w) restricted to one parity.
+ * out_parity = STAG_ALL applies D to every site (offset must be 0, count -1).
+ * in, out: device full-lattice fields in the even-odd layout (only the
+ * other parity of `in` is read); they must not overlap.  Sites outside the
+ * range are untouched.  FP64.  Asynchronous on `stream`.
+ * Errors: ENOENT, EINVAL (parity, range, NULL).
+ */
+int stag_dslash(stag_ctx *ctx, int32_t gauge_id, int32_t out_parity,
+                int64_t offset, int64_t count, const double *in, double *out,
+                int32_t accumulate, void *stream);
+
+/* ---- the conjugate-gradient solve (Sec. 4) --------------------------- */
+
+/*
+ * Solve (m^2 - D^2) x = b on the parity systems selected by params->parity,
+ * from x = 0 (Sec. 4).  b, x: device full-lattice fields in the even-odd
+ * layout; only the selected parities are read / written.  y (nullable): if
+ * given, y = D x on the opposite parity of every solved system (the paper's
+ * "solution on the second half lattice").  Every iteration runs on the GPU
+ * with the scalars and the stopping test kept in device memory; the host
+ * only polls a status word every few iterations.  The result is accepted
+ * when the FP64 true residual on the GPU satisfies ||b - A x|| <= tol ||b||
+ * for each parity system.  Blocks until done; info (nullable) receives the
+ * outcome.  Returns STAG_OK or the solve's error (ENOCONV: x holds the last
+ * iterate).  Errors: ENOENT, EINVAL (m <= 0, tol <= 0, bad parity or
+ * precision), ENOMEM, ENOCONV, EBREAKDOWN, ENONFINITE.
+ */
+int stag_cg_solve(stag_ctx *ctx, int32_t gauge_id, const stag_cg_params *params,
+                  const double *b, double *x, double *y, void *stream,
+                  stag_cg_info *info);
+
+/*
+ * Solve nrhs systems that share one gauge field in one batched solve: every
+ * CG iteration reads the links once for all right-hand sides.  params[i]
+ * may differ in mass, tol, maxiter and parity; precision must be the same for
+ * all.  b[i], x[i]: device full-lattice fields (even-odd layout).  The tile
+ * of right-hand sides processed per link read and the kernel shapes are
+ * chosen by the library's autotuner.  Each system's iteration sequence
+ * (and therefore its result) does not depend on which other systems share the
+ * batch.  infos[i] receives each outcome.  Blocks until all are done.
+ * Returns STAG_OK if every system converged, else the first error.
+ */
+int stag_cg_solve_batch(stag_ctx *ctx, int32_t gauge_id, int32_t nrhs,
+                        const stag_cg_params *params, const double *const *b,
+                        double *const *x, void *stream, stag_cg_info *infos);
+
+/* ---- serving: continuous batching ------------------------------------ */
+
+/*
+ * Queue a solve.  b_dev / x_dev are device full-lattice fields (even-odd
+ * layout) borrowed until stag_poll / stag_wait report completion.  A
+ * scheduler thread admits queued requests into batch slots of their gauge
+ * field while memory (the arena) and slots allow, runs the batch in epochs
+ * of CG iterations on the field's own stream, and between epochs retires
+ * converged requests and admits new ones, so requests arriving while others
+ * run join the running batch.  Different gauge fields run on different
+ * streams and overlap.  *ticket receives the request's handle.
+ * Errors: ENOENT, EINVAL, EAGAIN (queue full).
+ */
+int stag_submit(stag_ctx *ctx, int32_t gauge_id, const stag_cg_params *params,
+                const double *b_dev, double *x_dev, uint64_t *ticket);
+
+/* STAG_PENDING while the request is queued or running; otherwise its final
+ * status, with info filled (seconds = submit -> completion).  A completed
+ * ticket may be polled repeatedly until stag_release_ticket. ENOENT: unknown. */
+int stag_poll(stag_ctx *ctx, uint64_t ticket, stag_cg_info *info);
+
+/* Block until the request completes; returns its final status. */
+int stag_wait(stag_ctx *ctx, uint64_t ticket, stag_cg_info *info);
+
+/* Forget a completed ticket.  EBUSY if it is still pending. */
+int stag_release_ticket(stag_ctx *ctx, uint64_t ticket);
+
+/* Serving limits: slots per gauge field (1..64) and queue capacity.  Call
+ * before the first stag_submit; EBUSY afterwards. */
+int stag_serve_config(stag_ctx *ctx, int32_t slots_per_field, int32_t epoch_iters,
+                      int32_t queue_capacity);
+
+/* ---- tuning and introspection ---------------------------------------- */
+
+/*
+ * Describe the kernel configuration the autotuner chose for the D_slash of a
+ * gauge field at a precision (0 FP64, 1 FP32, 2 FP16) and right-hand-side
+ * count: lanes per site, threads per block, right-hand sides per link read,
+ * and whether the neighbour tables are read (1) or neighbours are computed
+ * from coordinates (0).  Runs the tuner if that case has not been tuned yet.
+ */
+int stag_tune_info(stag_ctx *ctx, int32_t gauge_id, int32_t precision,
+                   int32_t nrhs, int32_t *lanes_per_site, int32_t *block,
+                   int32_t *rhs_tile, int32_t *use_tables);
+
+/* Library version string. */
+const char *stag_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STAGCG_H */

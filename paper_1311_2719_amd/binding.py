@@ -1,0 +1,344 @@
+"""ctypes binding of libstagcg (C ABI in include/stagcg.h).
+
+Argument marshalling only: every step of D_slash and of the CG solves runs
+in the library's HIP kernels.  PyTorch supplies the device memory (one arena
+tensor per context, plus the caller's field tensors) and the HIP stream.
+
+Fermion fields on the device are torch.complex128 tensors in the library's
+even-odd layout, shape (2, 3, V/2): [parity][colour][checkerboard site].
+`Context.pack` / `Context.unpack` convert from / to the lexicographic
+(V, 3) layout that the oracle and the input generators use.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstagcg.so")
+
+OK, PENDING = 0, 1
+ERRORS = {
+    -1: "EINVAL", -2: "ENOMEM", -3: "ENOENT", -4: "EBUSY", -5: "EAGAIN",
+    -6: "ENOCONV", -7: "EBREAKDOWN", -8: "ENONFINITE", -9: "EHIP", -10: "ECANCELED",
+}
+EINVAL, ENOMEM, ENOENT, EBUSY, EAGAIN, ENOCONV, EBREAKDOWN, ENONFINITE, EHIP, ECANCELED = range(-1, -11, -1)
+EVEN, ODD, ALL = 0, 1, 2
+FP64, FP32_RU, FP16_RU = 0, 1, 2
+
+_lock = threading.Lock()
+_lib = None
+
+
+class StagError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "ERR"), code, msg))
+        self.code = code
+
+
+class CGParams(ctypes.Structure):
+    _fields_ = [
+        ("mass", ctypes.c_double),
+        ("tol", ctypes.c_double),
+        ("maxiter", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("parity", ctypes.c_int32),
+        ("max_restarts", ctypes.c_int32),
+        ("delta", ctypes.c_double),
+    ]
+
+
+class CGInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("iters", ctypes.c_int32),
+        ("reliable_updates", ctypes.c_int32),
+        ("restarts", ctypes.c_int32),
+        ("true_rel_resid", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+        ("queue_seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def load():
+    """Open libstagcg.so; raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                "libstagcg.so is not built (%s); run `python -m paper_1311_2719_amd.build`" % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, SZ, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_uint64
+        sig = {
+            "stag_create": ([ctypes.c_int, P, SZ, P, ctypes.POINTER(P)], ctypes.c_int),
+            "stag_destroy": ([P], ctypes.c_int),
+            "stag_last_error": ([], ctypes.c_char_p),
+            "stag_arena_usage": ([P, ctypes.POINTER(SZ), ctypes.POINTER(SZ)], ctypes.c_int),
+            "stag_set_gauge": ([P, P, P, I32, I32, ctypes.POINTER(I32)], ctypes.c_int),
+            "stag_free_gauge": ([P, I32], ctypes.c_int),
+            "stag_gauge_dims": ([P, I32, P], ctypes.c_int),
+            "stag_pack_fermion": ([P, P, P, P, P], ctypes.c_int),
+            "stag_unpack_fermion": ([P, P, P, P, P], ctypes.c_int),
+            "stag_dslash": ([P, I32, I32, I64, I64, P, P, I32, P], ctypes.c_int),
+            "stag_cg_solve": ([P, I32, ctypes.POINTER(CGParams), P, P, P, P, ctypes.POINTER(CGInfo)], ctypes.c_int),
+            "stag_cg_solve_batch": ([P, I32, I32, ctypes.POINTER(CGParams), P, P, P, ctypes.POINTER(CGInfo)],
+                                    ctypes.c_int),
+            "stag_submit": ([P, I32, ctypes.POINTER(CGParams), P, P, ctypes.POINTER(U64)], ctypes.c_int),
+            "stag_poll": ([P, U64, ctypes.POINTER(CGInfo)], ctypes.c_int),
+            "stag_wait": ([P, U64, ctypes.POINTER(CGInfo)], ctypes.c_int),
+            "stag_release_ticket": ([P, U64], ctypes.c_int),
+            "stag_serve_config": ([P, I32, I32, I32], ctypes.c_int),
+            "stag_tune_info": ([P, I32, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32),
+                                ctypes.POINTER(I32)], ctypes.c_int),
+            "stag_version": ([], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+        return lib
+
+
+def exported_symbols():
+    """Names of the C ABI entry points the binding expects."""
+    return [
+        "stag_create", "stag_destroy", "stag_last_error", "stag_arena_usage", "stag_set_gauge",
+        "stag_free_gauge", "stag_gauge_dims", "stag_pack_fermion", "stag_unpack_fermion", "stag_dslash",
+        "stag_cg_solve", "stag_cg_solve_batch", "stag_submit", "stag_poll", "stag_wait",
+        "stag_release_ticket", "stag_serve_config", "stag_tune_info", "stag_version",
+    ]
+
+
+def _check(rc: int, what: str) -> int:
+    if rc < 0:
+        msg = load().stag_last_error()
+        raise StagError(rc, "%s: %s" % (what, msg.decode() if msg else ""))
+    return rc
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def params(mass, tol=1e-10, maxiter=20000, precision=FP64, parity=ALL, max_restarts=10, delta=0.1) -> CGParams:
+    return CGParams(float(mass), float(tol), int(maxiter), int(precision), int(parity), int(max_restarts),
+                    float(delta))
+
+
+@dataclass
+class Field:
+    gauge_id: int
+    dims: tuple
+
+    @property
+    def volume(self):
+        return int(np.prod(self.dims))
+
+
+class Context:
+    """A library context on one GPU.  `arena_bytes` of device memory are
+    allocated once with torch and handed to the library, which sub-allocates
+    every gauge field and workspace from it."""
+
+    def __init__(self, device: int = 0, arena_bytes: int = 4 << 30, stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the stagcg library runs on the GPU only")
+        self.lib = load()
+        self.device = int(device)
+        self.torch_device = torch.device("cuda", self.device)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.torch_device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.torch_device)
+        h = ctypes.c_void_p()
+        _check(self.lib.stag_create(self.device, self.arena.data_ptr(), int(arena_bytes),
+                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "stag_create")
+        self.h = h
+        self.fields = {}
+
+    # -- lifetime ------------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            _check(self.lib.stag_destroy(self.h), "stag_destroy")
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def arena_usage(self):
+        used, total = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(self.lib.stag_arena_usage(self.h, ctypes.byref(used), ctypes.byref(total)), "stag_arena_usage")
+        return used.value, total.value
+
+    # -- gauge fields --------------------------------------------------------
+    def set_gauge(self, dims, links, antiperiodic_t=True) -> Field:
+        """links: complex128 [V,4,3,3], numpy (host) or a torch CUDA tensor."""
+        torch = _torch()
+        d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32))
+        gid = ctypes.c_int32()
+        if isinstance(links, torch.Tensor):
+            if links.dtype != torch.complex128 or not links.is_contiguous():
+                raise ValueError("links must be contiguous complex128")
+            ptr, on_dev = links.data_ptr(), int(links.is_cuda)
+            keep = links
+        else:
+            keep = np.ascontiguousarray(links, dtype=np.complex128)
+            ptr, on_dev = keep.ctypes.data, 0
+        V = int(np.prod(d))
+        if keep.shape != (V, 4, 3, 3):
+            raise ValueError("links must have shape (V,4,3,3)")
+        _check(self.lib.stag_set_gauge(self.h, d.ctypes.data, ctypes.c_void_p(ptr), on_dev,
+                                       int(bool(antiperiodic_t)), ctypes.byref(gid)), "stag_set_gauge")
+        f = Field(gid.value, tuple(int(v) for v in d))
+        self.fields[gid.value] = f
+        return f
+
+    def free_gauge(self, field: Field):
+        _check(self.lib.stag_free_gauge(self.h, field.gauge_id), "stag_free_gauge")
+        self.fields.pop(field.gauge_id, None)
+
+    # -- fields ----------------------------------------------------------------
+    def new_fermion(self, field: Field):
+        torch = _torch()
+        return torch.zeros((2, 3, field.volume // 2), dtype=torch.complex128, device=self.torch_device)
+
+    def pack(self, field: Field, lex):
+        """(V,3) complex128 (numpy or torch) -> device even-odd tensor (2,3,V/2)."""
+        torch = _torch()
+        if not isinstance(lex, torch.Tensor):
+            lex = torch.from_numpy(np.ascontiguousarray(lex, dtype=np.complex128))
+        lex = lex.to(self.torch_device).contiguous()
+        if lex.shape != (field.volume, 3) or lex.dtype != torch.complex128:
+            raise ValueError("expected complex128 (V,3)")
+        eo = self.new_fermion(field)
+        d = np.asarray(field.dims, dtype=np.int32)
+        _check(self.lib.stag_pack_fermion(self.h, d.ctypes.data, ctypes.c_void_p(lex.data_ptr()),
+                                          ctypes.c_void_p(eo.data_ptr()), None), "stag_pack_fermion")
+        return eo
+
+    def unpack(self, field: Field, eo):
+        """device even-odd (2,3,V/2) -> device lexicographic (V,3)."""
+        torch = _torch()
+        self._check_eo(field, eo)
+        lex = torch.empty((field.volume, 3), dtype=torch.complex128, device=self.torch_device)
+        d = np.asarray(field.dims, dtype=np.int32)
+        _check(self.lib.stag_unpack_fermion(self.h, d.ctypes.data, ctypes.c_void_p(eo.data_ptr()),
+                                            ctypes.c_void_p(lex.data_ptr()), None), "stag_unpack_fermion")
+        return lex
+
+    def _check_eo(self, field, t):
+        torch = _torch()
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()
+                and tuple(t.shape) == (2, 3, field.volume // 2)):
+            raise ValueError("expected a contiguous complex128 CUDA tensor of shape (2,3,V/2)")
+
+    # -- operator and solves ------------------------------------------------------
+    def dslash(self, field: Field, inp, out, out_parity=ALL, offset=0, count=-1, accumulate=False, stream=None):
+        self._check_eo(field, inp)
+        self._check_eo(field, out)
+        s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+        _check(self.lib.stag_dslash(self.h, field.gauge_id, int(out_parity), int(offset), int(count),
+                                    ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                    int(bool(accumulate)), s), "stag_dslash")
+        return out
+
+    def cg_solve(self, field: Field, b, x, y=None, check=True, **kw):
+        p = params(**kw)
+        self._check_eo(field, b)
+        self._check_eo(field, x)
+        if y is not None:
+            self._check_eo(field, y)
+        info = CGInfo()
+        rc = self.lib.stag_cg_solve(self.h, field.gauge_id, ctypes.byref(p), ctypes.c_void_p(b.data_ptr()),
+                                    ctypes.c_void_p(x.data_ptr()),
+                                    ctypes.c_void_p(y.data_ptr()) if y is not None else None, None,
+                                    ctypes.byref(info))
+        if check:
+            _check(rc, "stag_cg_solve")
+        d = info.as_dict()
+        d["rc"] = rc
+        return d
+
+    def cg_solve_batch(self, field: Field, bs, xs, plist, check=True):
+        n = len(bs)
+        if not (len(xs) == n == len(plist)):
+            raise ValueError("bs, xs and params must have the same length")
+        for t in list(bs) + list(xs):
+            self._check_eo(field, t)
+        P = (CGParams * n)(*plist)
+        B = (ctypes.c_void_p * n)(*[t.data_ptr() for t in bs])
+        X = (ctypes.c_void_p * n)(*[t.data_ptr() for t in xs])
+        infos = (CGInfo * n)()
+        rc = self.lib.stag_cg_solve_batch(self.h, field.gauge_id, n, P, ctypes.cast(B, ctypes.c_void_p),
+                                          ctypes.cast(X, ctypes.c_void_p), None, infos)
+        if check:
+            _check(rc, "stag_cg_solve_batch")
+        out = [i.as_dict() for i in infos]
+        for d in out:
+            d["rc"] = rc
+        return out
+
+    # -- serving ---------------------------------------------------------------
+    def serve_config(self, slots_per_field=16, epoch_iters=16, queue_capacity=4096):
+        _check(self.lib.stag_serve_config(self.h, int(slots_per_field), int(epoch_iters), int(queue_capacity)),
+               "stag_serve_config")
+
+    def submit(self, field: Field, b, x, **kw) -> int:
+        p = params(**kw)
+        self._check_eo(field, b)
+        self._check_eo(field, x)
+        t = ctypes.c_uint64()
+        _check(self.lib.stag_submit(self.h, field.gauge_id, ctypes.byref(p), ctypes.c_void_p(b.data_ptr()),
+                                    ctypes.c_void_p(x.data_ptr()), ctypes.byref(t)), "stag_submit")
+        return t.value
+
+    def poll(self, ticket: int):
+        info = CGInfo()
+        rc = self.lib.stag_poll(self.h, ctypes.c_uint64(ticket), ctypes.byref(info))
+        if rc == PENDING:
+            return None
+        d = info.as_dict()
+        d["rc"] = rc
+        return d
+
+    def wait(self, ticket: int):
+        info = CGInfo()
+        rc = self.lib.stag_wait(self.h, ctypes.c_uint64(ticket), ctypes.byref(info))
+        d = info.as_dict()
+        d["rc"] = rc
+        return d
+
+    def release(self, ticket: int):
+        _check(self.lib.stag_release_ticket(self.h, ctypes.c_uint64(ticket)), "stag_release_ticket")
+
+    def tune_info(self, field: Field, precision=FP64, nrhs=1):
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(self.lib.stag_tune_info(self.h, field.gauge_id, int(precision), int(nrhs),
+                                       *[ctypes.byref(t) for t in v]), "stag_tune_info")
+        return {"lanes_per_site": v[0].value, "block": v[1].value, "rhs_tile": v[2].value,
+                "use_tables": v[3].value}
+
+
+def version() -> str:
+    return load().stag_version().decode()

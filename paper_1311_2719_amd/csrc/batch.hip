@@ -1,0 +1,361 @@
+// Batch workspace and the per-iteration launch sequence; the blocking
+// (batched) CG solve built on it.
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+
+#include "batch.hpp"
+
+namespace stag {
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static int blocks_for(int Vh, int lps, int block) { return (int)(((int64_t)Vh * lps + block - 1) / block); }
+
+Batch::Batch(Ctx *ctx, std::shared_ptr<GaugeField> f, int prec, int slots, hipStream_t s)
+    : ctx_(ctx), f_(std::move(f)), prec_(prec), S_(slots), s_(s)
+{
+}
+
+Batch::~Batch()
+{
+    if (snap_ev_)
+        (void)hipEventDestroy(snap_ev_);
+    if (stage_ev_)
+        (void)hipEventDestroy(stage_ev_);
+    if (stage_)
+        (void)hipHostFree(stage_);
+    if (mem_)
+        ctx_->arena.release(mem_);
+}
+
+size_t Batch::workspace_bytes(const Geom &g, int prec, int slots, int pstride)
+{
+    const size_t nsys = 2 * (size_t)slots, Vh = g.Vh;
+    size_t b = 0;
+    b += align256(nsys * Vh * spinor_bytes_of(prec)) * 2;       // p, ap
+    b += align256(nsys * 3 * Vh * (prec == 0 ? 16 : 8));         // r
+    b += prec == 0 ? 0 : align256(nsys * 3 * Vh * 8);            // x_lo
+    b += align256(nsys * 3 * Vh * 16);                           // tmp
+    b += align256(nsys * sizeof(void *)) * 2;                    // pointer tables
+    b += align256(nsys * sizeof(SysState));
+    b += align256(nsys * (size_t)pstride * 2 * sizeof(double));  // partials
+    b += align256(nsys * sizeof(unsigned));
+    return b;
+}
+
+int Batch::create()
+{
+    const Geom &g = f_->g;
+    cfg_ = tune_config(ctx_, f_.get(), prec_, S_, s_);
+    cfg64_ = tune_config(ctx_, f_.get(), 0, 1, s_);
+    if (S_ % cfg_.rtile != 0)
+        cfg_.rtile = 1;
+    pstride_ = std::max(std::max(blocks_for(g.Vh, cfg_.lps, cfg_.block), blocks_for(g.Vh, cfg64_.lps, cfg64_.block)),
+                        blocks_for(g.Vh, 1, 256));
+    bytes_ = workspace_bytes(g, prec_, S_, pstride_);
+    mem_ = ctx_->arena.alloc(bytes_);
+    if (!mem_)
+        return set_error(STAG_ENOMEM, "arena exhausted: CG workspace needs %zu bytes (largest free block %zu)", bytes_,
+                         ctx_->arena.largest_free());
+    const size_t nsys = 2 * (size_t)S_, Vh = g.Vh;
+    char *c = (char *)mem_;
+    auto take = [&](size_t n) {
+        char *r = c;
+        c += align256(n);
+        return (void *)r;
+    };
+    p_ = take(nsys * Vh * spinor_bytes_of(prec_));
+    ap_ = take(nsys * Vh * spinor_bytes_of(prec_));
+    r_ = take(nsys * 3 * Vh * (prec_ == 0 ? 16 : 8));
+    xlo_ = prec_ == 0 ? nullptr : (flt2 *)take(nsys * 3 * Vh * 8);
+    tmp_ = (dbl2 *)take(nsys * 3 * Vh * 16);
+    xhi_d_ = (dbl2 **)take(nsys * sizeof(void *));
+    b_d_ = (const dbl2 **)take(nsys * sizeof(void *));
+    st_d_ = (SysState *)take(nsys * sizeof(SysState));
+    partials_ = (double *)take(nsys * (size_t)pstride_ * 2 * sizeof(double));
+    counters_ = (unsigned *)take(nsys * sizeof(unsigned));
+
+    const size_t host_bytes = 2 * nsys * sizeof(SysState) + 2 * nsys * sizeof(void *);
+    STAG_HIP_CHECK(hipHostMalloc((void **)&stage_, host_bytes, hipHostMallocDefault));
+    snap_ = stage_ + nsys;
+    xhi_h_ = (dbl2 **)(snap_ + nsys);
+    b_h_ = (const dbl2 **)(xhi_h_ + nsys);
+    memset(stage_, 0, host_bytes);
+    STAG_HIP_CHECK(hipEventCreateWithFlags(&snap_ev_, hipEventDisableTiming));
+    STAG_HIP_CHECK(hipEventCreateWithFlags(&stage_ev_, hipEventDisableTiming));
+    // every system starts idle; counters start at zero
+    STAG_HIP_CHECK(hipMemcpyAsync(st_d_, stage_, nsys * sizeof(SysState), hipMemcpyHostToDevice, s_));
+    STAG_HIP_CHECK(hipMemsetAsync(counters_, 0, nsys * sizeof(unsigned), s_));
+    STAG_HIP_CHECK(hipMemcpyAsync(xhi_d_, xhi_h_, nsys * sizeof(void *), hipMemcpyHostToDevice, s_));
+    STAG_HIP_CHECK(hipMemcpyAsync(b_d_, b_h_, nsys * sizeof(void *), hipMemcpyHostToDevice, s_));
+    STAG_HIP_CHECK(hipEventRecord(stage_ev_, s_));
+    stage_busy_ = true;
+    return STAG_OK;
+}
+
+void Batch::stage_system(int j, const stag_cg_params &p, const double *b_half, double *x_half)
+{
+    if (stage_busy_) {
+        (void)hipEventSynchronize(stage_ev_);
+        stage_busy_ = false;
+    }
+    SysState &st = stage_[j];
+    memset(&st, 0, sizeof(st));
+    if (!b_half || !x_half) {
+        st.phase = PH_IDLE;
+        xhi_h_[j] = nullptr;
+        b_h_[j] = nullptr;
+        return;
+    }
+    st.phase = PH_INIT;
+    st.mass2 = p.mass * p.mass;
+    st.tol2 = p.tol * p.tol;
+    st.maxiter = p.maxiter;
+    st.max_restarts = p.max_restarts;
+    st.mixed = prec_ != STAG_FP64;
+    const double delta = p.delta > 0 ? p.delta : 0.1;
+    st.delta2 = st.mixed ? delta * delta : 0.0;
+    xhi_h_[j] = (dbl2 *)x_half;
+    b_h_[j] = (const dbl2 *)b_half;
+}
+
+int Batch::upload_and_init(const std::vector<int> &systems)
+{
+    for (int j : systems) {
+        STAG_HIP_CHECK(hipMemcpyAsync(st_d_ + j, stage_ + j, sizeof(SysState), hipMemcpyHostToDevice, s_));
+        STAG_HIP_CHECK(hipMemcpyAsync(xhi_d_ + j, xhi_h_ + j, sizeof(void *), hipMemcpyHostToDevice, s_));
+        STAG_HIP_CHECK(hipMemcpyAsync(b_d_ + j, b_h_ + j, sizeof(void *), hipMemcpyHostToDevice, s_));
+    }
+    STAG_HIP_CHECK(hipEventRecord(stage_ev_, s_));
+    stage_busy_ = true;
+    const CgArgs a = args();
+    const CgLaunchTable &t = cg_table(prec_);
+    dim3 grid((unsigned)blocks_for(f_->g.Vh, 1, 256), (unsigned)nsys());
+    hipError_t e = t.init(grid, dim3(256), s_, a);
+    if (e != hipSuccess)
+        return set_error(STAG_EHIP, "init launch failed: %s", hipGetErrorString(e));
+    return STAG_OK;
+}
+
+CgArgs Batch::args() const
+{
+    CgArgs a;
+    memset(&a, 0, sizeof(a));
+    a.g = f_->g;
+    for (int par = 0; par < 2; ++par) {
+        a.links[par] = f_->links_for(prec_, par);
+        a.links64[par] = (const dbl2 *)f_->links_for(0, par);
+        a.nbr[par] = cfg_.tables ? f_->nbr_for(par) : nullptr;
+    }
+    a.p = p_;
+    a.ap = ap_;
+    a.r = r_;
+    a.xlo = xlo_;
+    a.tmp = tmp_;
+    a.xhi = xhi_d_;
+    a.b = b_d_;
+    a.st = st_d_;
+    a.partials = partials_;
+    a.counters = counters_;
+    a.S = S_;
+    a.pstride = pstride_;
+    a.remap = cfg_.remap;
+    return a;
+}
+
+int Batch::launch_iter(bool with_ru)
+{
+    const Geom &g = f_->g;
+    const CgLaunchTable &t = cg_table(prec_);
+    CgArgs a = args();
+    const int R = cfg_.rtile;
+    dim3 grid_h((unsigned)blocks_for(g.Vh, cfg_.lps, cfg_.block), (unsigned)(nsys() / R));
+    dim3 blk(cfg_.block);
+    hipError_t e = t.ap(cfg_.lps, R, grid_h, blk, s_, a);
+    if (e == hipSuccess)
+        e = t.update(cfg_.lps, R, grid_h, blk, s_, a);
+    if (e == hipSuccess && with_ru) {
+        CgArgs a64 = a;
+        a64.nbr[0] = cfg64_.tables ? f_->nbr_for(0) : nullptr;
+        a64.nbr[1] = cfg64_.tables ? f_->nbr_for(1) : nullptr;
+        a64.remap = cfg64_.remap;
+        dim3 grid64((unsigned)blocks_for(g.Vh, cfg64_.lps, cfg64_.block), (unsigned)nsys());
+        e = launch_ru_dx(cfg64_.lps, prec_ != 0, grid64, dim3(cfg64_.block), s_, a64);
+        if (e == hipSuccess)
+            e = t.ru_residual(cfg64_.lps, grid64, dim3(cfg64_.block), s_, a64);
+    }
+    if (e == hipSuccess) {
+        dim3 grid_v((unsigned)blocks_for(g.Vh, 1, 256), (unsigned)nsys());
+        e = t.direction(grid_v, dim3(256), s_, a);
+    }
+    if (e != hipSuccess)
+        return set_error(STAG_EHIP, "CG kernel launch failed: %s", hipGetErrorString(e));
+    return STAG_OK;
+}
+
+int Batch::enqueue_epoch(int iters, bool ru_every_iter)
+{
+    for (int k = 0; k < iters; ++k) {
+        int rc = launch_iter(ru_every_iter || k == iters - 1);
+        if (rc != STAG_OK)
+            return rc;
+    }
+    return STAG_OK;
+}
+
+int Batch::enqueue_snapshot()
+{
+    STAG_HIP_CHECK(hipMemcpyAsync(snap_, st_d_, nsys() * sizeof(SysState), hipMemcpyDeviceToHost, s_));
+    STAG_HIP_CHECK(hipEventRecord(snap_ev_, s_));
+    return STAG_OK;
+}
+
+int Batch::wait_snapshot()
+{
+    STAG_HIP_CHECK(hipEventSynchronize(snap_ev_));
+    return STAG_OK;
+}
+
+bool Batch::snapshot_ready() { return hipEventQuery(snap_ev_) == hipSuccess; }
+
+// ---- the blocking solve ------------------------------------------------------------
+
+static int validate_params(const stag_cg_params &p, int prec0)
+{
+    if (!(p.mass > 0) || !std::isfinite(p.mass))
+        return set_error(STAG_EINVAL, "mass must be > 0 (got %g)", p.mass);
+    if (!(p.tol > 0) || !std::isfinite(p.tol))
+        return set_error(STAG_EINVAL, "tol must be > 0 (got %g)", p.tol);
+    if (p.maxiter < 0)
+        return set_error(STAG_EINVAL, "maxiter must be >= 0");
+    if (p.max_restarts < 0)
+        return set_error(STAG_EINVAL, "max_restarts must be >= 0");
+    if (p.parity < STAG_EVEN || p.parity > STAG_ALL)
+        return set_error(STAG_EINVAL, "parity must be STAG_EVEN, STAG_ODD or STAG_ALL");
+    if (p.precision < STAG_FP64 || p.precision > STAG_FP16_RU)
+        return set_error(STAG_EINVAL, "unknown precision %d", p.precision);
+    if (p.precision != prec0)
+        return set_error(STAG_EINVAL, "all systems of a batch must use the same precision");
+    return STAG_OK;
+}
+
+int validate_cg_params(const stag_cg_params &p) { return validate_params(p, p.precision); }
+
+static int worse(int a, int b)
+{
+    if (a == STAG_OK)
+        return b;
+    return a;
+}
+
+void fill_info(const Batch &B, int slot, stag_cg_info *info)
+{
+    const int S = B.slots();
+    int status = STAG_OK, iters = 0, nru = 0, rst = 0;
+    double trr = 0, bb = 0;
+    bool any = false;
+    for (int par = 0; par < 2; ++par) {
+        const SysState &st = B.state(par * S + slot);
+        if (st.phase == PH_IDLE)
+            continue;
+        any = true;
+        status = worse(status, st.phase == PH_DONE ? st.status : STAG_ENOCONV);
+        iters = std::max(iters, st.iters);
+        nru += st.n_ru;
+        rst = std::max(rst, st.restarts);
+        trr += st.true_rr;
+        bb += st.bb;
+    }
+    info->status = any ? status : STAG_OK;
+    info->iters = iters;
+    info->reliable_updates = nru;
+    info->restarts = rst;
+    info->true_rel_resid = bb > 0 ? std::sqrt(trr / bb) : std::sqrt(trr);
+}
+
+int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs, const stag_cg_params *params,
+                   const double *const *b, double *const *x, double *const *y, hipStream_t s, stag_cg_info *infos)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const int prec = params[0].precision;
+    for (int i = 0; i < nrhs; ++i) {
+        int rc = validate_params(params[i], prec);
+        if (rc != STAG_OK)
+            return rc;
+        if (!b[i] || !x[i])
+            return set_error(STAG_EINVAL, "b and x must be device pointers");
+    }
+    Batch B(ctx, f, prec, nrhs, s);
+    int rc = B.create();
+    if (rc != STAG_OK)
+        return rc;
+    const size_t half = (size_t)3 * f->g.Vh * 2;  // doubles per parity half
+    std::vector<int> systems;
+    int max_iter = 0;
+    for (int i = 0; i < nrhs; ++i) {
+        max_iter = std::max(max_iter, params[i].maxiter);
+        for (int par = 0; par < 2; ++par) {
+            const int j = par * nrhs + i;
+            const bool on = params[i].parity == STAG_ALL || params[i].parity == par;
+            B.stage_system(j, params[i], on ? b[i] + par * half : nullptr, on ? x[i] + par * half : nullptr);
+            systems.push_back(j);
+        }
+    }
+    if ((rc = B.upload_and_init(systems)) != STAG_OK)
+        return rc;
+    const bool mixed = prec != STAG_FP64;
+    int E = 16;
+    if (const char *e = getenv("STAG_EPOCH"))
+        E = std::max(1, atoi(e));
+    // pipelined: epoch n+1 is queued before the state after epoch n is read
+    if ((rc = B.enqueue_epoch(E, mixed)) != STAG_OK || (rc = B.enqueue_snapshot()) != STAG_OK)
+        return rc;
+    const int64_t limit = (int64_t)(max_iter + 1) * (int64_t)(2 + params[0].max_restarts) / E + 64;
+    bool done = false;
+    for (int64_t ep = 0; ep < limit && !done; ++ep) {
+        if ((rc = B.enqueue_epoch(E, mixed)) != STAG_OK)
+            return rc;
+        if ((rc = B.wait_snapshot()) != STAG_OK)
+            return rc;
+        done = true;
+        for (int j = 0; j < B.nsys(); ++j) {
+            const int ph = B.state(j).phase;
+            if (ph == PH_RUN || ph == PH_INIT)
+                done = false;
+        }
+        if (!done && (rc = B.enqueue_snapshot()) != STAG_OK)
+            return rc;
+    }
+    if ((rc = B.enqueue_snapshot()) != STAG_OK || (rc = B.wait_snapshot()) != STAG_OK)
+        return rc;
+    // y = D x on the opposite parity of every solved system (Sec. 4, second half)
+    int first_err = STAG_OK;
+    for (int i = 0; i < nrhs; ++i) {
+        if (y && y[i]) {
+            const int par = params[i].parity;
+            const int out_par = par == STAG_ALL ? STAG_ALL : 1 - par;
+            if ((rc = dslash_f64(ctx, f.get(), out_par, 0, f->g.Vh, x[i], y[i], 0, s)) != STAG_OK)
+                return rc;
+        }
+    }
+    STAG_HIP_CHECK(hipStreamSynchronize(s));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int i = 0; i < nrhs; ++i) {
+        stag_cg_info inf;
+        memset(&inf, 0, sizeof(inf));
+        fill_info(B, i, &inf);
+        inf.seconds = secs;
+        if (!done && inf.status == STAG_OK)
+            inf.status = STAG_ENOCONV;
+        if (infos)
+            infos[i] = inf;
+        first_err = worse(first_err, inf.status);
+    }
+    if (first_err != STAG_OK)
+        return set_error(first_err, "CG did not converge (status %d)", first_err);
+    return STAG_OK;
+}
+
+}  // namespace stag

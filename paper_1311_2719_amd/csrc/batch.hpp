@@ -1,0 +1,75 @@
+// A batch of CG systems that share one gauge field: workspace, state and the
+// launch sequence of one CG iteration.  Used by stag_cg_solve (one right-hand
+// side, two parity systems), stag_cg_solve_batch and the serving scheduler.
+#pragma once
+
+#include "cg_launch.hpp"
+#include "runtime.hpp"
+
+namespace stag {
+
+class Batch {
+public:
+    Batch(Ctx *ctx, std::shared_ptr<GaugeField> f, int prec, int slots, hipStream_t s);
+    ~Batch();
+    Batch(const Batch &) = delete;
+    Batch &operator=(const Batch &) = delete;
+
+    // Allocate workspace from the arena and pinned host mirrors.  ENOMEM if
+    // the arena cannot hold it.
+    int create();
+    static size_t workspace_bytes(const Geom &g, int prec, int slots, int pstride);
+
+    int slots() const { return S_; }
+    int nsys() const { return 2 * S_; }
+    int prec() const { return prec_; }
+    const KernelCfg &cfg() const { return cfg_; }
+    hipStream_t stream() const { return s_; }
+    GaugeField *field() const { return f_.get(); }
+
+    // Stage system j (= parity * slots + slot) for initialisation with source
+    // b and solution x (parity halves, device), or mark it idle (b == x == null).
+    void stage_system(int j, const stag_cg_params &p, const double *b_half, double *x_half);
+    // Copy staged systems [j0, j0 + n) to the device and run the init kernel.
+    int upload_and_init(const std::vector<int> &systems);
+    // Enqueue `iters` CG iterations; residual recomputation after every
+    // iteration when ru_every_iter, else only after the last one.
+    int enqueue_epoch(int iters, bool ru_every_iter);
+    // Enqueue a copy of the device state into the host snapshot and record an
+    // event; wait_snapshot blocks until it has arrived.
+    int enqueue_snapshot();
+    int wait_snapshot();
+    bool snapshot_ready();
+    const SysState &state(int j) const { return snap_[j]; }
+
+private:
+    int launch_iter(bool with_ru);
+    CgArgs args() const;
+
+    Ctx *ctx_;
+    std::shared_ptr<GaugeField> f_;
+    int prec_, S_;
+    hipStream_t s_;
+    KernelCfg cfg_, cfg64_;
+    int pstride_ = 0;
+    void *mem_ = nullptr;
+    size_t bytes_ = 0;
+    // device views into mem_
+    void *p_ = nullptr, *ap_ = nullptr, *r_ = nullptr;
+    flt2 *xlo_ = nullptr;
+    dbl2 *tmp_ = nullptr;
+    dbl2 **xhi_d_ = nullptr;
+    const dbl2 **b_d_ = nullptr;
+    SysState *st_d_ = nullptr;
+    double *partials_ = nullptr;
+    unsigned *counters_ = nullptr;
+    // pinned host memory
+    SysState *stage_ = nullptr;   // [nsys] staged initial states
+    SysState *snap_ = nullptr;    // [nsys] last snapshot
+    dbl2 **xhi_h_ = nullptr;
+    const dbl2 **b_h_ = nullptr;
+    hipEvent_t snap_ev_ = nullptr, stage_ev_ = nullptr;
+    bool stage_busy_ = false;
+};
+
+}  // namespace stag

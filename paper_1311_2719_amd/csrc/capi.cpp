@@ -1,0 +1,411 @@
+// The C ABI of libstagcg (declared in include/stagcg.h): argument checking and
+// dispatch into the runtime.  No exception crosses this boundary.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "runtime.hpp"
+#include "serve.hpp"
+
+namespace stag {
+const char *last_error_cstr();
+int validate_cg_params(const stag_cg_params &p);
+}  // namespace stag
+
+using namespace stag;
+
+#define STAG_GUARD_BEGIN try {
+#define STAG_GUARD_END                                                              \
+    }                                                                               \
+    catch (const std::bad_alloc &) { return set_error(STAG_ENOMEM, "host allocation failed"); } \
+    catch (...) { return set_error(STAG_EHIP, "internal error"); }
+
+static hipStream_t pick_stream(stag_ctx *ctx, void *stream)
+{
+    return stream ? (hipStream_t)stream : reinterpret_cast<Ctx *>(ctx)->stream;
+}
+
+static bool dims_ok(const int32_t *d)
+{
+    if (!d)
+        return false;
+    int64_t v = 1;
+    for (int i = 0; i < 4; ++i) {
+        if (d[i] < 2 || (d[i] & 1))
+            return false;
+        v *= d[i];
+    }
+    // checkerboard indices are 32-bit: V/2 must fit
+    return v / 2 < (int64_t)1 << 31 && (v / 2) * 8 * 9 < ((int64_t)1 << 62);
+}
+
+extern "C" {
+
+const char *stag_version(void) { return "stagcg 1.0 (gfx950)"; }
+
+const char *stag_last_error(void) { return last_error_cstr(); }
+
+int stag_create(int device, void *arena_dev, size_t arena_bytes, void *stream, stag_ctx **out)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!out || !arena_dev)
+        return set_error(STAG_EINVAL, "stag_create: NULL arena or output pointer");
+    if (arena_bytes < ((size_t)1 << 20))
+        return set_error(STAG_EINVAL, "stag_create: arena must be at least 1 MiB");
+    int ndev = 0;
+    STAG_HIP_CHECK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev)
+        return set_error(STAG_EINVAL, "stag_create: device %d out of range (%d devices)", device, ndev);
+    DeviceGuard dg(device);
+    Ctx *c = new Ctx();
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    c->arena.init(arena_dev, arena_bytes);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        c->num_cus = cus;
+    *out = reinterpret_cast<stag_ctx *>(c);
+    return STAG_OK;
+    STAG_GUARD_END
+}
+
+int stag_destroy(stag_ctx *ctx)
+{
+    STAG_GUARD_BEGIN
+    if (!ctx)
+        return set_error(STAG_EINVAL, "stag_destroy: NULL context");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    DeviceGuard dg(c->device);
+    c->server.reset();
+    (void)hipDeviceSynchronize();
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        c->fields.clear();
+    }
+    delete c;
+    return STAG_OK;
+    STAG_GUARD_END
+}
+
+int stag_arena_usage(const stag_ctx *ctx, size_t *used, size_t *total)
+{
+    if (!ctx)
+        return set_error(STAG_EINVAL, "NULL context");
+    const Ctx *c = reinterpret_cast<const Ctx *>(ctx);
+    if (used)
+        *used = c->arena.used();
+    if (total)
+        *total = c->arena.total();
+    return STAG_OK;
+}
+
+int stag_set_gauge(stag_ctx *ctx, const int32_t dims[4], const double *links, int32_t links_on_device,
+                   int32_t t_antiperiodic, int32_t *gauge_id)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx || !links || !gauge_id)
+        return set_error(STAG_EINVAL, "stag_set_gauge: NULL argument");
+    if (!dims_ok(dims))
+        return set_error(STAG_EINVAL, "stag_set_gauge: every extent must be even and >= 2");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    DeviceGuard dg(c->device);
+    auto f = std::make_shared<GaugeField>();
+    memcpy(f->dims, dims, sizeof(f->dims));
+    f->tap = t_antiperiodic ? 1 : 0;
+    f->g = make_geom(dims);
+    const size_t Vh = f->g.Vh;
+    const size_t lbytes[3] = {2 * 8 * 9 * Vh * 16, 2 * 8 * 9 * Vh * 8, 2 * 8 * 9 * Vh * 4};
+    for (int p = 0; p < 3; ++p) {
+        f->links[p] = c->arena.alloc(lbytes[p]);
+        f->bytes += lbytes[p];
+    }
+    f->nbr = (int32_t *)c->arena.alloc(2 * 8 * Vh * sizeof(int32_t));
+    f->bytes += 2 * 8 * Vh * sizeof(int32_t);
+    auto release_all = [&]() {
+        for (int p = 0; p < 3; ++p)
+            c->arena.release(f->links[p]);
+        c->arena.release(f->nbr);
+    };
+    if (!f->links[0] || !f->links[1] || !f->links[2] || !f->nbr) {
+        release_all();
+        return set_error(STAG_ENOMEM, "stag_set_gauge: arena exhausted (%zu bytes needed)", f->bytes);
+    }
+    const size_t in_bytes = 2 * Vh * 4 * 9 * 16;
+    const double *src = links;
+    void *staging = nullptr;
+    hipStream_t s = c->stream;
+    if (!links_on_device) {
+        staging = c->arena.alloc(in_bytes);
+        if (!staging) {
+            release_all();
+            return set_error(STAG_ENOMEM, "stag_set_gauge: arena exhausted (staging %zu bytes)", in_bytes);
+        }
+        hipError_t e = hipMemcpyAsync(staging, links, in_bytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) {
+            c->arena.release(staging);
+            release_all();
+            return set_error(STAG_EHIP, "stag_set_gauge: copy failed: %s", hipGetErrorString(e));
+        }
+        src = (const double *)staging;
+    }
+    int rc = gauge_prepare(c, f.get(), src, s);
+    if (staging)
+        c->arena.release(staging);
+    if (rc != STAG_OK) {
+        release_all();
+        return rc;
+    }
+    std::lock_guard<std::mutex> lk(c->mu);
+    f->id = c->next_id++;
+    c->fields[f->id] = f;
+    *gauge_id = f->id;
+    return STAG_OK;
+    STAG_GUARD_END
+}
+
+int stag_free_gauge(stag_ctx *ctx, int32_t gauge_id)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx)
+        return set_error(STAG_EINVAL, "NULL context");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    DeviceGuard dg(c->device);
+    std::shared_ptr<GaugeField> f;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        auto it = c->fields.find(gauge_id);
+        if (it == c->fields.end())
+            return set_error(STAG_ENOENT, "unknown gauge id %d", gauge_id);
+        if (it->second->users.load() > 0)
+            return set_error(STAG_EBUSY, "gauge field %d has %d pending requests", gauge_id,
+                             it->second->users.load());
+        f = it->second;
+        c->fields.erase(it);
+    }
+    if (c->server)
+        c->server->drop_field(gauge_id);
+    (void)hipDeviceSynchronize();
+    for (int p = 0; p < 3; ++p)
+        c->arena.release(f->links[p]);
+    c->arena.release(f->nbr);
+    return STAG_OK;
+    STAG_GUARD_END
+}
+
+int stag_gauge_dims(stag_ctx *ctx, int32_t gauge_id, int32_t dims[4])
+{
+    if (!ctx || !dims)
+        return set_error(STAG_EINVAL, "NULL argument");
+    auto f = reinterpret_cast<Ctx *>(ctx)->field(gauge_id);
+    if (!f)
+        return set_error(STAG_ENOENT, "unknown gauge id %d", gauge_id);
+    memcpy(dims, f->dims, sizeof(f->dims));
+    return STAG_OK;
+}
+
+int stag_pack_fermion(stag_ctx *ctx, const int32_t dims[4], const double *lex, double *eo, void *stream)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx || !lex || !eo)
+        return set_error(STAG_EINVAL, "stag_pack_fermion: NULL argument");
+    if (!dims_ok(dims))
+        return set_error(STAG_EINVAL, "stag_pack_fermion: every extent must be even and >= 2");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    DeviceGuard dg(c->device);
+    return launch_pack(make_geom(dims), lex, eo, 1, pick_stream(ctx, stream));
+    STAG_GUARD_END
+}
+
+int stag_unpack_fermion(stag_ctx *ctx, const int32_t dims[4], const double *eo, double *lex, void *stream)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx || !lex || !eo)
+        return set_error(STAG_EINVAL, "stag_unpack_fermion: NULL argument");
+    if (!dims_ok(dims))
+        return set_error(STAG_EINVAL, "stag_unpack_fermion: every extent must be even and >= 2");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    DeviceGuard dg(c->device);
+    return launch_pack(make_geom(dims), lex, const_cast<double *>(eo), 0, pick_stream(ctx, stream));
+    STAG_GUARD_END
+}
+
+int stag_dslash(stag_ctx *ctx, int32_t gauge_id, int32_t out_parity, int64_t offset, int64_t count,
+                const double *in, double *out, int32_t accumulate, void *stream)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx || !in || !out)
+        return set_error(STAG_EINVAL, "stag_dslash: NULL argument");
+    if (in == out)
+        return set_error(STAG_EINVAL, "stag_dslash: in and out must not overlap");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    auto f = c->field(gauge_id);
+    if (!f)
+        return set_error(STAG_ENOENT, "unknown gauge id %d", gauge_id);
+    const int64_t Vh = f->g.Vh;
+    if (out_parity < STAG_EVEN || out_parity > STAG_ALL)
+        return set_error(STAG_EINVAL, "stag_dslash: bad parity %d", out_parity);
+    if (count < 0)
+        count = Vh - offset;
+    if (out_parity == STAG_ALL && (offset != 0 || count != Vh))
+        return set_error(STAG_EINVAL, "stag_dslash: STAG_ALL takes offset 0 and count -1");
+    if (offset < 0 || offset > Vh || count < 0 || offset + count > Vh)
+        return set_error(STAG_EINVAL, "stag_dslash: range [%lld, %lld) outside [0, %lld)", (long long)offset,
+                         (long long)(offset + count), (long long)Vh);
+    const char *a0 = (const char *)in, *b0 = (const char *)out;
+    const size_t fb = (size_t)2 * 3 * Vh * 16;
+    if (a0 < b0 + fb && b0 < a0 + fb)
+        return set_error(STAG_EINVAL, "stag_dslash: in and out must not overlap");
+    if (count == 0)
+        return STAG_OK;
+    DeviceGuard dg(c->device);
+    return dslash_f64(c, f.get(), out_parity, offset, count, in, out, accumulate, pick_stream(ctx, stream));
+    STAG_GUARD_END
+}
+
+int stag_cg_solve(stag_ctx *ctx, int32_t gauge_id, const stag_cg_params *params, const double *b, double *x,
+                  double *y, void *stream, stag_cg_info *info)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx || !params || !b || !x)
+        return set_error(STAG_EINVAL, "stag_cg_solve: NULL argument");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    auto f = c->field(gauge_id);
+    if (!f)
+        return set_error(STAG_ENOENT, "unknown gauge id %d", gauge_id);
+    int rc = validate_cg_params(*params);
+    if (rc != STAG_OK)
+        return rc;
+    DeviceGuard dg(c->device);
+    double *ys[1] = {y};
+    return cg_solve_batch(c, f, 1, params, &b, &x, ys, pick_stream(ctx, stream), info);
+    STAG_GUARD_END
+}
+
+int stag_cg_solve_batch(stag_ctx *ctx, int32_t gauge_id, int32_t nrhs, const stag_cg_params *params,
+                        const double *const *b, double *const *x, void *stream, stag_cg_info *infos)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx || !params || !b || !x || nrhs <= 0)
+        return set_error(STAG_EINVAL, "stag_cg_solve_batch: NULL argument or nrhs <= 0");
+    if (nrhs > 64)
+        return set_error(STAG_EINVAL, "stag_cg_solve_batch: at most 64 right-hand sides");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    auto f = c->field(gauge_id);
+    if (!f)
+        return set_error(STAG_ENOENT, "unknown gauge id %d", gauge_id);
+    for (int i = 0; i < nrhs; ++i) {
+        int rc = validate_cg_params(params[i]);
+        if (rc != STAG_OK)
+            return rc;
+    }
+    DeviceGuard dg(c->device);
+    return cg_solve_batch(c, f, nrhs, params, b, x, nullptr, pick_stream(ctx, stream), infos);
+    STAG_GUARD_END
+}
+
+int stag_tune_info(stag_ctx *ctx, int32_t gauge_id, int32_t precision, int32_t nrhs, int32_t *lanes_per_site,
+                   int32_t *block, int32_t *rhs_tile, int32_t *use_tables)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx || precision < 0 || precision > 2 || nrhs <= 0)
+        return set_error(STAG_EINVAL, "stag_tune_info: bad argument");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    auto f = c->field(gauge_id);
+    if (!f)
+        return set_error(STAG_ENOENT, "unknown gauge id %d", gauge_id);
+    DeviceGuard dg(c->device);
+    KernelCfg k = tune_config(c, f.get(), precision, nrhs, c->stream);
+    if (lanes_per_site)
+        *lanes_per_site = k.lps;
+    if (block)
+        *block = k.block;
+    if (rhs_tile)
+        *rhs_tile = k.rtile;
+    if (use_tables)
+        *use_tables = k.tables;
+    return STAG_OK;
+    STAG_GUARD_END
+}
+
+// ---- serving ------------------------------------------------------------------
+
+static Server *server_of(Ctx *c)
+{
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (!c->server)
+        c->server.reset(new Server(c));
+    return c->server.get();
+}
+
+int stag_serve_config(stag_ctx *ctx, int32_t slots_per_field, int32_t epoch_iters, int32_t queue_capacity)
+{
+    if (!ctx)
+        return set_error(STAG_EINVAL, "NULL context");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (slots_per_field < 1 || slots_per_field > 64 || epoch_iters < 1 || epoch_iters > 1024 || queue_capacity < 1)
+        return set_error(STAG_EINVAL, "stag_serve_config: slots 1..64, epoch 1..1024, capacity >= 1");
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->server)
+        return set_error(STAG_EBUSY, "stag_serve_config: serving already started");
+    c->slots_per_field = slots_per_field;
+    c->epoch_iters = epoch_iters;
+    c->queue_capacity = queue_capacity;
+    return STAG_OK;
+}
+
+int stag_submit(stag_ctx *ctx, int32_t gauge_id, const stag_cg_params *params, const double *b_dev, double *x_dev,
+                uint64_t *ticket)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx || !params || !b_dev || !x_dev || !ticket)
+        return set_error(STAG_EINVAL, "stag_submit: NULL argument");
+    int rc = validate_cg_params(*params);
+    if (rc != STAG_OK)
+        return rc;
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    auto f = c->field(gauge_id);
+    if (!f)
+        return set_error(STAG_ENOENT, "unknown gauge id %d", gauge_id);
+    return server_of(c)->submit(f, *params, b_dev, x_dev, ticket);
+    STAG_GUARD_END
+}
+
+int stag_poll(stag_ctx *ctx, uint64_t ticket, stag_cg_info *info)
+{
+    STAG_GUARD_BEGIN
+    if (!ctx)
+        return set_error(STAG_EINVAL, "NULL context");
+    return server_of(reinterpret_cast<Ctx *>(ctx))->poll(ticket, info, false);
+    STAG_GUARD_END
+}
+
+int stag_wait(stag_ctx *ctx, uint64_t ticket, stag_cg_info *info)
+{
+    STAG_GUARD_BEGIN
+    if (!ctx)
+        return set_error(STAG_EINVAL, "NULL context");
+    return server_of(reinterpret_cast<Ctx *>(ctx))->poll(ticket, info, true);
+    STAG_GUARD_END
+}
+
+int stag_release_ticket(stag_ctx *ctx, uint64_t ticket)
+{
+    STAG_GUARD_BEGIN
+    if (!ctx)
+        return set_error(STAG_EINVAL, "NULL context");
+    return server_of(reinterpret_cast<Ctx *>(ctx))->release(ticket);
+    STAG_GUARD_END
+}
+
+}  // extern "C"

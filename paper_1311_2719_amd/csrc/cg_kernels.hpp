@@ -1,0 +1,623 @@
+// Fused conjugate-gradient kernels for (m^2 - D^2) x = b on one parity,
+// batched over systems that share a gauge field.
+//
+// The iteration is the loop of the paper's Sec. 4 with the mass explicit,
+// split into three kernels so that no vector is re-read needlessly and every
+// scalar stays on the device:
+//   K1  ap = D p (other parity), <ap,ap>;           last block: alpha = rr / (m^2 <p,p> + <ap,ap>)
+//   K2  Ap = m^2 p - D ap; x += alpha p; r -= alpha Ap; <r,r>   (Ap is never stored)
+//                                                    last block: stopping test, beta
+//   K3  p = r + beta p, <p,p>
+// Reliable updates (mixed precision, and the final FP64 check in every mode):
+//   RU2 t = D x on the other parity in FP64 (x = x_hi + x_lo)
+//   RU3 x_hi += x_lo, x_lo = 0, r = b - m^2 x_hi + D t in FP64, <r,r>
+// Each kernel's per-block partial sums are reduced by the last block to finish
+// (ticket counter), which also evaluates the scalar recurrences of the
+// systems: the host never reads a scalar inside the loop.
+//
+// Systems: nsys = 2*S, system j has parity j / S (its x, r, p live on that
+// parity; ap and t on the other).  A tile is R systems of one parity that are
+// processed together so each link entry is loaded once for all of them.
+#pragma once
+
+#include "hop.hpp"
+
+namespace stag {
+
+enum Phase : int32_t { PH_IDLE = 0, PH_INIT = 1, PH_RUN = 2, PH_DONE = 3 };
+
+struct SysState {
+    double mass2;
+    double tol2;
+    double stop2;    // tol^2 <b,b>
+    double bb;
+    double rr;       // <r,r> of the current (iterated) residual
+    double pp;       // <p,p> of the stored search direction
+    double alpha;
+    double beta;
+    double maxr2;    // largest <r,r> since the last residual recomputation
+    double delta2;   // reliable-update threshold squared (0: final check only)
+    double true_rr;  // <r,r> of the last FP64 residual recomputation
+    double pad0;
+    int32_t phase;
+    int32_t ru_pending;  // residual recomputation requested
+    int32_t stopping;    // status to report if the recomputation does not converge
+    int32_t status;      // final status (phase == PH_DONE)
+    int32_t iters;
+    int32_t maxiter;
+    int32_t n_ru;
+    int32_t restarts;
+    int32_t max_restarts;
+    int32_t mixed;
+    int32_t pad1[2];
+};
+
+struct CgArgs {
+    Geom g;
+    const void *links[2];      // links of the working precision, per output parity
+    const dbl2 *links64[2];    // FP64 links, per output parity
+    const int32_t *nbr[2];     // neighbour tables per output parity, or null
+    void *p;                   // [nsys] stored spinors (working precision)
+    void *ap;                  // [nsys] stored spinors (working precision)
+    void *r;                   // [nsys][3][Vh] complex of the compute type
+    flt2 *xlo;                 // [nsys][3][Vh] (mixed precision only)
+    dbl2 *tmp;                 // [nsys][3][Vh] FP64 work vector (other parity)
+    dbl2 *const *xhi;          // [nsys] parity half of the caller's x
+    const dbl2 *const *b;      // [nsys] parity half of the caller's b
+    SysState *st;              // [nsys]
+    double *partials;          // [nsys][pstride]
+    unsigned *counters;        // [nsys]
+    int S;                     // systems per parity
+    int pstride;
+    int remap;
+};
+
+template <typename T> struct vec2_of;
+template <> struct vec2_of<double> { using type = dbl2; };
+template <> struct vec2_of<float> { using type = flt2; };
+
+template <class P> __device__ __forceinline__ void *spin_at(void *base, int j, int Vh)
+{
+    return (char *)base + (size_t)j * Vh * P::spinor_bytes;
+}
+
+template <class P> __device__ __forceinline__ cplx<typename P::real> load_colour(const void *base, int Vh, int s, int c)
+{
+    cplx<typename P::real> v[3];
+    if constexpr (P::id == 2) {
+        P::load_spinor(base, Vh, s, v);
+        return v[c];
+    } else {
+        using v2 = typename vec2_of<typename P::real>::type;
+        v2 t = ((const v2 *)base)[(int64_t)c * Vh + s];
+        return {t.x, t.y};
+    }
+}
+
+__device__ __forceinline__ void tile_of(const CgArgs &a, int tile, int R, int &par, int &j0)
+{
+    const int tpp = a.S / R;
+    par = tile / tpp;
+    j0 = par * a.S + (tile % tpp) * R;
+}
+
+__device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v < INFINITY; }
+
+// ---- K1: ap = D p -----------------------------------------------------------
+
+template <class P, int LPS, int R>
+__global__ void __launch_bounds__(256) k_cg_ap(CgArgs a)
+{
+    using real = typename P::real;
+    __shared__ double lds[R * 4];
+    __shared__ int flag;
+    int par, j0;
+    tile_of(a, blockIdx.y, R, par, j0);
+    const int pout = 1 - par;
+    bool act[R];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const SysState &st = a.st[j0 + r];
+        act[r] = st.phase == PH_RUN && !st.ru_pending;
+        any |= act[r];
+    }
+    if (!any)
+        return;
+    const int Vh = a.g.Vh;
+    const int lb = logical_block(blockIdx.x, gridDim.x, a.remap);
+    const int gt = lb * blockDim.x + threadIdx.x;
+    const int s = gt / LPS, sub = gt % LPS;
+    double nrm[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        nrm[r] = 0.0;
+    if (s < Vh) {
+        const void *in[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            in[r] = spin_at<P>(a.p, j0 + r, Vh);
+        cplx<real> acc[R][3];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                acc[r][c] = czero<real>();
+        hop_accumulate<P, LPS, R>(a.g, (const typename P::link_t *)a.links[pout], a.nbr[pout], pout, s, sub,
+                                  in, act, acc);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (!act[r])
+                continue;
+            void *out = spin_at<P>(a.ap, j0 + r, Vh);
+            if constexpr (P::id == 2) {
+                if (sub == 0)
+                    P::store_spinor(out, Vh, s, acc[r]);
+            } else {
+                using v2 = typename vec2_of<real>::type;
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    if (owns_colour<LPS>(sub, c))
+                        ((v2 *)out)[(int64_t)c * Vh + s] = v2{acc[r][c].re, acc[r][c].im};
+            }
+            if (sub == 0) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    nrm[r] += (double)acc[r][c].re * acc[r][c].re + (double)acc[r][c].im * acc[r][c].im;
+            }
+        }
+    }
+    double tot;
+    block_sum_multi<R>(nrm, lds, tot);
+    if (threadIdx.x < R)
+        publish_partial(a.partials + (size_t)(j0 + threadIdx.x) * a.pstride + blockIdx.x, tot);
+    if (!arrive_last(a.counters + blockIdx.y, gridDim.x, &flag))
+        return;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!act[r])
+            continue;
+        const double apap = reduce_partials(a.partials + (size_t)(j0 + r) * a.pstride, gridDim.x, lds);
+        if (threadIdx.x == 0) {
+            SysState &st = a.st[j0 + r];
+            const double pap = st.mass2 * st.pp + apap;
+            if (!finite_pos(pap)) {
+                st.ru_pending = 1;
+                st.stopping = STAG_EBREAKDOWN;
+            } else {
+                st.alpha = st.rr / pap;
+            }
+        }
+    }
+}
+
+// ---- K2: Ap = m^2 p - D ap, x += alpha p, r -= alpha Ap ------------------------
+
+template <class P, int LPS, int R>
+__global__ void __launch_bounds__(256) k_cg_update(CgArgs a)
+{
+    using real = typename P::real;
+    using v2 = typename vec2_of<real>::type;
+    __shared__ double lds[R * 4];
+    __shared__ int flag;
+    int par, j0;
+    tile_of(a, blockIdx.y, R, par, j0);
+    bool act[R];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const SysState &st = a.st[j0 + r];
+        act[r] = st.phase == PH_RUN && !st.ru_pending;
+        any |= act[r];
+    }
+    if (!any)
+        return;
+    const int Vh = a.g.Vh;
+    const int lb = logical_block(blockIdx.x, gridDim.x, a.remap);
+    const int gt = lb * blockDim.x + threadIdx.x;
+    const int s = gt / LPS, sub = gt % LPS;
+    double nrm[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        nrm[r] = 0.0;
+    if (s < Vh) {
+        const void *in[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            in[r] = spin_at<P>(a.ap, j0 + r, Vh);
+        cplx<real> acc[R][3];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                acc[r][c] = czero<real>();
+        hop_accumulate<P, LPS, R>(a.g, (const typename P::link_t *)a.links[par], a.nbr[par], par, s, sub, in,
+                                  act, acc);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (!act[r])
+                continue;
+            const int j = j0 + r;
+            const SysState &st = a.st[j];
+            const real m2 = (real)st.mass2, alpha = (real)st.alpha;
+            const void *pb = spin_at<P>(a.p, j, Vh);
+            v2 *rv = (v2 *)a.r + (size_t)j * 3 * Vh;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (!owns_colour<LPS>(sub, c))
+                    continue;
+                const cplx<real> pv = load_colour<P>(pb, Vh, s, c);
+                const int64_t o = (int64_t)c * Vh + s;
+                if constexpr (P::id == 0) {
+                    dbl2 *x = a.xhi[j];
+                    dbl2 xv = x[o];
+                    x[o] = dbl2{fma(alpha, pv.re, xv.x), fma(alpha, pv.im, xv.y)};
+                } else {
+                    flt2 xv = a.xlo[(size_t)j * 3 * Vh + o];
+                    a.xlo[(size_t)j * 3 * Vh + o] = flt2{fmaf(alpha, pv.re, xv.x), fmaf(alpha, pv.im, xv.y)};
+                }
+                const real apr = m2 * pv.re - acc[r][c].re;
+                const real api = m2 * pv.im - acc[r][c].im;
+                v2 rr = rv[o];
+                rr.x = fma(-alpha, apr, rr.x);
+                rr.y = fma(-alpha, api, rr.y);
+                rv[o] = rr;
+                nrm[r] += (double)rr.x * rr.x + (double)rr.y * rr.y;
+            }
+        }
+    }
+    double tot;
+    block_sum_multi<R>(nrm, lds, tot);
+    if (threadIdx.x < R)
+        publish_partial(a.partials + (size_t)(j0 + threadIdx.x) * a.pstride + blockIdx.x, tot);
+    if (!arrive_last(a.counters + blockIdx.y, gridDim.x, &flag))
+        return;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!act[r])
+            continue;
+        const double rn = reduce_partials(a.partials + (size_t)(j0 + r) * a.pstride, gridDim.x, lds);
+        if (threadIdx.x == 0) {
+            SysState &st = a.st[j0 + r];
+            st.iters += 1;
+            if (!(rn < INFINITY)) {
+                st.ru_pending = 1;
+                st.stopping = STAG_EBREAKDOWN;
+            } else {
+                const bool conv = rn < st.stop2;
+                st.maxr2 = rn > st.maxr2 ? rn : st.maxr2;
+                bool recompute = conv || rn < st.delta2 * st.maxr2;
+                if (!conv && st.iters >= st.maxiter) {
+                    st.stopping = STAG_ENOCONV;
+                    recompute = true;
+                }
+                if (recompute) {
+                    // beta is formed from the recomputed residual; rr keeps the
+                    // previous iteration's value as its denominator
+                    st.ru_pending = 1;
+                } else {
+                    st.beta = rn / st.rr;
+                    st.rr = rn;
+                }
+            }
+        }
+    }
+}
+
+// ---- K3: p = r + beta p, <p,p> -------------------------------------------------
+
+template <class P>
+__global__ void __launch_bounds__(256) k_cg_direction(CgArgs a)
+{
+    using real = typename P::real;
+    using v2 = typename vec2_of<real>::type;
+    __shared__ double lds[4];
+    __shared__ int flag;
+    const int j = blockIdx.y;
+    {
+        const SysState &st = a.st[j];
+        if (!(st.phase == PH_RUN && !st.ru_pending))
+            return;
+    }
+    const int Vh = a.g.Vh;
+    const int s = logical_block(blockIdx.x, gridDim.x, a.remap) * blockDim.x + threadIdx.x;
+    double nrm[1] = {0.0};
+    if (s < Vh) {
+        const real beta = (real)a.st[j].beta;
+        const v2 *rv = (const v2 *)a.r + (size_t)j * 3 * Vh;
+        void *pb = spin_at<P>(a.p, j, Vh);
+        cplx<real> pv[3];
+        P::load_spinor(pb, Vh, s, pv);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const v2 rr = rv[(int64_t)c * Vh + s];
+            pv[c].re = fma(beta, pv[c].re, rr.x);
+            pv[c].im = fma(beta, pv[c].im, rr.y);
+        }
+        P::store_spinor(pb, Vh, s, pv);
+        if constexpr (P::id == 2)
+            P::load_spinor(pb, Vh, s, pv);  // norm of the value D will read
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            nrm[0] += (double)pv[c].re * pv[c].re + (double)pv[c].im * pv[c].im;
+    }
+    double tot;
+    block_sum_multi<1>(nrm, lds, tot);
+    if (threadIdx.x == 0)
+        publish_partial(a.partials + (size_t)j * a.pstride + blockIdx.x, tot);
+    if (!arrive_last(a.counters + j, gridDim.x, &flag))
+        return;
+    const double pp = reduce_partials(a.partials + (size_t)j * a.pstride, gridDim.x, lds);
+    if (threadIdx.x == 0)
+        a.st[j].pp = pp;
+}
+
+// ---- init: x = 0, r = b, p = r ---------------------------------------------------
+
+template <class P>
+__global__ void __launch_bounds__(256) k_cg_init(CgArgs a)
+{
+    using real = typename P::real;
+    using v2 = typename vec2_of<real>::type;
+    __shared__ double lds[8];
+    __shared__ int flag;
+    const int j = blockIdx.y;
+    if (a.st[j].phase != PH_INIT)
+        return;
+    const int Vh = a.g.Vh;
+    const int s = logical_block(blockIdx.x, gridDim.x, a.remap) * blockDim.x + threadIdx.x;
+    double nrm[2] = {0.0, 0.0};
+    if (s < Vh) {
+        const dbl2 *b = a.b[j];
+        dbl2 *x = a.xhi[j];
+        v2 *rv = (v2 *)a.r + (size_t)j * 3 * Vh;
+        cplx<real> pv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t o = (int64_t)c * Vh + s;
+            const dbl2 bv = b[o];
+            x[o] = dbl2{0.0, 0.0};
+            if constexpr (P::id != 0)
+                a.xlo[(size_t)j * 3 * Vh + o] = flt2{0.f, 0.f};
+            rv[o] = v2{(real)bv.x, (real)bv.y};
+            pv[c] = {(real)bv.x, (real)bv.y};
+            nrm[0] += bv.x * bv.x + bv.y * bv.y;
+        }
+        void *pb = spin_at<P>(a.p, j, Vh);
+        P::store_spinor(pb, Vh, s, pv);
+        if constexpr (P::id == 2)
+            P::load_spinor(pb, Vh, s, pv);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            nrm[1] += (double)pv[c].re * pv[c].re + (double)pv[c].im * pv[c].im;
+    }
+    double tot;
+    block_sum_multi<2>(nrm, lds, tot);
+    if (threadIdx.x < 2)
+        publish_partial(a.partials + (size_t)j * a.pstride * 2 + threadIdx.x * a.pstride + blockIdx.x, tot);
+    if (!arrive_last(a.counters + j, gridDim.x, &flag))
+        return;
+    const double bb = reduce_partials(a.partials + (size_t)j * a.pstride * 2, gridDim.x, lds);
+    const double pp = reduce_partials(a.partials + (size_t)j * a.pstride * 2 + a.pstride, gridDim.x, lds);
+    if (threadIdx.x == 0) {
+        SysState &st = a.st[j];
+        st.bb = bb;
+        st.stop2 = st.tol2 * bb;
+        st.rr = bb;
+        st.pp = pp;
+        st.maxr2 = bb;
+        st.iters = 0;
+        st.n_ru = 0;
+        st.restarts = 0;
+        st.ru_pending = 0;
+        st.stopping = 0;
+        st.beta = 0.0;
+        st.alpha = 0.0;
+        st.true_rr = bb;
+        if (!(bb < INFINITY)) {
+            st.phase = PH_DONE;
+            st.status = STAG_ENONFINITE;
+        } else if (bb == 0.0) {
+            st.phase = PH_DONE;
+            st.status = STAG_OK;
+            st.true_rr = 0.0;
+        } else {
+            st.phase = PH_RUN;
+        }
+    }
+}
+
+// ---- RU2: t = D (x_hi + x_lo) on the other parity, FP64 -----------------------------
+
+template <int LPS, bool MIXED>
+__global__ void __launch_bounds__(256) k_ru_dx(CgArgs a)
+{
+    const int j = blockIdx.y;
+    {
+        const SysState &st = a.st[j];
+        if (!(st.phase == PH_RUN && st.ru_pending))
+            return;
+    }
+    const int par = j / a.S, pout = 1 - par;
+    const int Vh = a.g.Vh;
+    const int gt = logical_block(blockIdx.x, gridDim.x, a.remap) * blockDim.x + threadIdx.x;
+    const int s = gt / LPS, sub = gt % LPS;
+    if (s >= Vh)
+        return;
+    const dbl2 *lk = a.links64[pout];
+    const int32_t *nb = a.nbr[pout];
+    SiteCoord co;
+    if (!nb)
+        co = decode_site(a.g, pout, s);
+    const dbl2 *xh = a.xhi[j];
+    const flt2 *xl = a.xlo + (size_t)j * 3 * Vh;
+    cplx<double> acc[3] = {czero<double>(), czero<double>(), czero<double>()};
+#pragma unroll
+    for (int q = 0; q < 8 / LPS; ++q) {
+        const int d = sub + q * LPS;
+        const int n = nb ? nb[(int64_t)d * Vh + s] : neighbour(a.g, co, s, d);
+        cplx<double> U[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const dbl2 v = lk[((int64_t)d * 9 + k) * Vh + s];
+            U[k] = {v.x, v.y};
+        }
+        cplx<double> chi[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            dbl2 v = xh[(int64_t)c * Vh + n];
+            if constexpr (MIXED) {
+                const flt2 w = xl[(int64_t)c * Vh + n];
+                v.x += (double)w.x;
+                v.y += (double)w.y;
+            }
+            chi[c] = {v.x, v.y};
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                cmac(acc[c], U[c * 3 + b], chi[b]);
+    }
+    dbl2 *t = a.tmp + (size_t)j * 3 * Vh;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        acc[c].re = lane_sum<LPS>(acc[c].re);
+        acc[c].im = lane_sum<LPS>(acc[c].im);
+        if (owns_colour<LPS>(sub, c))
+            t[(int64_t)c * Vh + s] = dbl2{acc[c].re, acc[c].im};
+    }
+}
+
+// ---- RU3: x_hi += x_lo, r = b - m^2 x_hi + D t in FP64 ----------------------------------
+
+template <class P, int LPS>
+__global__ void __launch_bounds__(256) k_ru_residual(CgArgs a)
+{
+    using real = typename P::real;
+    using v2 = typename vec2_of<real>::type;
+    constexpr bool MIXED = P::id != 0;
+    __shared__ double lds[4];
+    __shared__ int flag;
+    const int j = blockIdx.y;
+    {
+        const SysState &st = a.st[j];
+        if (!(st.phase == PH_RUN && st.ru_pending))
+            return;
+    }
+    const int par = j / a.S;
+    const int Vh = a.g.Vh;
+    const int gt = logical_block(blockIdx.x, gridDim.x, a.remap) * blockDim.x + threadIdx.x;
+    const int s = gt / LPS, sub = gt % LPS;
+    double nrm[1] = {0.0};
+    if (s < Vh) {
+        const void *in[1] = {a.tmp + (size_t)j * 3 * Vh};
+        const bool act[1] = {true};
+        cplx<double> acc[1][3] = {{czero<double>(), czero<double>(), czero<double>()}};
+        hop_accumulate<PrecF64, LPS, 1>(a.g, a.links64[par], a.nbr[par], par, s, sub, in, act, acc);
+        const double m2 = a.st[j].mass2;
+        dbl2 *x = a.xhi[j];
+        const dbl2 *b = a.b[j];
+        v2 *rv = (v2 *)a.r + (size_t)j * 3 * Vh;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (!owns_colour<LPS>(sub, c))
+                continue;
+            const int64_t o = (int64_t)c * Vh + s;
+            dbl2 xv = x[o];
+            if constexpr (MIXED) {
+                const flt2 w = a.xlo[(size_t)j * 3 * Vh + o];
+                xv.x += (double)w.x;
+                xv.y += (double)w.y;
+                x[o] = xv;
+                a.xlo[(size_t)j * 3 * Vh + o] = flt2{0.f, 0.f};
+            }
+            const dbl2 bv = b[o];
+            const double rre = bv.x - m2 * xv.x + acc[0][c].re;
+            const double rim = bv.y - m2 * xv.y + acc[0][c].im;
+            rv[o] = v2{(real)rre, (real)rim};
+            nrm[0] += rre * rre + rim * rim;
+        }
+    }
+    double tot;
+    block_sum_multi<1>(nrm, lds, tot);
+    if (threadIdx.x == 0)
+        publish_partial(a.partials + (size_t)j * a.pstride + blockIdx.x, tot);
+    if (!arrive_last(a.counters + j, gridDim.x, &flag))
+        return;
+    const double trr = reduce_partials(a.partials + (size_t)j * a.pstride, gridDim.x, lds);
+    if (threadIdx.x == 0) {
+        SysState &st = a.st[j];
+        st.n_ru += 1;
+        st.ru_pending = 0;
+        st.true_rr = trr;
+        if (trr <= st.stop2) {
+            st.phase = PH_DONE;
+            st.status = STAG_OK;
+        } else if (st.stopping) {
+            st.phase = PH_DONE;
+            st.status = st.stopping;
+        } else if (!st.mixed) {
+            // FP64: the recursive residual claimed convergence but the true one
+            // disagrees: restart CG from the current x (fresh search direction).
+            st.restarts += 1;
+            if (st.restarts > st.max_restarts) {
+                st.phase = PH_DONE;
+                st.status = STAG_ENOCONV;
+            } else {
+                st.beta = 0.0;
+                st.rr = trr;
+                st.maxr2 = trr;
+            }
+        } else {
+            // reliable update: keep the search direction, continue from the true residual
+            st.beta = trr / st.rr;
+            st.rr = trr;
+            st.maxr2 = trr;
+        }
+    }
+}
+
+// ---- tuning probe: out_r = D in_r for R systems, no reductions -------------------
+
+template <class P, int LPS, int R>
+__global__ void __launch_bounds__(256) k_hop_probe(Geom g, const void *links, const int32_t *nbr, int pout,
+                                                    const void *in, void *out, int remap)
+{
+    using real = typename P::real;
+    const int Vh = g.Vh;
+    const int gt = logical_block(blockIdx.x, gridDim.x, remap) * blockDim.x + threadIdx.x;
+    const int s = gt / LPS, sub = gt % LPS;
+    if (s >= Vh)
+        return;
+    const void *inp[R];
+    bool act[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        inp[r] = (const char *)in + (size_t)r * Vh * P::spinor_bytes;
+        act[r] = true;
+    }
+    cplx<real> acc[R][3];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            acc[r][c] = czero<real>();
+    hop_accumulate<P, LPS, R>(g, (const typename P::link_t *)links, nbr, pout, s, sub, inp, act, acc);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        void *o = (char *)out + (size_t)r * Vh * P::spinor_bytes;
+        if constexpr (P::id == 2) {
+            if (sub == 0)
+                P::store_spinor(o, Vh, s, acc[r]);
+        } else {
+            using v2 = typename vec2_of<real>::type;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (owns_colour<LPS>(sub, c))
+                    ((v2 *)o)[(int64_t)c * Vh + s] = v2{acc[r][c].re, acc[r][c].im};
+        }
+    }
+}
+
+}  // namespace stag

@@ -1,0 +1,243 @@
+// The standalone FP64 D_slash (the paper's matrix-vector routine of Sec. 3,
+// `matrix-vector(offset, local_length, v, w)`, restricted to one parity or
+// applied to the whole lattice), the FP64 residual-recomputation hop, and the
+// kernel-configuration tuner.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "cg_launch.hpp"
+#include "runtime.hpp"
+
+namespace stag {
+
+const CgLaunchTable &cg_table_f64();
+const CgLaunchTable &cg_table_f32();
+const CgLaunchTable &cg_table_f16();
+
+const CgLaunchTable &cg_table(int prec)
+{
+    return prec == 0 ? cg_table_f64() : prec == 1 ? cg_table_f32() : cg_table_f16();
+}
+
+namespace {
+
+// out(x) (+)= (D in)(x) for checkerboard sites [offset, offset + count) of the
+// output parity (blockIdx.y selects the parity when par_fixed < 0).
+template <int LPS>
+__global__ void __launch_bounds__(256)
+k_dslash64(Geom g, const dbl2 *__restrict__ links, const int32_t *__restrict__ nbr, const dbl2 *__restrict__ in,
+           dbl2 *__restrict__ out, int par_fixed, int offset, int count, int accumulate, int remap)
+{
+    const int p = par_fixed >= 0 ? par_fixed : (int)blockIdx.y;
+    const int Vh = g.Vh;
+    const int gt = logical_block(blockIdx.x, gridDim.x, remap) * blockDim.x + threadIdx.x;
+    const int site = gt / LPS, sub = gt % LPS;
+    if (site >= count)
+        return;
+    const int s = offset + site;
+    const void *inp[1] = {in + (size_t)(1 - p) * 3 * Vh};
+    const bool act[1] = {true};
+    cplx<double> acc[1][3] = {{czero<double>(), czero<double>(), czero<double>()}};
+    hop_accumulate<PrecF64, LPS, 1>(g, links + (size_t)p * 8 * 9 * Vh, nbr ? nbr + (size_t)p * 8 * Vh : nullptr, p,
+                                    s, sub, inp, act, acc);
+    dbl2 *o = out + (size_t)p * 3 * Vh;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (!owns_colour<LPS>(sub, c))
+            continue;
+        dbl2 v = dbl2{acc[0][c].re, acc[0][c].im};
+        if (accumulate)
+            v += o[(int64_t)c * Vh + s];
+        o[(int64_t)c * Vh + s] = v;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_ru_dx(int lps, bool mixed, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a)
+{
+#define STAG_RU_DX(L)                                                                   \
+    if (mixed)                                                                          \
+        hipLaunchKernelGGL((k_ru_dx<L, true>), grid, block, 0, s, a);                  \
+    else                                                                                \
+        hipLaunchKernelGGL((k_ru_dx<L, false>), grid, block, 0, s, a);
+    switch (lps) {
+    case 1: STAG_RU_DX(1); break;
+    case 2: STAG_RU_DX(2); break;
+    case 4: STAG_RU_DX(4); break;
+    case 8: STAG_RU_DX(8); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef STAG_RU_DX
+    return hipGetLastError();
+}
+
+static hipError_t launch_dslash64(const KernelCfg &cfg, const GaugeField *f, int par_fixed, int nparity, int offset,
+                                  int count, const double *in, double *out, int accumulate, hipStream_t s)
+{
+    const int64_t threads = (int64_t)count * cfg.lps;
+    dim3 grid((unsigned)((threads + cfg.block - 1) / cfg.block), (unsigned)nparity);
+    dim3 block(cfg.block);
+    const dbl2 *lk = (const dbl2 *)f->links[0];
+    const int32_t *nb = cfg.tables ? f->nbr : nullptr;
+    switch (cfg.lps) {
+    case 1:
+        hipLaunchKernelGGL((k_dslash64<1>), grid, block, 0, s, f->g, lk, nb, (const dbl2 *)in, (dbl2 *)out, par_fixed,
+                           offset, count, accumulate, cfg.remap);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_dslash64<2>), grid, block, 0, s, f->g, lk, nb, (const dbl2 *)in, (dbl2 *)out, par_fixed,
+                           offset, count, accumulate, cfg.remap);
+        break;
+    case 4:
+        hipLaunchKernelGGL((k_dslash64<4>), grid, block, 0, s, f->g, lk, nb, (const dbl2 *)in, (dbl2 *)out, par_fixed,
+                           offset, count, accumulate, cfg.remap);
+        break;
+    case 8:
+        hipLaunchKernelGGL((k_dslash64<8>), grid, block, 0, s, f->g, lk, nb, (const dbl2 *)in, (dbl2 *)out, par_fixed,
+                           offset, count, accumulate, cfg.remap);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int dslash_f64(Ctx *ctx, GaugeField *f, int out_parity, int64_t offset, int64_t count, const double *in,
+               double *out, int accumulate, hipStream_t s)
+{
+    const KernelCfg cfg = tune_config(ctx, f, 0, 1, s);
+    const int Vh = f->g.Vh;
+    hipError_t e;
+    if (out_parity == STAG_ALL)
+        e = launch_dslash64(cfg, f, -1, 2, 0, Vh, in, out, accumulate, s);
+    else
+        e = launch_dslash64(cfg, f, out_parity, 1, (int)offset, (int)count, in, out, accumulate, s);
+    if (e != hipSuccess)
+        return set_error(STAG_EHIP, "dslash launch failed: %s", hipGetErrorString(e));
+    return STAG_OK;
+}
+
+// ---- tuner ----------------------------------------------------------------------
+
+static bool env_cfg(KernelCfg &c)
+{
+    const char *e = getenv("STAG_KERNEL_CFG");  // "lps,block,rtile,tables,remap"
+    if (!e || !*e)
+        return false;
+    int v[5];
+    if (sscanf(e, "%d,%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3], &v[4]) != 5)
+        return false;
+    c.lps = v[0];
+    c.block = v[1];
+    c.rtile = v[2];
+    c.tables = v[3];
+    c.remap = v[4];
+    return true;
+}
+
+static bool valid_lps(int l) { return l == 1 || l == 2 || l == 4 || l == 8; }
+
+static int default_rtile(const CgLaunchTable &t, int nrhs)
+{
+    int best = 1;
+    for (int i = 0; i < t.n_rtiles; ++i)
+        if (nrhs % t.rtiles[i] == 0)
+            best = std::max(best, t.rtiles[i]);
+    return best;
+}
+
+KernelCfg tune_config(Ctx *ctx, GaugeField *f, int prec, int nrhs, hipStream_t s)
+{
+    const uint64_t key = ((uint64_t)prec << 32) | (uint32_t)nrhs;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = f->tuned.find(key);
+        if (it != f->tuned.end())
+            return it->second;
+    }
+    const CgLaunchTable &tab = cg_table(prec);
+    KernelCfg best;
+    best.lps = prec == 0 ? 2 : 1;
+    best.block = 256;
+    best.rtile = default_rtile(tab, nrhs);
+    best.tables = 0;
+    best.remap = 1;
+    KernelCfg forced;
+    const char *tune_env = getenv("STAG_TUNE");
+    const bool tune = !(tune_env && tune_env[0] == '0');
+    if (env_cfg(forced)) {
+        if (valid_lps(forced.lps) && forced.block >= 64 && forced.block <= 256 && forced.block % 64 == 0 &&
+            nrhs % forced.rtile == 0)
+            best = forced;
+    } else if (tune) {
+        // time out_r = D in_r on scratch vectors for every candidate; keep the
+        // fastest per right-hand side
+        std::vector<int> tiles;
+        for (int i = 0; i < tab.n_rtiles; ++i)
+            if (nrhs % tab.rtiles[i] == 0)
+                tiles.push_back(tab.rtiles[i]);
+        const int rmax = *std::max_element(tiles.begin(), tiles.end());
+        const size_t vbytes = (size_t)f->g.Vh * spinor_bytes_of(prec) * rmax;
+        void *in = ctx->arena.alloc(vbytes), *out = ctx->arena.alloc(vbytes);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        bool ok = in && out && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+                  hipMemsetAsync(in, 0, vbytes, s) == hipSuccess;
+        double best_t = 1e30;
+        const int lps_c[4] = {1, 2, 4, 8}, blk_c[3] = {64, 128, 256};
+        for (int R : tiles) {
+            for (int L : lps_c) {
+                for (int B : blk_c) {
+                    for (int T = 0; T < 2 && ok; ++T) {
+                        for (int X = 0; X < 2 && ok; ++X) {
+                            const int64_t threads = (int64_t)f->g.Vh * L;
+                            dim3 grid((unsigned)((threads + B - 1) / B)), block(B);
+                            const void *links = f->links_for(prec, 1);
+                            const int32_t *nb = T ? f->nbr_for(1) : nullptr;
+                            auto run = [&]() {
+                                return tab.probe(L, R, grid, block, s, f->g, links, nb, 1, in, out, X);
+                            };
+                            if (run() != hipSuccess) {
+                                ok = false;
+                                break;
+                            }
+                            const int reps = 4;
+                            (void)hipEventRecord(e0, s);
+                            for (int i = 0; i < reps; ++i)
+                                (void)run();
+                            (void)hipEventRecord(e1, s);
+                            if (hipEventSynchronize(e1) != hipSuccess) {
+                                ok = false;
+                                break;
+                            }
+                            float ms = 0.f;
+                            (void)hipEventElapsedTime(&ms, e0, e1);
+                            const double per_rhs = ms / reps / R;
+                            if (per_rhs < best_t * 0.995) {
+                                best_t = per_rhs;
+                                best.lps = L;
+                                best.block = B;
+                                best.rtile = R;
+                                best.tables = T;
+                                best.remap = X;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        if (e0)
+            (void)hipEventDestroy(e0);
+        if (e1)
+            (void)hipEventDestroy(e1);
+        ctx->arena.release(in);
+        ctx->arena.release(out);
+        (void)hipGetLastError();
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    f->tuned[key] = best;
+    return best;
+}
+
+}  // namespace stag

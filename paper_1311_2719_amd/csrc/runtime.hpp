@@ -1,0 +1,136 @@
+// Host-side runtime of libstagcg: context, HBM arena, gauge-field registry,
+// error reporting, kernel-configuration tuner.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "stagcg.h"
+#include "stag_types.hpp"
+
+namespace stag {
+
+// ---- errors ------------------------------------------------------------------
+
+int set_error(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+#define STAG_HIP_CHECK(expr)                                                          \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return ::stag::set_error(STAG_EHIP, "%s failed: %s (%s:%d)", #expr,       \
+                                     hipGetErrorString(e_), __FILE__, __LINE__);      \
+    } while (0)
+
+// ---- arena -------------------------------------------------------------------
+
+// First-fit sub-allocator over a caller-owned device buffer.  Blocks are
+// 256-byte aligned.  Thread-safe.
+class Arena {
+public:
+    void init(void *base, size_t bytes);
+    void *alloc(size_t bytes);
+    void release(void *p);
+    size_t used() const { return used_.load(); }
+    size_t total() const { return size_; }
+    size_t largest_free() const;
+
+private:
+    char *base_ = nullptr;
+    size_t size_ = 0;
+    mutable std::mutex mu_;
+    std::map<size_t, size_t> free_;  // offset -> size
+    std::map<size_t, size_t> live_;  // offset -> size
+    std::atomic<size_t> used_{0};
+};
+
+// ---- kernel configuration ----------------------------------------------------
+
+struct KernelCfg {
+    int lps = 1;        // lanes per output site (1, 2, 4, 8)
+    int block = 256;    // threads per block
+    int rtile = 1;      // right-hand sides per link read
+    int tables = 0;     // 1: read iup/idn tables, 0: compute neighbours
+    int remap = 1;      // XCD-aware block order
+};
+
+// ---- gauge field -------------------------------------------------------------
+
+struct GaugeField {
+    int32_t id = 0;
+    int32_t dims[4] = {0, 0, 0, 0};
+    int32_t tap = 1;
+    Geom g{};
+    void *links[3] = {nullptr, nullptr, nullptr};  // per precision id: [2][8][9][Vh]
+    int32_t *nbr = nullptr;                          // [2][8][Vh]
+    std::atomic<int> users{0};                       // serving requests queued / running
+    std::map<uint64_t, KernelCfg> tuned;             // key: (prec, nrhs)
+    size_t bytes = 0;
+
+    const void *links_for(int prec, int out_parity) const
+    {
+        size_t per_parity = (size_t)8 * 9 * g.Vh * link_entry_bytes_of(prec);
+        return (const char *)links[prec] + (size_t)out_parity * per_parity;
+    }
+    const int32_t *nbr_for(int out_parity) const { return nbr + (size_t)out_parity * 8 * g.Vh; }
+};
+
+class Server;
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    Arena arena;
+    int num_cus = 256;
+    std::mutex mu;                                       // registry
+    std::map<int32_t, std::shared_ptr<GaugeField>> fields;
+    int32_t next_id = 1;
+    std::unique_ptr<Server> server;
+    // serving configuration
+    int slots_per_field = 16;
+    int epoch_iters = 16;
+    int queue_capacity = 4096;
+
+    std::shared_ptr<GaugeField> field(int32_t id);
+};
+
+// Current device guard: makes ctx->device current for the scope.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess)
+            prev = -1;
+        if (prev != dev)
+            (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0)
+            (void)hipSetDevice(prev);
+    }
+};
+
+// ---- functions implemented in the .hip files -------------------------------
+
+int gauge_prepare(Ctx *ctx, GaugeField *f, const double *links_dev, hipStream_t s);
+int launch_pack(const Geom &g, const double *lex, double *eo, int to_eo, hipStream_t s);
+int dslash_f64(Ctx *ctx, GaugeField *f, int out_parity, int64_t offset, int64_t count,
+               const double *in, double *out, int accumulate, hipStream_t s);
+KernelCfg tune_config(Ctx *ctx, GaugeField *f, int prec, int nrhs, hipStream_t s);
+
+int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs,
+                   const stag_cg_params *params, const double *const *b, double *const *x,
+                   double *const *y, hipStream_t s, stag_cg_info *infos);
+
+}  // namespace stag

@@ -1,0 +1,217 @@
+// Device-side types shared by the HIP kernels of libstagcg.
+//
+// Storage formats (all structure-of-arrays over the checkerboard index of one
+// parity, so consecutive lanes touch consecutive addresses):
+//   links   [parity][dir 8][entry 9][Vh] of a complex type; dir 0..3 are the
+//           forward links W_mu(x) = 1/2 eta_mu(x) s_fwd(x) U_mu(x), dir 4..7 the
+//           backward links B_mu(x) = -1/2 eta_mu(x) s_bwd(x) U_mu(x-mu)^dagger,
+//           both stored at the site x that uses them; s_fwd / s_bwd are the
+//           t-boundary signs.  With these, (D chi)(x) = sum_d L_d(x) chi(n_d(x)),
+//           n_d = x+mu (d < 4) or x-mu (d >= 4).
+//   spinors FP64 / FP32: [colour 3][Vh] of complex; FP16: one 16-byte record
+//           per site (3 half2 colours scaled by 1/norm, and the FP32 norm =
+//           largest |component| of the site).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "stagcg.h"
+
+namespace stag {
+
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+typedef float flt2 __attribute__((ext_vector_type(2)));
+typedef _Float16 hlf2 __attribute__((ext_vector_type(2)));
+
+struct __attribute__((aligned(16))) HalfSpinor {
+    hlf2 c[3];
+    float norm;
+};
+static_assert(sizeof(HalfSpinor) == 16, "half spinor record must be 16 bytes");
+
+// Lattice geometry of one parity in checkerboard order.
+struct Geom {
+    int32_t L[4];
+    int32_t Lxh;  // Lx / 2
+    int32_t Vh;   // sites per parity
+    int32_t sy;   // checkerboard stride of one step in y: Lxh
+    int32_t sz;   // ... in z: Lxh * Ly
+    int32_t st;   // ... in t: Lxh * Ly * Lz
+};
+
+inline Geom make_geom(const int32_t d[4])
+{
+    Geom g;
+    for (int i = 0; i < 4; ++i)
+        g.L[i] = d[i];
+    g.Lxh = d[0] / 2;
+    g.Vh = (int32_t)((int64_t)d[0] * d[1] * d[2] * d[3] / 2);
+    g.sy = g.Lxh;
+    g.sz = g.Lxh * d[1];
+    g.st = g.Lxh * d[1] * d[2];
+    return g;
+}
+
+struct SiteCoord {
+    int x, y, z, t;
+    int base;  // checkerboard index of (x = 0 or 1, y, z, t)
+};
+
+// Coordinates of checkerboard site s of parity p.
+__device__ __forceinline__ SiteCoord decode_site(const Geom &g, int p, int s)
+{
+    SiteCoord c;
+    const int xh = s % g.Lxh;
+    int r = s / g.Lxh;
+    c.y = r % g.L[1];
+    r /= g.L[1];
+    c.z = r % g.L[2];
+    c.t = r / g.L[2];
+    c.x = 2 * xh + ((p + c.y + c.z + c.t) & 1);
+    c.base = s - xh;
+    return c;
+}
+
+// Checkerboard index (in the other parity) of neighbour d of site s:
+// d = 0..3 forward in x,y,z,t; d = 4..7 backward.  Written with selects only,
+// so lanes of one wavefront that take different directions do not diverge.
+__device__ __forceinline__ int neighbour(const Geom &g, const SiteCoord &c, int s, int d)
+{
+    const int mu = d & 3;
+    const bool fwd = d < 4;
+    if (mu == 0) {
+        const int xn = fwd ? (c.x + 1 == g.L[0] ? 0 : c.x + 1) : (c.x == 0 ? g.L[0] - 1 : c.x - 1);
+        return c.base + (xn >> 1);
+    }
+    const int co = mu == 1 ? c.y : (mu == 2 ? c.z : c.t);
+    const int L = mu == 1 ? g.L[1] : (mu == 2 ? g.L[2] : g.L[3]);
+    const int st = mu == 1 ? g.sy : (mu == 2 ? g.sz : g.st);
+    if (fwd)
+        return co + 1 == L ? s - (L - 1) * st : s + st;
+    return co == 0 ? s + (L - 1) * st : s - st;
+}
+
+// ---- complex arithmetic in the compute type --------------------------------
+
+template <typename T> struct cplx {
+    T re, im;
+};
+
+template <typename T> __device__ __forceinline__ cplx<T> czero() { return {T(0), T(0)}; }
+
+// acc += a * b
+template <typename T>
+__device__ __forceinline__ void cmac(cplx<T> &acc, const cplx<T> &a, const cplx<T> &b)
+{
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(-a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(a.im, b.re, acc.im);
+}
+
+// ---- precision traits --------------------------------------------------------
+//
+// Each precision defines the link storage type, the spinor storage format used
+// for vectors that D gathers (p, ap), the compute type, and load/store helpers.
+
+struct PrecF64 {
+    using real = double;
+    using link_t = dbl2;
+    static constexpr int id = 0;
+    // spinor storage: [3][Vh] dbl2
+    using spin_store = dbl2;
+    static __device__ __forceinline__ cplx<real> load_link(const link_t *p)
+    {
+        dbl2 v = *p;
+        return {v.x, v.y};
+    }
+    static __device__ __forceinline__ void load_spinor(const void *base, int Vh, int s, cplx<real> out[3])
+    {
+        const dbl2 *b = (const dbl2 *)base;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            dbl2 v = b[(int64_t)c * Vh + s];
+            out[c] = {v.x, v.y};
+        }
+    }
+    static __device__ __forceinline__ void store_spinor(void *base, int Vh, int s, const cplx<real> v[3])
+    {
+        dbl2 *b = (dbl2 *)base;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            b[(int64_t)c * Vh + s] = dbl2{v[c].re, v[c].im};
+    }
+    static constexpr size_t spinor_bytes = 48;  // per site
+    static constexpr size_t link_bytes = 16;     // per complex entry
+};
+
+struct PrecF32 {
+    using real = float;
+    using link_t = flt2;
+    static constexpr int id = 1;
+    static __device__ __forceinline__ cplx<real> load_link(const link_t *p)
+    {
+        flt2 v = *p;
+        return {v.x, v.y};
+    }
+    static __device__ __forceinline__ void load_spinor(const void *base, int Vh, int s, cplx<real> out[3])
+    {
+        const flt2 *b = (const flt2 *)base;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            flt2 v = b[(int64_t)c * Vh + s];
+            out[c] = {v.x, v.y};
+        }
+    }
+    static __device__ __forceinline__ void store_spinor(void *base, int Vh, int s, const cplx<real> v[3])
+    {
+        flt2 *b = (flt2 *)base;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            b[(int64_t)c * Vh + s] = flt2{v[c].re, v[c].im};
+    }
+    static constexpr size_t spinor_bytes = 24;
+    static constexpr size_t link_bytes = 8;
+};
+
+struct PrecF16 {
+    using real = float;
+    using link_t = hlf2;
+    static constexpr int id = 2;
+    static __device__ __forceinline__ cplx<real> load_link(const link_t *p)
+    {
+        hlf2 v = *p;
+        return {(float)v.x, (float)v.y};
+    }
+    static __device__ __forceinline__ void load_spinor(const void *base, int, int s, cplx<real> out[3])
+    {
+        const HalfSpinor h = ((const HalfSpinor *)base)[s];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            out[c] = {(float)h.c[c].x * h.norm, (float)h.c[c].y * h.norm};
+    }
+    static __device__ __forceinline__ void store_spinor(void *base, int, int s, const cplx<real> v[3])
+    {
+        float m = 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+        HalfSpinor h;
+        const float inv = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            h.c[c] = hlf2{(_Float16)(v[c].re * inv), (_Float16)(v[c].im * inv)};
+        h.norm = m;
+        ((HalfSpinor *)base)[s] = h;
+    }
+    // value as it will be read back after store_spinor (for norms of stored vectors)
+    static constexpr size_t spinor_bytes = 16;
+    static constexpr size_t link_bytes = 4;
+};
+
+// Bytes per site of one stored spinor / one link field entry, per precision id.
+inline size_t spinor_bytes_of(int prec) { return prec == 0 ? 48 : prec == 1 ? 24 : 16; }
+inline size_t link_entry_bytes_of(int prec) { return prec == 0 ? 16 : prec == 1 ? 8 : 4; }
+
+}  // namespace stag
