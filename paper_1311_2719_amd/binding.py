@@ -318,6 +318,8 @@ class Context:
         rc = self.lib.stag_poll(self.h, ctypes.c_uint64(ticket), ctypes.byref(info))
         if rc == PENDING:
             return None
+        if rc in (ENOENT, EINVAL):
+            _check(rc, "stag_poll")
         d = info.as_dict()
         d["rc"] = rc
         return d
@@ -325,6 +327,8 @@ class Context:
     def wait(self, ticket: int):
         info = CGInfo()
         rc = self.lib.stag_wait(self.h, ctypes.c_uint64(ticket), ctypes.byref(info))
+        if rc in (ENOENT, EINVAL):
+            _check(rc, "stag_wait")
         d = info.as_dict()
         d["rc"] = rc
         return d

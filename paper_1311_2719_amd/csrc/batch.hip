@@ -1,6 +1,8 @@
 // Batch workspace and the per-iteration launch sequence; the blocking
 // (batched) CG solve built on it.
+#include <algorithm>
 #include <chrono>
+#include <map>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -20,6 +22,12 @@ Batch::Batch(Ctx *ctx, std::shared_ptr<GaugeField> f, int prec, int slots, hipSt
 
 Batch::~Batch()
 {
+    if (s_ || mem_)
+        (void)hipStreamSynchronize(s_);  // no kernel may still use the workspace
+    for (auto &kv : graphs_)
+        (void)hipGraphExecDestroy(kv.second);
+    if (cap_stream_)
+        (void)hipStreamDestroy(cap_stream_);
     if (snap_ev_)
         (void)hipEventDestroy(snap_ev_);
     if (stage_ev_)
@@ -34,14 +42,13 @@ size_t Batch::workspace_bytes(const Geom &g, int prec, int slots, int pstride)
 {
     const size_t nsys = 2 * (size_t)slots, Vh = g.Vh;
     size_t b = 0;
-    b += align256(nsys * Vh * spinor_bytes_of(prec)) * 2;       // p, ap
+    b += align256(nsys * Vh * spinor_bytes_of(prec)) * 3;       // p (two buffers), ap
     b += align256(nsys * 3 * Vh * (prec == 0 ? 16 : 8));         // r
     b += prec == 0 ? 0 : align256(nsys * 3 * Vh * 8);            // x_lo
     b += align256(nsys * 3 * Vh * 16);                           // tmp
     b += align256(nsys * sizeof(void *)) * 2;                    // pointer tables
     b += align256(nsys * sizeof(SysState));
     b += align256(nsys * (size_t)pstride * 2 * sizeof(double));  // partials
-    b += align256(nsys * sizeof(unsigned));
     return b;
 }
 
@@ -54,6 +61,7 @@ int Batch::create()
         cfg_.rtile = 1;
     pstride_ = std::max(std::max(blocks_for(g.Vh, cfg_.lps, cfg_.block), blocks_for(g.Vh, cfg64_.lps, cfg64_.block)),
                         blocks_for(g.Vh, 1, 256));
+    pstride_ = (pstride_ + 63) & ~63;
     bytes_ = workspace_bytes(g, prec_, S_, pstride_);
     mem_ = ctx_->arena.alloc(bytes_);
     if (!mem_)
@@ -66,7 +74,8 @@ int Batch::create()
         c += align256(n);
         return (void *)r;
     };
-    p_ = take(nsys * Vh * spinor_bytes_of(prec_));
+    p_[0] = take(nsys * Vh * spinor_bytes_of(prec_));
+    p_[1] = take(nsys * Vh * spinor_bytes_of(prec_));
     ap_ = take(nsys * Vh * spinor_bytes_of(prec_));
     r_ = take(nsys * 3 * Vh * (prec_ == 0 ? 16 : 8));
     xlo_ = prec_ == 0 ? nullptr : (flt2 *)take(nsys * 3 * Vh * 8);
@@ -75,7 +84,6 @@ int Batch::create()
     b_d_ = (const dbl2 **)take(nsys * sizeof(void *));
     st_d_ = (SysState *)take(nsys * sizeof(SysState));
     partials_ = (double *)take(nsys * (size_t)pstride_ * 2 * sizeof(double));
-    counters_ = (unsigned *)take(nsys * sizeof(unsigned));
 
     const size_t host_bytes = 2 * nsys * sizeof(SysState) + 2 * nsys * sizeof(void *);
     STAG_HIP_CHECK(hipHostMalloc((void **)&stage_, host_bytes, hipHostMallocDefault));
@@ -83,11 +91,14 @@ int Batch::create()
     xhi_h_ = (dbl2 **)(snap_ + nsys);
     b_h_ = (const dbl2 **)(xhi_h_ + nsys);
     memset(stage_, 0, host_bytes);
+    if (const char *e = getenv("STAG_GRAPHS"))
+        use_graphs_ = e[0] != '0';
+    if (use_graphs_)
+        STAG_HIP_CHECK(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
     STAG_HIP_CHECK(hipEventCreateWithFlags(&snap_ev_, hipEventDisableTiming));
     STAG_HIP_CHECK(hipEventCreateWithFlags(&stage_ev_, hipEventDisableTiming));
-    // every system starts idle; counters start at zero
+    // every system starts idle
     STAG_HIP_CHECK(hipMemcpyAsync(st_d_, stage_, nsys * sizeof(SysState), hipMemcpyHostToDevice, s_));
-    STAG_HIP_CHECK(hipMemsetAsync(counters_, 0, nsys * sizeof(unsigned), s_));
     STAG_HIP_CHECK(hipMemcpyAsync(xhi_d_, xhi_h_, nsys * sizeof(void *), hipMemcpyHostToDevice, s_));
     STAG_HIP_CHECK(hipMemcpyAsync(b_d_, b_h_, nsys * sizeof(void *), hipMemcpyHostToDevice, s_));
     STAG_HIP_CHECK(hipEventRecord(stage_ev_, s_));
@@ -134,9 +145,23 @@ int Batch::upload_and_init(const std::vector<int> &systems)
     const CgLaunchTable &t = cg_table(prec_);
     dim3 grid((unsigned)blocks_for(f_->g.Vh, 1, 256), (unsigned)nsys());
     hipError_t e = t.init(grid, dim3(256), s_, a);
+    if (e == hipSuccess)
+        e = launch_fin(FIN_INIT, (int)grid.x, a, s_);
     if (e != hipSuccess)
         return set_error(STAG_EHIP, "init launch failed: %s", hipGetErrorString(e));
     return STAG_OK;
+}
+
+hipError_t Batch::launch_fin(int role, int nblk, const CgArgs &a, hipStream_t st)
+{
+    dim3 grid((unsigned)nsys()), block(256);
+    switch (role) {
+    case FIN_INIT: hipLaunchKernelGGL((k_cg_fin<FIN_INIT>), grid, block, 0, st, a, nblk); break;
+    case FIN_AP: hipLaunchKernelGGL((k_cg_fin<FIN_AP>), grid, block, 0, st, a, nblk); break;
+    case FIN_UPDATE: hipLaunchKernelGGL((k_cg_fin<FIN_UPDATE>), grid, block, 0, st, a, nblk); break;
+    default: hipLaunchKernelGGL((k_cg_fin<FIN_RU>), grid, block, 0, st, a, nblk); break;
+    }
+    return hipGetLastError();
 }
 
 CgArgs Batch::args() const
@@ -149,7 +174,8 @@ CgArgs Batch::args() const
         a.links64[par] = (const dbl2 *)f_->links_for(0, par);
         a.nbr[par] = cfg_.tables ? f_->nbr_for(par) : nullptr;
     }
-    a.p = p_;
+    a.p[0] = p_[0];
+    a.p[1] = p_[1];
     a.ap = ap_;
     a.r = r_;
     a.xlo = xlo_;
@@ -158,14 +184,13 @@ CgArgs Batch::args() const
     a.b = b_d_;
     a.st = st_d_;
     a.partials = partials_;
-    a.counters = counters_;
     a.S = S_;
     a.pstride = pstride_;
     a.remap = cfg_.remap;
     return a;
 }
 
-int Batch::launch_iter(bool with_ru)
+int Batch::launch_iter(bool with_ru, hipStream_t st)
 {
     const Geom &g = f_->g;
     const CgLaunchTable &t = cg_table(prec_);
@@ -173,35 +198,67 @@ int Batch::launch_iter(bool with_ru)
     const int R = cfg_.rtile;
     dim3 grid_h((unsigned)blocks_for(g.Vh, cfg_.lps, cfg_.block), (unsigned)(nsys() / R));
     dim3 blk(cfg_.block);
-    hipError_t e = t.ap(cfg_.lps, R, grid_h, blk, s_, a);
+    hipError_t e = t.ap(cfg_.lps, R, grid_h, blk, st, a);
     if (e == hipSuccess)
-        e = t.update(cfg_.lps, R, grid_h, blk, s_, a);
+        e = launch_fin(FIN_AP, (int)grid_h.x, a, st);
+    if (e == hipSuccess)
+        e = t.update(cfg_.lps, R, grid_h, blk, st, a);
+    if (e == hipSuccess)
+        e = launch_fin(FIN_UPDATE, (int)grid_h.x, a, st);
     if (e == hipSuccess && with_ru) {
         CgArgs a64 = a;
         a64.nbr[0] = cfg64_.tables ? f_->nbr_for(0) : nullptr;
         a64.nbr[1] = cfg64_.tables ? f_->nbr_for(1) : nullptr;
         a64.remap = cfg64_.remap;
         dim3 grid64((unsigned)blocks_for(g.Vh, cfg64_.lps, cfg64_.block), (unsigned)nsys());
-        e = launch_ru_dx(cfg64_.lps, prec_ != 0, grid64, dim3(cfg64_.block), s_, a64);
+        e = launch_ru_dx(cfg64_.lps, prec_ != 0, grid64, dim3(cfg64_.block), st, a64);
         if (e == hipSuccess)
-            e = t.ru_residual(cfg64_.lps, grid64, dim3(cfg64_.block), s_, a64);
-    }
-    if (e == hipSuccess) {
-        dim3 grid_v((unsigned)blocks_for(g.Vh, 1, 256), (unsigned)nsys());
-        e = t.direction(grid_v, dim3(256), s_, a);
+            e = t.ru_residual(cfg64_.lps, grid64, dim3(cfg64_.block), st, a64);
+        if (e == hipSuccess)
+            e = launch_fin(FIN_RU, (int)grid64.x, a64, st);
     }
     if (e != hipSuccess)
         return set_error(STAG_EHIP, "CG kernel launch failed: %s", hipGetErrorString(e));
     return STAG_OK;
 }
 
-int Batch::enqueue_epoch(int iters, bool ru_every_iter)
+int Batch::enqueue_epoch(int iters, int ru_interval)
 {
-    for (int k = 0; k < iters; ++k) {
-        int rc = launch_iter(ru_every_iter || k == iters - 1);
-        if (rc != STAG_OK)
-            return rc;
+    if (!use_graphs_) {
+        for (int k = 0; k < iters; ++k) {
+            int rc = launch_iter((k + 1) % ru_interval == 0 || k == iters - 1, s_);
+            if (rc != STAG_OK)
+                return rc;
+        }
+        return STAG_OK;
     }
+    // The kernel arguments of an epoch depend only on this workspace, so an
+    // epoch of a given length is recorded once and replayed: the launches of
+    // all its kernels cost one graph launch on the host.
+    const auto key = std::make_pair(iters, std::min(ru_interval, iters + 1));
+    auto it = graphs_.find(key);
+    if (it == graphs_.end()) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        STAG_HIP_CHECK(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
+        int rc = STAG_OK;
+        for (int k = 0; k < iters && rc == STAG_OK; ++k)
+            rc = launch_iter((k + 1) % ru_interval == 0 || k == iters - 1, cap_stream_);
+        hipError_t e = hipStreamEndCapture(cap_stream_, &graph);
+        if (rc != STAG_OK) {
+            if (graph)
+                (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess)
+            return set_error(STAG_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess)
+            return set_error(STAG_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+        it = graphs_.emplace(key, exec).first;
+    }
+    STAG_HIP_CHECK(hipGraphLaunch(it->second, s_));
     return STAG_OK;
 }
 
@@ -275,6 +332,89 @@ void fill_info(const Batch &B, int slot, stag_cg_info *info)
     info->true_rel_resid = bb > 0 ? std::sqrt(trr / bb) : std::sqrt(trr);
 }
 
+int acquire_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int prec, int slots, hipStream_t s,
+                  std::shared_ptr<Batch> &out)
+{
+    {
+        std::lock_guard<std::mutex> lk(ctx->cache_mu);
+        for (auto it = ctx->batch_cache.begin(); it != ctx->batch_cache.end(); ++it) {
+            Batch &b = **it;
+            if (b.field() == f.get() && b.prec() == prec && b.slots() == slots && b.stream() == s) {
+                out = *it;
+                ctx->batch_cache.erase(it);
+                return STAG_OK;
+            }
+        }
+    }
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        auto b = std::make_shared<Batch>(ctx, f, prec, slots, s);
+        int rc = b->create();
+        if (rc == STAG_OK) {
+            out = b;
+            return STAG_OK;
+        }
+        b.reset();
+        if (rc != STAG_ENOMEM || attempt == 1)
+            return rc;
+        drop_cached_batches(ctx, -1);
+    }
+    return STAG_ENOMEM;
+}
+
+void release_batch(Ctx *ctx, std::shared_ptr<Batch> b)
+{
+    if (!b)
+        return;
+    std::lock_guard<std::mutex> lk(ctx->cache_mu);
+    ctx->batch_cache.push_back(std::move(b));
+    if (ctx->batch_cache.size() > 8)
+        ctx->batch_cache.erase(ctx->batch_cache.begin());
+}
+
+void drop_cached_batches(Ctx *ctx, int32_t gauge_id)
+{
+    std::vector<std::shared_ptr<Batch>> dead;
+    {
+        std::lock_guard<std::mutex> lk(ctx->cache_mu);
+        for (auto it = ctx->batch_cache.begin(); it != ctx->batch_cache.end();) {
+            if (gauge_id < 0 || (*it)->field()->id == gauge_id) {
+                dead.push_back(*it);
+                it = ctx->batch_cache.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+    for (auto &b : dead)
+        (void)hipStreamSynchronize(b->stream());
+    dead.clear();
+}
+
+// Iterations left for the slowest running system, from the decrease of its
+// residual since the previous snapshot (large when unknown).
+static int estimate_remaining(const Batch &B, std::vector<std::pair<int, double>> &prev)
+{
+    double worst = 0;
+    bool known = true;
+    for (int j = 0; j < B.nsys(); ++j) {
+        const SysState &st = B.state(j);
+        if (st.phase != PH_RUN) {
+            prev[j] = {st.iters, st.rr};
+            continue;
+        }
+        const int di = st.iters - prev[j].first;
+        if (di > 0 && st.rr > 0 && prev[j].second > st.rr && st.stop2 > 0) {
+            const double rate = std::log(prev[j].second / st.rr) / di;
+            const double rem = std::log(st.rr / st.stop2) / rate;
+            worst = std::max(worst, rem);
+        } else {
+            known = false;
+        }
+        prev[j] = {st.iters, st.rr};
+    }
+    return known ? (int)std::ceil(worst) : 1 << 20;
+}
+
 int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs, const stag_cg_params *params,
                    const double *const *b, double *const *x, double *const *y, hipStream_t s, stag_cg_info *infos)
 {
@@ -287,10 +427,15 @@ int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs, con
         if (!b[i] || !x[i])
             return set_error(STAG_EINVAL, "b and x must be device pointers");
     }
-    Batch B(ctx, f, prec, nrhs, s);
-    int rc = B.create();
+    std::shared_ptr<Batch> Bp;
+    int rc = acquire_batch(ctx, f, prec, nrhs, s, Bp);
     if (rc != STAG_OK)
         return rc;
+    Batch &B = *Bp;
+    struct SyncOnExit {  // on an error return, drain the stream before the workspace goes
+        hipStream_t s;
+        ~SyncOnExit() { (void)hipStreamSynchronize(s); }
+    } drain{s};
     const size_t half = (size_t)3 * f->g.Vh * 2;  // doubles per parity half
     std::vector<int> systems;
     int max_iter = 0;
@@ -305,18 +450,25 @@ int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs, con
     }
     if ((rc = B.upload_and_init(systems)) != STAG_OK)
         return rc;
-    const bool mixed = prec != STAG_FP64;
-    int E = 16;
+    // residual recomputations are requested on the device; their kernels run
+    // every ru_interval iterations (mixed precision) or at the end of an
+    // epoch (FP64, where they only serve the final check)
+    int ru_interval = prec != STAG_FP64 ? 2 : 1 << 30;
+    if (const char *e = getenv("STAG_RU_INTERVAL"))
+        ru_interval = std::max(1, atoi(e));
+    int E = 8, Emax = 64;
     if (const char *e = getenv("STAG_EPOCH"))
-        E = std::max(1, atoi(e));
+        E = Emax = std::max(1, atoi(e));
+    std::vector<std::pair<int, double>> prev(B.nsys(), {0, 0.0});
     // pipelined: epoch n+1 is queued before the state after epoch n is read
-    if ((rc = B.enqueue_epoch(E, mixed)) != STAG_OK || (rc = B.enqueue_snapshot()) != STAG_OK)
+    if ((rc = B.enqueue_epoch(E, ru_interval)) != STAG_OK || (rc = B.enqueue_snapshot()) != STAG_OK)
         return rc;
-    const int64_t limit = (int64_t)(max_iter + 1) * (int64_t)(2 + params[0].max_restarts) / E + 64;
+    int64_t budget = (int64_t)(max_iter + 1) * (int64_t)(2 + params[0].max_restarts) + 4096;
     bool done = false;
-    for (int64_t ep = 0; ep < limit && !done; ++ep) {
-        if ((rc = B.enqueue_epoch(E, mixed)) != STAG_OK)
+    while (!done && budget > 0) {
+        if ((rc = B.enqueue_epoch(E, ru_interval)) != STAG_OK)
             return rc;
+        budget -= E;
         if ((rc = B.wait_snapshot()) != STAG_OK)
             return rc;
         done = true;
@@ -325,8 +477,16 @@ int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs, con
             if (ph == PH_RUN || ph == PH_INIT)
                 done = false;
         }
-        if (!done && (rc = B.enqueue_snapshot()) != STAG_OK)
-            return rc;
+        if (!done) {
+            const int rem = estimate_remaining(B, prev);
+            E = 2;
+            while (E * 2 <= std::min(Emax, rem / 2))
+                E *= 2;
+            if (getenv("STAG_EPOCH"))
+                E = Emax;
+            if ((rc = B.enqueue_snapshot()) != STAG_OK)
+                return rc;
+        }
     }
     if ((rc = B.enqueue_snapshot()) != STAG_OK || (rc = B.wait_snapshot()) != STAG_OK)
         return rc;
@@ -353,6 +513,7 @@ int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs, con
             infos[i] = inf;
         first_err = worse(first_err, inf.status);
     }
+    release_batch(ctx, std::move(Bp));
     if (first_err != STAG_OK)
         return set_error(first_err, "CG did not converge (status %d)", first_err);
     return STAG_OK;

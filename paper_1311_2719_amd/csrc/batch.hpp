@@ -32,9 +32,9 @@ public:
     void stage_system(int j, const stag_cg_params &p, const double *b_half, double *x_half);
     // Copy staged systems [j0, j0 + n) to the device and run the init kernel.
     int upload_and_init(const std::vector<int> &systems);
-    // Enqueue `iters` CG iterations; residual recomputation after every
-    // iteration when ru_every_iter, else only after the last one.
-    int enqueue_epoch(int iters, bool ru_every_iter);
+    // Enqueue `iters` CG iterations; the residual-recomputation kernels run
+    // after every ru_interval-th iteration and after the last one.
+    int enqueue_epoch(int iters, int ru_interval);
     // Enqueue a copy of the device state into the host snapshot and record an
     // event; wait_snapshot blocks until it has arrived.
     int enqueue_snapshot();
@@ -43,7 +43,8 @@ public:
     const SysState &state(int j) const { return snap_[j]; }
 
 private:
-    int launch_iter(bool with_ru);
+    int launch_iter(bool with_ru, hipStream_t st);
+    hipError_t launch_fin(int role, int nblk, const CgArgs &a, hipStream_t st);
     CgArgs args() const;
 
     Ctx *ctx_;
@@ -55,14 +56,13 @@ private:
     void *mem_ = nullptr;
     size_t bytes_ = 0;
     // device views into mem_
-    void *p_ = nullptr, *ap_ = nullptr, *r_ = nullptr;
+    void *p_[2] = {nullptr, nullptr}, *ap_ = nullptr, *r_ = nullptr;
     flt2 *xlo_ = nullptr;
     dbl2 *tmp_ = nullptr;
     dbl2 **xhi_d_ = nullptr;
     const dbl2 **b_d_ = nullptr;
     SysState *st_d_ = nullptr;
     double *partials_ = nullptr;
-    unsigned *counters_ = nullptr;
     // pinned host memory
     SysState *stage_ = nullptr;   // [nsys] staged initial states
     SysState *snap_ = nullptr;    // [nsys] last snapshot
@@ -70,6 +70,10 @@ private:
     const dbl2 **b_h_ = nullptr;
     hipEvent_t snap_ev_ = nullptr, stage_ev_ = nullptr;
     bool stage_busy_ = false;
+    // epochs recorded once as HIP graphs (kernel nodes only) and replayed
+    bool use_graphs_ = true;
+    hipStream_t cap_stream_ = nullptr;
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs_;
 };
 
 }  // namespace stag

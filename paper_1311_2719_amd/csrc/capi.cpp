@@ -79,6 +79,7 @@ int stag_destroy(stag_ctx *ctx)
     Ctx *c = reinterpret_cast<Ctx *>(ctx);
     DeviceGuard dg(c->device);
     c->server.reset();
+    drop_cached_batches(c, -1);
     (void)hipDeviceSynchronize();
     {
         std::lock_guard<std::mutex> lk(c->mu);
@@ -188,6 +189,7 @@ int stag_free_gauge(stag_ctx *ctx, int32_t gauge_id)
     }
     if (c->server)
         c->server->drop_field(gauge_id);
+    drop_cached_batches(c, gauge_id);
     (void)hipDeviceSynchronize();
     for (int p = 0; p < 3; ++p)
         c->arena.release(f->links[p]);

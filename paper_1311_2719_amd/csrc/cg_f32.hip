@@ -37,16 +37,16 @@ hipError_t update(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const Cg
 }
 
 hipError_t probe(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const Geom &g, const void *links,
-                 const int32_t *nbr, int pout, const void *in, void *out, int remap)
+                 const int32_t *nbr, const void *in, void *out, int remap)
 {
     switch (R) {
-    case 1: return RLaunch<P, 1>::probe(lps, grid, block, s, g, links, nbr, pout, in, out, remap);
-    case 2: return RLaunch<P, 2>::probe(lps, grid, block, s, g, links, nbr, pout, in, out, remap);
-    case 3: return RLaunch<P, 3>::probe(lps, grid, block, s, g, links, nbr, pout, in, out, remap);
-    case 4: return RLaunch<P, 4>::probe(lps, grid, block, s, g, links, nbr, pout, in, out, remap);
-    case 6: return RLaunch<P, 6>::probe(lps, grid, block, s, g, links, nbr, pout, in, out, remap);
-    case 8: return RLaunch<P, 8>::probe(lps, grid, block, s, g, links, nbr, pout, in, out, remap);
-    case 12: return RLaunch<P, 12>::probe(lps, grid, block, s, g, links, nbr, pout, in, out, remap);
+    case 1: return RLaunch<P, 1>::probe(lps, grid, block, s, g, links, nbr, in, out, remap);
+    case 2: return RLaunch<P, 2>::probe(lps, grid, block, s, g, links, nbr, in, out, remap);
+    case 3: return RLaunch<P, 3>::probe(lps, grid, block, s, g, links, nbr, in, out, remap);
+    case 4: return RLaunch<P, 4>::probe(lps, grid, block, s, g, links, nbr, in, out, remap);
+    case 6: return RLaunch<P, 6>::probe(lps, grid, block, s, g, links, nbr, in, out, remap);
+    case 8: return RLaunch<P, 8>::probe(lps, grid, block, s, g, links, nbr, in, out, remap);
+    case 12: return RLaunch<P, 12>::probe(lps, grid, block, s, g, links, nbr, in, out, remap);
     default: return hipErrorInvalidValue;
     }
 }
@@ -55,7 +55,7 @@ hipError_t probe(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const Geo
 
 const CgLaunchTable &cg_table_f32()
 {
-    static const CgLaunchTable t = {ap, update, PLaunch<P>::direction, PLaunch<P>::init, PLaunch<P>::ru_residual,
+    static const CgLaunchTable t = {ap, update, PLaunch<P>::init, PLaunch<P>::ru_residual,
                                     probe, kTiles, (int)(sizeof(kTiles) / sizeof(kTiles[0]))};
     return t;
 }

@@ -2,18 +2,23 @@
 // batched over systems that share a gauge field.
 //
 // The iteration is the loop of the paper's Sec. 4 with the mass explicit,
-// split into three kernels so that no vector is re-read needlessly and every
+// rearranged into two kernels so that every vector is streamed once and every
 // scalar stays on the device:
-//   K1  ap = D p (other parity), <ap,ap>;           last block: alpha = rr / (m^2 <p,p> + <ap,ap>)
-//   K2  Ap = m^2 p - D ap; x += alpha p; r -= alpha Ap; <r,r>   (Ap is never stored)
-//                                                    last block: stopping test, beta
-//   K3  p = r + beta p, <p,p>
-// Reliable updates (mixed precision, and the final FP64 check in every mode):
+//   K1  p' = r + beta p (formed on the fly at every gathered neighbour, and
+//       stored once at the partner site), ap = D p' on the other parity,
+//       <ap,ap> and <p',p'>;          finalize: alpha = rr / (m^2 <p',p'> + <ap,ap>)
+//   K2  Ap = m^2 p' - D ap; x += alpha p'; r -= alpha Ap; <r,r>   (Ap never stored)
+//                                     finalize: stopping test, beta = rn / rr
+// p and p' alternate between two buffers per system (pcur).
+// FP64 residual recomputation (reliable updates in mixed precision, and the
+// final true-residual check in every mode):
 //   RU2 t = D x on the other parity in FP64 (x = x_hi + x_lo)
 //   RU3 x_hi += x_lo, x_lo = 0, r = b - m^2 x_hi + D t in FP64, <r,r>
-// Each kernel's per-block partial sums are reduced by the last block to finish
-// (ticket counter), which also evaluates the scalar recurrences of the
-// systems: the host never reads a scalar inside the loop.
+// Each main kernel writes per-block partial sums; a one-block-per-system
+// finalize kernel (k_cg_fin) launched right after it reduces them in a fixed
+// order and evaluates the scalar recurrences and the stopping test of its
+// system, so the host never reads a scalar inside the loop and no cross-block
+// synchronisation (fence or atomic) is needed inside a kernel.
 //
 // Systems: nsys = 2*S, system j has parity j / S (its x, r, p live on that
 // parity; ap and t on the other).  A tile is R systems of one parity that are
@@ -49,7 +54,8 @@ struct SysState {
     int32_t restarts;
     int32_t max_restarts;
     int32_t mixed;
-    int32_t pad1[2];
+    int32_t pcur;        // which of the two p buffers holds the current direction
+    int32_t pad1;
 };
 
 struct CgArgs {
@@ -57,7 +63,7 @@ struct CgArgs {
     const void *links[2];      // links of the working precision, per output parity
     const dbl2 *links64[2];    // FP64 links, per output parity
     const int32_t *nbr[2];     // neighbour tables per output parity, or null
-    void *p;                   // [nsys] stored spinors (working precision)
+    void *p[2];                // [nsys] stored search directions (working precision), two buffers
     void *ap;                  // [nsys] stored spinors (working precision)
     void *r;                   // [nsys][3][Vh] complex of the compute type
     flt2 *xlo;                 // [nsys][3][Vh] (mixed precision only)
@@ -65,8 +71,7 @@ struct CgArgs {
     dbl2 *const *xhi;          // [nsys] parity half of the caller's x
     const dbl2 *const *b;      // [nsys] parity half of the caller's b
     SysState *st;              // [nsys]
-    double *partials;          // [nsys][pstride]
-    unsigned *counters;        // [nsys]
+    double *partials;          // [nsys][2][pstride]
     int S;                     // systems per parity
     int pstride;
     int remap;
@@ -83,8 +88,8 @@ template <class P> __device__ __forceinline__ void *spin_at(void *base, int j, i
 
 template <class P> __device__ __forceinline__ cplx<typename P::real> load_colour(const void *base, int Vh, int s, int c)
 {
-    cplx<typename P::real> v[3];
     if constexpr (P::id == 2) {
+        cplx<typename P::real> v[3];
         P::load_spinor(base, Vh, s, v);
         return v[c];
     } else {
@@ -103,62 +108,104 @@ __device__ __forceinline__ void tile_of(const CgArgs &a, int tile, int R, int &p
 
 __device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v < INFINITY; }
 
-// ---- K1: ap = D p -----------------------------------------------------------
+__device__ __forceinline__ double *partial_slot(const CgArgs &a, int j, int which)
+{
+    return a.partials + ((size_t)j * 2 + which) * a.pstride;
+}
+
+// ---- K1: p' = r + beta p, ap = D p' ---------------------------------------------
 
 template <class P, int LPS, int R>
 __global__ void __launch_bounds__(256) k_cg_ap(CgArgs a)
 {
     using real = typename P::real;
-    __shared__ double lds[R * 4];
-    __shared__ int flag;
+    using v2 = typename vec2_of<real>::type;
+    __shared__ double lds[2 * R * 4];
     int par, j0;
     tile_of(a, blockIdx.y, R, par, j0);
     const int pout = 1 - par;
     bool act[R];
+    real beta[R];
+    int pc[R];
     bool any = false;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const SysState &st = a.st[j0 + r];
         act[r] = st.phase == PH_RUN && !st.ru_pending;
+        beta[r] = (real)st.beta;
+        pc[r] = st.pcur;
         any |= act[r];
     }
     if (!any)
         return;
     const int Vh = a.g.Vh;
-    const int lb = logical_block(blockIdx.x, gridDim.x, a.remap);
-    const int gt = lb * blockDim.x + threadIdx.x;
-    const int s = gt / LPS, sub = gt % LPS;
-    double nrm[R];
+    int s, sub;
+    site_of_thread<LPS>(logical_block(blockIdx.x, gridDim.x, a.remap) * blockDim.x + threadIdx.x, s, sub);
+    double nrm[2 * R];
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+    for (int r = 0; r < 2 * R; ++r)
         nrm[r] = 0.0;
     if (s < Vh) {
-        const void *in[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            in[r] = spin_at<P>(a.p, j0 + r, Vh);
         cplx<real> acc[R][3];
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 acc[r][c] = czero<real>();
-        hop_accumulate<P, LPS, R>(a.g, (const typename P::link_t *)a.links[pout], a.nbr[pout], pout, s, sub,
-                                  in, act, acc);
+        auto load = [&](int r, int n, cplx<real> *chi) {
+            const int j = j0 + r;
+            const v2 *rv = (const v2 *)a.r + (size_t)j * 3 * Vh;
+            cplx<real> pv[3];
+            P::load_spinor(spin_at<P>(a.p[pc[r]], j, Vh), Vh, n, pv);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const v2 t = rv[(int64_t)c * Vh + n];
+                chi[c].re = fma(beta[r], pv[c].re, t.x);
+                chi[c].im = fma(beta[r], pv[c].im, t.y);
+            }
+        };
+        hop_accumulate<P, LPS, R>(a.g, (const typename P::link_t *)a.links[pout], a.nbr[pout], pout, s, sub, act,
+                                  acc, load);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (!act[r])
                 continue;
-            void *out = spin_at<P>(a.ap, j0 + r, Vh);
+            const int j = j0 + r;
+            void *out = spin_at<P>(a.ap, j, Vh);
+            const v2 *rv = (const v2 *)a.r + (size_t)j * 3 * Vh;
+            const void *pold = spin_at<P>(a.p[pc[r]], j, Vh);
+            void *pnew = spin_at<P>(a.p[pc[r] ^ 1], j, Vh);
             if constexpr (P::id == 2) {
-                if (sub == 0)
+                if (sub == 0) {
                     P::store_spinor(out, Vh, s, acc[r]);
-            } else {
-                using v2 = typename vec2_of<real>::type;
+                    // the new direction at the partner site (same index, parity par)
+                    cplx<real> pv[3];
+                    P::load_spinor(pold, Vh, s, pv);
 #pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    if (owns_colour<LPS>(sub, c))
-                        ((v2 *)out)[(int64_t)c * Vh + s] = v2{acc[r][c].re, acc[r][c].im};
+                    for (int c = 0; c < 3; ++c) {
+                        const v2 t = rv[(int64_t)c * Vh + s];
+                        pv[c].re = fma(beta[r], pv[c].re, t.x);
+                        pv[c].im = fma(beta[r], pv[c].im, t.y);
+                    }
+                    P::store_spinor(pnew, Vh, s, pv);
+                    P::load_spinor(pnew, Vh, s, pv);  // the norm of the value D will read
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        nrm[R + r] += (double)pv[c].re * pv[c].re + (double)pv[c].im * pv[c].im;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if (!owns_colour<LPS>(sub, c))
+                        continue;
+                    const int64_t o = (int64_t)c * Vh + s;
+                    ((v2 *)out)[o] = v2{acc[r][c].re, acc[r][c].im};
+                    const v2 po = ((const v2 *)pold)[o];
+                    const v2 t = rv[o];
+                    const v2 pn = v2{fma(beta[r], po.x, t.x), fma(beta[r], po.y, t.y)};
+                    ((v2 *)pnew)[o] = pn;
+                    nrm[R + r] += (double)pn.x * pn.x + (double)pn.y * pn.y;
+                }
             }
             if (sub == 0) {
 #pragma unroll
@@ -168,27 +215,9 @@ __global__ void __launch_bounds__(256) k_cg_ap(CgArgs a)
         }
     }
     double tot;
-    block_sum_multi<R>(nrm, lds, tot);
-    if (threadIdx.x < R)
-        publish_partial(a.partials + (size_t)(j0 + threadIdx.x) * a.pstride + blockIdx.x, tot);
-    if (!arrive_last(a.counters + blockIdx.y, gridDim.x, &flag))
-        return;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (!act[r])
-            continue;
-        const double apap = reduce_partials(a.partials + (size_t)(j0 + r) * a.pstride, gridDim.x, lds);
-        if (threadIdx.x == 0) {
-            SysState &st = a.st[j0 + r];
-            const double pap = st.mass2 * st.pp + apap;
-            if (!finite_pos(pap)) {
-                st.ru_pending = 1;
-                st.stopping = STAG_EBREAKDOWN;
-            } else {
-                st.alpha = st.rr / pap;
-            }
-        }
-    }
+    block_sum_multi<2 * R>(nrm, lds, tot);
+    if (threadIdx.x < 2 * R)
+        partial_slot(a, j0 + (int)threadIdx.x % R, (int)threadIdx.x / R)[blockIdx.x] = tot;
 }
 
 // ---- K2: Ap = m^2 p - D ap, x += alpha p, r -= alpha Ap ------------------------
@@ -199,7 +228,6 @@ __global__ void __launch_bounds__(256) k_cg_update(CgArgs a)
     using real = typename P::real;
     using v2 = typename vec2_of<real>::type;
     __shared__ double lds[R * 4];
-    __shared__ int flag;
     int par, j0;
     tile_of(a, blockIdx.y, R, par, j0);
     bool act[R];
@@ -213,26 +241,22 @@ __global__ void __launch_bounds__(256) k_cg_update(CgArgs a)
     if (!any)
         return;
     const int Vh = a.g.Vh;
-    const int lb = logical_block(blockIdx.x, gridDim.x, a.remap);
-    const int gt = lb * blockDim.x + threadIdx.x;
-    const int s = gt / LPS, sub = gt % LPS;
+    int s, sub;
+    site_of_thread<LPS>(logical_block(blockIdx.x, gridDim.x, a.remap) * blockDim.x + threadIdx.x, s, sub);
     double nrm[R];
 #pragma unroll
     for (int r = 0; r < R; ++r)
         nrm[r] = 0.0;
     if (s < Vh) {
-        const void *in[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            in[r] = spin_at<P>(a.ap, j0 + r, Vh);
         cplx<real> acc[R][3];
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 acc[r][c] = czero<real>();
-        hop_accumulate<P, LPS, R>(a.g, (const typename P::link_t *)a.links[par], a.nbr[par], par, s, sub, in,
-                                  act, acc);
+        auto load = [&](int r, int n, cplx<real> *chi) { P::load_spinor(spin_at<P>(a.ap, j0 + r, Vh), Vh, n, chi); };
+        hop_accumulate<P, LPS, R>(a.g, (const typename P::link_t *)a.links[par], a.nbr[par], par, s, sub, act, acc,
+                                  load);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (!act[r])
@@ -240,7 +264,7 @@ __global__ void __launch_bounds__(256) k_cg_update(CgArgs a)
             const int j = j0 + r;
             const SysState &st = a.st[j];
             const real m2 = (real)st.mass2, alpha = (real)st.alpha;
-            const void *pb = spin_at<P>(a.p, j, Vh);
+            const void *pb = spin_at<P>(a.p[st.pcur], j, Vh);
             v2 *rv = (v2 *)a.r + (size_t)j * 3 * Vh;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -250,11 +274,12 @@ __global__ void __launch_bounds__(256) k_cg_update(CgArgs a)
                 const int64_t o = (int64_t)c * Vh + s;
                 if constexpr (P::id == 0) {
                     dbl2 *x = a.xhi[j];
-                    dbl2 xv = x[o];
+                    const dbl2 xv = x[o];
                     x[o] = dbl2{fma(alpha, pv.re, xv.x), fma(alpha, pv.im, xv.y)};
                 } else {
-                    flt2 xv = a.xlo[(size_t)j * 3 * Vh + o];
-                    a.xlo[(size_t)j * 3 * Vh + o] = flt2{fmaf(alpha, pv.re, xv.x), fmaf(alpha, pv.im, xv.y)};
+                    flt2 *xl = a.xlo + (size_t)j * 3 * Vh;
+                    const flt2 xv = xl[o];
+                    xl[o] = flt2{fmaf(alpha, pv.re, xv.x), fmaf(alpha, pv.im, xv.y)};
                 }
                 const real apr = m2 * pv.re - acc[r][c].re;
                 const real api = m2 * pv.im - acc[r][c].im;
@@ -269,104 +294,23 @@ __global__ void __launch_bounds__(256) k_cg_update(CgArgs a)
     double tot;
     block_sum_multi<R>(nrm, lds, tot);
     if (threadIdx.x < R)
-        publish_partial(a.partials + (size_t)(j0 + threadIdx.x) * a.pstride + blockIdx.x, tot);
-    if (!arrive_last(a.counters + blockIdx.y, gridDim.x, &flag))
-        return;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (!act[r])
-            continue;
-        const double rn = reduce_partials(a.partials + (size_t)(j0 + r) * a.pstride, gridDim.x, lds);
-        if (threadIdx.x == 0) {
-            SysState &st = a.st[j0 + r];
-            st.iters += 1;
-            if (!(rn < INFINITY)) {
-                st.ru_pending = 1;
-                st.stopping = STAG_EBREAKDOWN;
-            } else {
-                const bool conv = rn < st.stop2;
-                st.maxr2 = rn > st.maxr2 ? rn : st.maxr2;
-                bool recompute = conv || rn < st.delta2 * st.maxr2;
-                if (!conv && st.iters >= st.maxiter) {
-                    st.stopping = STAG_ENOCONV;
-                    recompute = true;
-                }
-                if (recompute) {
-                    // beta is formed from the recomputed residual; rr keeps the
-                    // previous iteration's value as its denominator
-                    st.ru_pending = 1;
-                } else {
-                    st.beta = rn / st.rr;
-                    st.rr = rn;
-                }
-            }
-        }
-    }
+        partial_slot(a, j0 + (int)threadIdx.x, 0)[blockIdx.x] = tot;
 }
 
-// ---- K3: p = r + beta p, <p,p> -------------------------------------------------
-
-template <class P>
-__global__ void __launch_bounds__(256) k_cg_direction(CgArgs a)
-{
-    using real = typename P::real;
-    using v2 = typename vec2_of<real>::type;
-    __shared__ double lds[4];
-    __shared__ int flag;
-    const int j = blockIdx.y;
-    {
-        const SysState &st = a.st[j];
-        if (!(st.phase == PH_RUN && !st.ru_pending))
-            return;
-    }
-    const int Vh = a.g.Vh;
-    const int s = logical_block(blockIdx.x, gridDim.x, a.remap) * blockDim.x + threadIdx.x;
-    double nrm[1] = {0.0};
-    if (s < Vh) {
-        const real beta = (real)a.st[j].beta;
-        const v2 *rv = (const v2 *)a.r + (size_t)j * 3 * Vh;
-        void *pb = spin_at<P>(a.p, j, Vh);
-        cplx<real> pv[3];
-        P::load_spinor(pb, Vh, s, pv);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const v2 rr = rv[(int64_t)c * Vh + s];
-            pv[c].re = fma(beta, pv[c].re, rr.x);
-            pv[c].im = fma(beta, pv[c].im, rr.y);
-        }
-        P::store_spinor(pb, Vh, s, pv);
-        if constexpr (P::id == 2)
-            P::load_spinor(pb, Vh, s, pv);  // norm of the value D will read
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            nrm[0] += (double)pv[c].re * pv[c].re + (double)pv[c].im * pv[c].im;
-    }
-    double tot;
-    block_sum_multi<1>(nrm, lds, tot);
-    if (threadIdx.x == 0)
-        publish_partial(a.partials + (size_t)j * a.pstride + blockIdx.x, tot);
-    if (!arrive_last(a.counters + j, gridDim.x, &flag))
-        return;
-    const double pp = reduce_partials(a.partials + (size_t)j * a.pstride, gridDim.x, lds);
-    if (threadIdx.x == 0)
-        a.st[j].pp = pp;
-}
-
-// ---- init: x = 0, r = b, p = r ---------------------------------------------------
+// ---- init: x = 0, r = b, p = r, beta = 0 ------------------------------------------
 
 template <class P>
 __global__ void __launch_bounds__(256) k_cg_init(CgArgs a)
 {
     using real = typename P::real;
     using v2 = typename vec2_of<real>::type;
-    __shared__ double lds[8];
-    __shared__ int flag;
+    __shared__ double lds[4];
     const int j = blockIdx.y;
     if (a.st[j].phase != PH_INIT)
         return;
     const int Vh = a.g.Vh;
     const int s = logical_block(blockIdx.x, gridDim.x, a.remap) * blockDim.x + threadIdx.x;
-    double nrm[2] = {0.0, 0.0};
+    double nrm[1] = {0.0};
     if (s < Vh) {
         const dbl2 *b = a.b[j];
         dbl2 *x = a.xhi[j];
@@ -383,48 +327,12 @@ __global__ void __launch_bounds__(256) k_cg_init(CgArgs a)
             pv[c] = {(real)bv.x, (real)bv.y};
             nrm[0] += bv.x * bv.x + bv.y * bv.y;
         }
-        void *pb = spin_at<P>(a.p, j, Vh);
-        P::store_spinor(pb, Vh, s, pv);
-        if constexpr (P::id == 2)
-            P::load_spinor(pb, Vh, s, pv);
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            nrm[1] += (double)pv[c].re * pv[c].re + (double)pv[c].im * pv[c].im;
+        P::store_spinor(spin_at<P>(a.p[0], j, Vh), Vh, s, pv);
     }
     double tot;
-    block_sum_multi<2>(nrm, lds, tot);
-    if (threadIdx.x < 2)
-        publish_partial(a.partials + (size_t)j * a.pstride * 2 + threadIdx.x * a.pstride + blockIdx.x, tot);
-    if (!arrive_last(a.counters + j, gridDim.x, &flag))
-        return;
-    const double bb = reduce_partials(a.partials + (size_t)j * a.pstride * 2, gridDim.x, lds);
-    const double pp = reduce_partials(a.partials + (size_t)j * a.pstride * 2 + a.pstride, gridDim.x, lds);
-    if (threadIdx.x == 0) {
-        SysState &st = a.st[j];
-        st.bb = bb;
-        st.stop2 = st.tol2 * bb;
-        st.rr = bb;
-        st.pp = pp;
-        st.maxr2 = bb;
-        st.iters = 0;
-        st.n_ru = 0;
-        st.restarts = 0;
-        st.ru_pending = 0;
-        st.stopping = 0;
-        st.beta = 0.0;
-        st.alpha = 0.0;
-        st.true_rr = bb;
-        if (!(bb < INFINITY)) {
-            st.phase = PH_DONE;
-            st.status = STAG_ENONFINITE;
-        } else if (bb == 0.0) {
-            st.phase = PH_DONE;
-            st.status = STAG_OK;
-            st.true_rr = 0.0;
-        } else {
-            st.phase = PH_RUN;
-        }
-    }
+    block_sum_multi<1>(nrm, lds, tot);
+    if (threadIdx.x == 0)
+        partial_slot(a, j, 0)[blockIdx.x] = tot;
 }
 
 // ---- RU2: t = D (x_hi + x_lo) on the other parity, FP64 -----------------------------
@@ -440,29 +348,15 @@ __global__ void __launch_bounds__(256) k_ru_dx(CgArgs a)
     }
     const int par = j / a.S, pout = 1 - par;
     const int Vh = a.g.Vh;
-    const int gt = logical_block(blockIdx.x, gridDim.x, a.remap) * blockDim.x + threadIdx.x;
-    const int s = gt / LPS, sub = gt % LPS;
+    int s, sub;
+    site_of_thread<LPS>(logical_block(blockIdx.x, gridDim.x, a.remap) * blockDim.x + threadIdx.x, s, sub);
     if (s >= Vh)
         return;
-    const dbl2 *lk = a.links64[pout];
-    const int32_t *nb = a.nbr[pout];
-    SiteCoord co;
-    if (!nb)
-        co = decode_site(a.g, pout, s);
     const dbl2 *xh = a.xhi[j];
     const flt2 *xl = a.xlo + (size_t)j * 3 * Vh;
-    cplx<double> acc[3] = {czero<double>(), czero<double>(), czero<double>()};
-#pragma unroll
-    for (int q = 0; q < 8 / LPS; ++q) {
-        const int d = sub + q * LPS;
-        const int n = nb ? nb[(int64_t)d * Vh + s] : neighbour(a.g, co, s, d);
-        cplx<double> U[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const dbl2 v = lk[((int64_t)d * 9 + k) * Vh + s];
-            U[k] = {v.x, v.y};
-        }
-        cplx<double> chi[3];
+    const bool act[1] = {true};
+    cplx<double> acc[1][3] = {{czero<double>(), czero<double>(), czero<double>()}};
+    auto load = [&](int, int n, cplx<double> *chi) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             dbl2 v = xh[(int64_t)c * Vh + n];
@@ -473,20 +367,13 @@ __global__ void __launch_bounds__(256) k_ru_dx(CgArgs a)
             }
             chi[c] = {v.x, v.y};
         }
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-                cmac(acc[c], U[c * 3 + b], chi[b]);
-    }
+    };
+    hop_accumulate<PrecF64, LPS, 1>(a.g, a.links64[pout], a.nbr[pout], pout, s, sub, act, acc, load);
     dbl2 *t = a.tmp + (size_t)j * 3 * Vh;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        acc[c].re = lane_sum<LPS>(acc[c].re);
-        acc[c].im = lane_sum<LPS>(acc[c].im);
+    for (int c = 0; c < 3; ++c)
         if (owns_colour<LPS>(sub, c))
-            t[(int64_t)c * Vh + s] = dbl2{acc[c].re, acc[c].im};
-    }
+            t[(int64_t)c * Vh + s] = dbl2{acc[0][c].re, acc[0][c].im};
 }
 
 // ---- RU3: x_hi += x_lo, r = b - m^2 x_hi + D t in FP64 ----------------------------------
@@ -498,7 +385,6 @@ __global__ void __launch_bounds__(256) k_ru_residual(CgArgs a)
     using v2 = typename vec2_of<real>::type;
     constexpr bool MIXED = P::id != 0;
     __shared__ double lds[4];
-    __shared__ int flag;
     const int j = blockIdx.y;
     {
         const SysState &st = a.st[j];
@@ -507,14 +393,15 @@ __global__ void __launch_bounds__(256) k_ru_residual(CgArgs a)
     }
     const int par = j / a.S;
     const int Vh = a.g.Vh;
-    const int gt = logical_block(blockIdx.x, gridDim.x, a.remap) * blockDim.x + threadIdx.x;
-    const int s = gt / LPS, sub = gt % LPS;
+    int s, sub;
+    site_of_thread<LPS>(logical_block(blockIdx.x, gridDim.x, a.remap) * blockDim.x + threadIdx.x, s, sub);
     double nrm[1] = {0.0};
     if (s < Vh) {
-        const void *in[1] = {a.tmp + (size_t)j * 3 * Vh};
+        const dbl2 *t = a.tmp + (size_t)j * 3 * Vh;
         const bool act[1] = {true};
         cplx<double> acc[1][3] = {{czero<double>(), czero<double>(), czero<double>()}};
-        hop_accumulate<PrecF64, LPS, 1>(a.g, a.links64[par], a.nbr[par], par, s, sub, in, act, acc);
+        auto load = [&](int, int n, cplx<double> *chi) { PrecF64::load_spinor(t, Vh, n, chi); };
+        hop_accumulate<PrecF64, LPS, 1>(a.g, a.links64[par], a.nbr[par], par, s, sub, act, acc, load);
         const double m2 = a.st[j].mass2;
         dbl2 *x = a.xhi[j];
         const dbl2 *b = a.b[j];
@@ -542,12 +429,101 @@ __global__ void __launch_bounds__(256) k_ru_residual(CgArgs a)
     double tot;
     block_sum_multi<1>(nrm, lds, tot);
     if (threadIdx.x == 0)
-        publish_partial(a.partials + (size_t)j * a.pstride + blockIdx.x, tot);
-    if (!arrive_last(a.counters + j, gridDim.x, &flag))
+        partial_slot(a, j, 0)[blockIdx.x] = tot;
+}
+
+// ---- finalize kernels: one block per system ---------------------------------------
+//
+// Launched right after the main kernel of the same role, with the main
+// kernel's block count.  The main kernels do not modify the state, so the
+// finalize kernel re-evaluates exactly the activity test the main kernel
+// used.
+
+enum FinRole { FIN_INIT = 0, FIN_AP = 1, FIN_UPDATE = 2, FIN_RU = 3 };
+
+template <int ROLE>
+__global__ void __launch_bounds__(256) k_cg_fin(CgArgs a, int nblk)
+{
+    __shared__ double lds[4];
+    const int j = blockIdx.x;
+    SysState &st = a.st[j];
+    bool act;
+    if (ROLE == FIN_INIT)
+        act = st.phase == PH_INIT;
+    else if (ROLE == FIN_RU)
+        act = st.phase == PH_RUN && st.ru_pending;
+    else
+        act = st.phase == PH_RUN && !st.ru_pending;
+    if (!act)
         return;
-    const double trr = reduce_partials(a.partials + (size_t)j * a.pstride, gridDim.x, lds);
-    if (threadIdx.x == 0) {
-        SysState &st = a.st[j];
+    const double v0 = reduce_partials(partial_slot(a, j, 0), nblk, lds);
+    double v1 = 0.0;
+    if (ROLE == FIN_AP)
+        v1 = reduce_partials(partial_slot(a, j, 1), nblk, lds);
+    if (threadIdx.x != 0)
+        return;
+    if (ROLE == FIN_INIT) {
+        const double bb = v0;
+        st.bb = bb;
+        st.stop2 = st.tol2 * bb;
+        st.rr = bb;
+        st.pp = bb;
+        st.maxr2 = bb;
+        st.iters = 0;
+        st.n_ru = 0;
+        st.restarts = 0;
+        st.ru_pending = 0;
+        st.stopping = 0;
+        st.beta = 0.0;
+        st.alpha = 0.0;
+        st.pcur = 0;
+        st.true_rr = bb;
+        if (!(bb < INFINITY)) {
+            st.phase = PH_DONE;
+            st.status = STAG_ENONFINITE;
+        } else if (bb == 0.0) {
+            st.phase = PH_DONE;
+            st.status = STAG_OK;
+            st.true_rr = 0.0;
+        } else {
+            st.phase = PH_RUN;
+        }
+    } else if (ROLE == FIN_AP) {
+        const double apap = v0, pp = v1;
+        st.pcur ^= 1;
+        st.pp = pp;
+        const double pap = st.mass2 * pp + apap;
+        if (!finite_pos(pap)) {
+            st.ru_pending = 1;
+            st.stopping = STAG_EBREAKDOWN;
+        } else {
+            st.alpha = st.rr / pap;
+        }
+    } else if (ROLE == FIN_UPDATE) {
+        const double rn = v0;
+        st.iters += 1;
+        if (!(rn < INFINITY)) {
+            st.ru_pending = 1;
+            st.stopping = STAG_EBREAKDOWN;
+        } else {
+            const bool conv = rn < st.stop2;
+            st.maxr2 = rn > st.maxr2 ? rn : st.maxr2;
+            bool recompute = conv || rn < st.delta2 * st.maxr2;
+            if (!conv && st.iters >= st.maxiter) {
+                st.stopping = STAG_ENOCONV;
+                recompute = true;
+            }
+            if (recompute) {
+                // beta is formed from the recomputed residual; rr keeps the
+                // previous iteration's value as its denominator
+                st.ru_pending = 1;
+            } else {
+                st.beta = rn / st.rr;
+                st.rr = rn;
+            }
+        }
+    } else {
+        const double trr = v0;
         st.n_ru += 1;
         st.ru_pending = 0;
         st.true_rr = trr;
@@ -579,34 +555,38 @@ __global__ void __launch_bounds__(256) k_ru_residual(CgArgs a)
 }
 
 // ---- tuning probe: out_r = D in_r for R systems, no reductions -------------------
+// blockIdx.y = tile; tiles alternate output parity like the CG kernels' tiles.
 
 template <class P, int LPS, int R>
-__global__ void __launch_bounds__(256) k_hop_probe(Geom g, const void *links, const int32_t *nbr, int pout,
-                                                    const void *in, void *out, int remap)
+__global__ void __launch_bounds__(256) k_hop_probe(Geom g, const void *links, const int32_t *nbr, const void *in,
+                                                    void *out, int remap)
 {
     using real = typename P::real;
     const int Vh = g.Vh;
-    const int gt = logical_block(blockIdx.x, gridDim.x, remap) * blockDim.x + threadIdx.x;
-    const int s = gt / LPS, sub = gt % LPS;
+    const int pout = blockIdx.y & 1;
+    int s, sub;
+    site_of_thread<LPS>(logical_block(blockIdx.x, gridDim.x, remap) * blockDim.x + threadIdx.x, s, sub);
     if (s >= Vh)
         return;
-    const void *inp[R];
+    const size_t vb = (size_t)Vh * P::spinor_bytes;
+    const char *inb = (const char *)in + (size_t)blockIdx.y * R * vb;
+    char *outb = (char *)out + (size_t)blockIdx.y * R * vb;
     bool act[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        inp[r] = (const char *)in + (size_t)r * Vh * P::spinor_bytes;
+    for (int r = 0; r < R; ++r)
         act[r] = true;
-    }
     cplx<real> acc[R][3];
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             acc[r][c] = czero<real>();
-    hop_accumulate<P, LPS, R>(g, (const typename P::link_t *)links, nbr, pout, s, sub, inp, act, acc);
+    auto load = [&](int r, int n, cplx<real> *chi) { P::load_spinor(inb + r * vb, Vh, n, chi); };
+    const typename P::link_t *lk = (const typename P::link_t *)links + (size_t)pout * 72 * Vh;
+    hop_accumulate<P, LPS, R>(g, lk, nbr ? nbr + (size_t)pout * 8 * Vh : nullptr, pout, s, sub, act, acc, load);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        void *o = (char *)out + (size_t)r * Vh * P::spinor_bytes;
+        void *o = outb + r * vb;
         if constexpr (P::id == 2) {
             if (sub == 0)
                 P::store_spinor(o, Vh, s, acc[r]);

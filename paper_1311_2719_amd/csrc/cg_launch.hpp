@@ -11,11 +11,11 @@ struct CgLaunchTable {
     // K1 / K2 / probe take (lanes per site, right-hand sides per tile)
     hipError_t (*ap)(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a);
     hipError_t (*update)(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a);
-    hipError_t (*direction)(dim3 grid, dim3 block, hipStream_t s, const CgArgs &a);
     hipError_t (*init)(dim3 grid, dim3 block, hipStream_t s, const CgArgs &a);
     hipError_t (*ru_residual)(int lps, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a);
+    // out_r = D in_r over grid.y tiles of R right-hand sides (tiles alternate parity)
     hipError_t (*probe)(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const Geom &g, const void *links,
-                        const int32_t *nbr, int pout, const void *in, void *out, int remap);
+                        const int32_t *nbr, const void *in, void *out, int remap);
     const int *rtiles;  // right-hand-side tile sizes compiled for this precision
     int n_rtiles;
 };
@@ -45,19 +45,14 @@ template <class P, int R> struct RLaunch {
         return hipGetLastError();
     }
     static hipError_t probe(int lps, dim3 grid, dim3 block, hipStream_t s, const Geom &g, const void *links,
-                            const int32_t *nbr, int pout, const void *in, void *out, int remap)
+                            const int32_t *nbr, const void *in, void *out, int remap)
     {
-        STAG_LPS_SWITCH(k_hop_probe, P, R, g, links, nbr, pout, in, out, remap);
+        STAG_LPS_SWITCH(k_hop_probe, P, R, g, links, nbr, in, out, remap);
         return hipGetLastError();
     }
 };
 
 template <class P> struct PLaunch {
-    static hipError_t direction(dim3 grid, dim3 block, hipStream_t s, const CgArgs &a)
-    {
-        hipLaunchKernelGGL((k_cg_direction<P>), grid, block, 0, s, a);
-        return hipGetLastError();
-    }
     static hipError_t init(dim3 grid, dim3 block, hipStream_t s, const CgArgs &a)
     {
         hipLaunchKernelGGL((k_cg_init<P>), grid, block, 0, s, a);

@@ -3,6 +3,7 @@
 // applied to the whole lattice), the FP64 residual-recomputation hop, and the
 // kernel-configuration tuner.
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -32,16 +33,17 @@ k_dslash64(Geom g, const dbl2 *__restrict__ links, const int32_t *__restrict__ n
 {
     const int p = par_fixed >= 0 ? par_fixed : (int)blockIdx.y;
     const int Vh = g.Vh;
-    const int gt = logical_block(blockIdx.x, gridDim.x, remap) * blockDim.x + threadIdx.x;
-    const int site = gt / LPS, sub = gt % LPS;
+    int site, sub;
+    site_of_thread<LPS>(logical_block(blockIdx.x, gridDim.x, remap) * blockDim.x + threadIdx.x, site, sub);
     if (site >= count)
         return;
     const int s = offset + site;
-    const void *inp[1] = {in + (size_t)(1 - p) * 3 * Vh};
+    const dbl2 *src = in + (size_t)(1 - p) * 3 * Vh;
     const bool act[1] = {true};
     cplx<double> acc[1][3] = {{czero<double>(), czero<double>(), czero<double>()}};
-    hop_accumulate<PrecF64, LPS, 1>(g, links + (size_t)p * 8 * 9 * Vh, nbr ? nbr + (size_t)p * 8 * Vh : nullptr, p,
-                                    s, sub, inp, act, acc);
+    auto load = [&](int, int n, cplx<double> *chi) { PrecF64::load_spinor(src, Vh, n, chi); };
+    hop_accumulate<PrecF64, LPS, 1>(g, links + (size_t)p * 72 * Vh, nbr ? nbr + (size_t)p * 8 * Vh : nullptr, p, s,
+                                    sub, act, acc, load);
     dbl2 *o = out + (size_t)p * 3 * Vh;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -77,7 +79,7 @@ hipError_t launch_ru_dx(int lps, bool mixed, dim3 grid, dim3 block, hipStream_t 
 static hipError_t launch_dslash64(const KernelCfg &cfg, const GaugeField *f, int par_fixed, int nparity, int offset,
                                   int count, const double *in, double *out, int accumulate, hipStream_t s)
 {
-    const int64_t threads = (int64_t)count * cfg.lps;
+    const int64_t threads = (int64_t)count * cfg.lps;  // site = wave * (64/lps) + lane % (64/lps)
     dim3 grid((unsigned)((threads + cfg.block - 1) / cfg.block), (unsigned)nparity);
     dim3 block(cfg.block);
     const dbl2 *lk = (const dbl2 *)f->links[0];
@@ -178,8 +180,9 @@ KernelCfg tune_config(Ctx *ctx, GaugeField *f, int prec, int nrhs, hipStream_t s
         for (int i = 0; i < tab.n_rtiles; ++i)
             if (nrhs % tab.rtiles[i] == 0)
                 tiles.push_back(tab.rtiles[i]);
-        const int rmax = *std::max_element(tiles.begin(), tiles.end());
-        const size_t vbytes = (size_t)f->g.Vh * spinor_bytes_of(prec) * rmax;
+        const bool verbose = getenv("STAG_TUNE_VERBOSE") != nullptr;
+        // scratch vectors for every system of the solve shape (2 parities x nrhs)
+        const size_t vbytes = (size_t)f->g.Vh * spinor_bytes_of(prec) * 2 * nrhs;
         void *in = ctx->arena.alloc(vbytes), *out = ctx->arena.alloc(vbytes);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         bool ok = in && out && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
@@ -192,12 +195,10 @@ KernelCfg tune_config(Ctx *ctx, GaugeField *f, int prec, int nrhs, hipStream_t s
                     for (int T = 0; T < 2 && ok; ++T) {
                         for (int X = 0; X < 2 && ok; ++X) {
                             const int64_t threads = (int64_t)f->g.Vh * L;
-                            dim3 grid((unsigned)((threads + B - 1) / B)), block(B);
-                            const void *links = f->links_for(prec, 1);
-                            const int32_t *nb = T ? f->nbr_for(1) : nullptr;
-                            auto run = [&]() {
-                                return tab.probe(L, R, grid, block, s, f->g, links, nb, 1, in, out, X);
-                            };
+                            dim3 grid((unsigned)((threads + B - 1) / B), (unsigned)(2 * nrhs / R)), block(B);
+                            const void *links = f->links_for(prec, 0);
+                            const int32_t *nb = T ? f->nbr_for(0) : nullptr;
+                            auto run = [&]() { return tab.probe(L, R, grid, block, s, f->g, links, nb, in, out, X); };
                             if (run() != hipSuccess) {
                                 ok = false;
                                 break;
@@ -213,7 +214,11 @@ KernelCfg tune_config(Ctx *ctx, GaugeField *f, int prec, int nrhs, hipStream_t s
                             }
                             float ms = 0.f;
                             (void)hipEventElapsedTime(&ms, e0, e1);
-                            const double per_rhs = ms / reps / R;
+                            const double per_rhs = ms / reps / nrhs;
+                            if (verbose)
+                                fprintf(stderr, "[stag tune] V=%d prec=%d nrhs=%d lps=%d block=%d rtile=%d tables=%d "
+                                                "remap=%d: %.2f us per rhs\n",
+                                        2 * f->g.Vh, prec, nrhs, L, B, R, T, X, per_rhs * 1e3);
                             if (per_rhs < best_t * 0.995) {
                                 best_t = per_rhs;
                                 best.lps = L;

@@ -48,7 +48,7 @@ k_prepare_links(Geom g, int tap, const double *__restrict__ U, dbl2 *__restrict_
     const int64_t lex = src[0] + (int64_t)g.L[0] * (src[1] + (int64_t)g.L[1] * (src[2] + (int64_t)g.L[2] * src[3]));
     const double *u = U + (lex * 4 + mu) * 18;
     int nonfinite = 0;
-    const int64_t obase = (((int64_t)p * 8 + d) * 9) * g.Vh + s;
+    const int64_t pbase = (int64_t)p * 72 * g.Vh;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
 #pragma unroll
@@ -61,7 +61,7 @@ k_prepare_links(Geom g, int tap, const double *__restrict__ U, dbl2 *__restrict_
             re *= fac;
             im *= fac;
             nonfinite |= !(isfinite(re) && isfinite(im));
-            const int64_t o = obase + (int64_t)(a * 3 + b) * g.Vh;
+            const int64_t o = pbase + link_offset(g.Vh, d, a * 3 + b, s);
             l64[o] = dbl2{re, im};
             if (l32)
                 l32[o] = flt2{(float)re, (float)im};

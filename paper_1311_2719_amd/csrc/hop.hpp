@@ -2,11 +2,13 @@
 // Sec. 3) as device building blocks shared by the standalone D_slash and the
 // fused CG kernels.
 //
-// One output site is processed by LPS lanes (LPS = 1, 2, 4, 8 consecutive lanes
-// of a wavefront); lane `sub` takes the directions d = sub, sub + LPS, ...  and
-// the partial sums are combined with cross-lane shuffles.  R right-hand sides
-// that share the gauge field are processed together so that each link entry is
-// loaded once for all of them.
+// One output site is processed by LPS lanes (LPS = 1, 2, 4, 8) of one
+// wavefront.  Lanes are numbered sub-major: lane = sub * (64/LPS) + i, so the
+// lanes that share `sub` take 64/LPS consecutive sites and every load they
+// issue is unit-stride.  Lane `sub` takes the directions d = sub, sub + LPS,
+// ... and the partial sums of a site are combined with cross-lane shuffles
+// (xor 32, 16, 8).  R right-hand sides that share the gauge field are processed
+// together so that each link entry is loaded once for all of them.
 #pragma once
 
 #include "stag_types.hpp"
@@ -25,20 +27,30 @@ __device__ __forceinline__ int logical_block(int b, int nblocks, int remap)
     return xcd * q + (xcd < rem ? xcd : rem) + i;
 }
 
+// Site and lane-within-site of global thread gt (blocks are whole wavefronts).
+template <int LPS> __device__ __forceinline__ void site_of_thread(int gt, int &s, int &sub)
+{
+    constexpr int SPW = 64 / LPS;  // sites per wavefront
+    const int lane = gt & 63;
+    sub = lane / SPW;
+    s = (gt >> 6) * SPW + (lane % SPW);
+}
+
 template <int LPS, typename T> __device__ __forceinline__ T lane_sum(T v)
 {
 #pragma unroll
-    for (int o = LPS / 2; o >= 1; o >>= 1)
+    for (int o = 32; o >= 64 / LPS; o >>= 1)
         v += __shfl_xor(v, o);
     return v;
 }
 
-// acc[r][a] += sum over this lane's directions of L_d(s)[a][b] in_r(n_d(s))[b]
-template <class P, int LPS, int R>
+// acc[r][a] += sum over this lane's directions of L_d(s)[a][b] in_r(n_d(s))[b],
+// then summed over the LPS lanes of the site.  load(r, n, chi) fetches the
+// input colour vector of right-hand side r at neighbour site n.
+template <class P, int LPS, int R, class Load>
 __device__ __forceinline__ void hop_accumulate(const Geom &g, const typename P::link_t *__restrict__ links,
                                                const int32_t *__restrict__ nbr, int p_out, int s, int sub,
-                                               const void *const *in, const bool *act,
-                                               cplx<typename P::real> (*acc)[3])
+                                               const bool *act, cplx<typename P::real> (*acc)[3], Load load)
 {
     using real = typename P::real;
     SiteCoord c;
@@ -49,16 +61,16 @@ __device__ __forceinline__ void hop_accumulate(const Geom &g, const typename P::
         const int d = sub + j * LPS;
         const int n = nbr ? nbr[(int64_t)d * g.Vh + s] : neighbour(g, c, s, d);
         cplx<real> U[9];
-        const typename P::link_t *lp = links + (int64_t)d * 9 * g.Vh + s;
+        const typename P::link_t *lp = links + link_offset(g.Vh, d, 0, s);
 #pragma unroll
         for (int k = 0; k < 9; ++k)
-            U[k] = P::load_link(lp + (int64_t)k * g.Vh);
+            U[k] = P::load_link(lp + (int64_t)k * 8 * g.Vh);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (!act[r])
                 continue;
             cplx<real> chi[3];
-            P::load_spinor(in[r], g.Vh, n, chi);
+            load(r, n, chi);
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -107,44 +119,13 @@ template <int R> __device__ __forceinline__ void block_sum_multi(double (&v)[R],
     __syncthreads();
 }
 
-// Per-block partial sums are published with a device-scope store followed by a
-// device-scope fence by the writing thread; the block then takes a ticket from
-// a device-scope atomic counter.  The block that draws the last ticket fences
-// again before reading the partials, so it sees every block's value even when
-// the blocks ran on different XCDs (each XCD has its own L2).
-__device__ __forceinline__ void publish_partial(double *p, double v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-}
-
-__device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned nblocks, int *lds_flag)
-{
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned t = atomicAdd(counter, 1u);
-        const int last = (t == nblocks - 1);
-        if (last) {
-            __threadfence();
-            __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        *lds_flag = last;
-    }
-    __syncthreads();
-    return *lds_flag != 0;
-}
-
-__device__ __forceinline__ double load_partial(const double *p)
-{
-    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// In the last block: total of partials[0 .. n) in a fixed order; valid in thread 0.
+// Total of partials[0 .. n) in a fixed order (a strided sum per thread, then
+// the block tree); valid in thread 0.
 __device__ __forceinline__ double reduce_partials(const double *partials, int n, double *lds)
 {
     double v = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x)
-        v += load_partial(partials + i);
+        v += partials[i];
     double arr[1] = {v};
     double out;
     block_sum_multi<1>(arr, lds, out);

@@ -86,6 +86,7 @@ struct GaugeField {
 };
 
 class Server;
+class Batch;
 
 struct Ctx {
     int device = 0;
@@ -96,6 +97,9 @@ struct Ctx {
     std::map<int32_t, std::shared_ptr<GaugeField>> fields;
     int32_t next_id = 1;
     std::unique_ptr<Server> server;
+    // idle CG workspaces kept for reuse by later solves of the same shape
+    std::mutex cache_mu;
+    std::vector<std::shared_ptr<Batch>> batch_cache;
     // serving configuration
     int slots_per_field = 16;
     int epoch_iters = 16;
@@ -128,6 +132,13 @@ int launch_pack(const Geom &g, const double *lex, double *eo, int to_eo, hipStre
 int dslash_f64(Ctx *ctx, GaugeField *f, int out_parity, int64_t offset, int64_t count,
                const double *in, double *out, int accumulate, hipStream_t s);
 KernelCfg tune_config(Ctx *ctx, GaugeField *f, int prec, int nrhs, hipStream_t s);
+
+// Take a workspace for (field, precision, slots, stream) from the cache or
+// create one; give it back with release_batch.  ENOMEM after evicting the cache.
+int acquire_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int prec, int slots, hipStream_t s,
+                  std::shared_ptr<Batch> &out);
+void release_batch(Ctx *ctx, std::shared_ptr<Batch> b);
+void drop_cached_batches(Ctx *ctx, int32_t gauge_id);  // all if gauge_id < 0
 
 int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs,
                    const stag_cg_params *params, const double *const *b, double *const *x,

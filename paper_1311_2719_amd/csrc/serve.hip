@@ -174,8 +174,8 @@ bool Server::step_lane(Lane &l)
     Batch *B = l.batch.get();
     // keep one epoch queued beyond the outstanding snapshot
     if (B && l.active > 0 && !l.epoch_queued) {
-        const bool mixed = l.prec != STAG_FP64;
-        if (B->enqueue_epoch(ctx_->epoch_iters, mixed) == STAG_OK)
+        const int ru_interval = l.prec != STAG_FP64 ? 2 : 1 << 30;
+        if (B->enqueue_epoch(ctx_->epoch_iters, ru_interval) == STAG_OK)
             l.epoch_queued = true;
         progress = true;
     }

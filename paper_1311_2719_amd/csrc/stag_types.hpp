@@ -1,13 +1,18 @@
 // Device-side types shared by the HIP kernels of libstagcg.
 //
-// Storage formats (all structure-of-arrays over the checkerboard index of one
-// parity, so consecutive lanes touch consecutive addresses):
-//   links   [parity][dir 8][entry 9][Vh] of a complex type; dir 0..3 are the
-//           forward links W_mu(x) = 1/2 eta_mu(x) s_fwd(x) U_mu(x), dir 4..7 the
-//           backward links B_mu(x) = -1/2 eta_mu(x) s_bwd(x) U_mu(x-mu)^dagger,
-//           both stored at the site x that uses them; s_fwd / s_bwd are the
-//           t-boundary signs.  With these, (D chi)(x) = sum_d L_d(x) chi(n_d(x)),
-//           n_d = x+mu (d < 4) or x-mu (d >= 4).
+// Storage formats (structure-of-arrays over the checkerboard index of one
+// parity, so lanes that take consecutive sites touch consecutive addresses):
+//   links   per parity [entry 9][site tile Vh/8][dir 8][site 8] of a complex
+//           type: each (entry, tile) is a contiguous 8 x 8 block, so a
+//           wavefront reading one entry for 64 consecutive sites and one
+//           direction, or for 8 sites and all 8 directions, touches whole
+//           cache lines either way.  Dir 0..3 are the forward links
+//           W_mu(x) = 1/2 eta_mu(x) s_fwd(x) U_mu(x), dir 4..7 the backward
+//           links B_mu(x) = -1/2 eta_mu(x) s_bwd(x) U_mu(x-mu)^dagger, both stored
+//           at the site x that uses them; s_fwd / s_bwd are the t-boundary
+//           signs.  With these, (D chi)(x) = sum_d L_d(x) chi(n_d(x)),
+//           n_d = x+mu (d < 4) or x-mu (d >= 4).  Vh is a multiple of 8
+//           because every extent is even.
 //   spinors FP64 / FP32: [colour 3][Vh] of complex; FP16: one 16-byte record
 //           per site (3 half2 colours scaled by 1/norm, and the FP32 norm =
 //           largest |component| of the site).
@@ -51,6 +56,12 @@ inline Geom make_geom(const int32_t d[4])
     g.sz = g.Lxh * d[1];
     g.st = g.Lxh * d[1] * d[2];
     return g;
+}
+
+// Offset of link entry k of direction d at checkerboard site s, within one parity.
+__host__ __device__ __forceinline__ int64_t link_offset(int Vh, int d, int k, int s)
+{
+    return (int64_t)k * 8 * Vh + (int64_t)(s >> 3) * 64 + d * 8 + (s & 7);
 }
 
 struct SiteCoord {

@@ -11,3 +11,13 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: longer CPU test")
+
+
+@pytest.fixture(scope="session")
+def gpu_ctx():
+    """One library context on cuda:0 for the whole GPU test session."""
+    from paper_1311_2719_amd import binding
+
+    ctx = binding.Context(device=0, arena_bytes=6 << 30)
+    yield ctx
+    ctx.close()

@@ -1,0 +1,148 @@
+"""GPU: multi-right-hand-side batched solves and the serving loop.
+
+Each system of a batch meets the FP64 true residual (recomputed by the
+oracle) and agrees with the same system solved alone within the error the
+tolerance allows; the serving stream's results are the same alone and in the
+mix within that tolerance."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1311_2719_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("prec", [binding.FP32_RU, binding.FP64, binding.FP16_RU])
+def test_batch_matches_single_solves(gpu_ctx, prec):
+    dims, tol, n = (8, 8, 8, 8), 1e-10, 12
+    U = inputs.smooth_su3(dims, 0.5, 104)
+    masses = inputs.masses_uniform(0.01, 0.2, n)
+    srcs = [inputs.gaussian_source(dims, 2040 + i) for i in range(n)]
+    f = gpu_ctx.set_gauge(dims, U)
+    try:
+        bs = [gpu_ctx.pack(f, s) for s in srcs]
+        xs = [gpu_ctx.new_fermion(f) for _ in range(n)]
+        plist = [binding.params(float(mm), tol=tol, precision=prec) for mm in masses]
+        infos = gpu_ctx.cg_solve_batch(f, bs, xs, plist)
+        torch.cuda.synchronize()
+        for i in range(n):
+            assert infos[i]["status"] == 0
+            x = gpu_ctx.unpack(f, xs[i]).cpu().numpy()
+            tr = oracle.true_residual(dims, U, masses[i], srcs[i], x)
+            assert tr <= tol, (i, tr)
+            xa = gpu_ctx.new_fermion(f)
+            ia = gpu_ctx.cg_solve(f, bs[i], xa, mass=float(masses[i]), tol=tol, precision=prec)
+            xa = gpu_ctx.unpack(f, xa).cpu().numpy()
+            assert rel(x, xa) < 1e-8
+            if prec == binding.FP64:
+                assert abs(ia["iters"] - infos[i]["iters"]) <= 1
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
+def test_batch_heterogeneous_parameters(gpu_ctx):
+    # different parities, tolerances and iteration limits in one batch
+    dims = (4, 4, 4, 8)
+    U = inputs.haar_su3(dims, 131)
+    f = gpu_ctx.set_gauge(dims, U)
+    try:
+        srcs = [inputs.gaussian_source(dims, 140 + i) for i in range(4)]
+        bs = [gpu_ctx.pack(f, s) for s in srcs]
+        xs = [gpu_ctx.new_fermion(f) for _ in range(4)]
+        plist = [binding.params(0.1, tol=1e-10, precision=binding.FP32_RU, parity=binding.EVEN),
+                 binding.params(0.2, tol=1e-8, precision=binding.FP32_RU, parity=binding.ODD),
+                 binding.params(0.05, tol=1e-10, precision=binding.FP32_RU, maxiter=4),
+                 binding.params(0.3, tol=1e-10, precision=binding.FP32_RU)]
+        infos = gpu_ctx.cg_solve_batch(f, bs, xs, plist, check=False)
+        assert infos[0]["status"] == 0 and infos[1]["status"] == 0 and infos[3]["status"] == 0
+        assert infos[2]["status"] == binding.ENOCONV
+        x0 = gpu_ctx.unpack(f, xs[0]).cpu().numpy()
+        assert oracle.true_residual(dims, U, 0.1, srcs[0], x0, parity=0) <= 1e-10
+        x1 = gpu_ctx.unpack(f, xs[1]).cpu().numpy()
+        assert oracle.true_residual(dims, U, 0.2, srcs[1], x1, parity=1) <= 1e-8
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
+def test_serving_alone_equals_in_the_mix(gpu_ctx):
+    # fields of different sizes resident at once; requests arrive while others run
+    specs = [((4, 4, 4, 4), 105), ((8, 8, 8, 8), 106), ((6, 6, 6, 8), 107)]
+    fields = []
+    try:
+        for dims, seed in specs:
+            U = inputs.smooth_su3(dims, 0.5, seed)
+            fields.append((dims, U, gpu_ctx.set_gauge(dims, U)))
+        rng = np.random.default_rng(305)
+        reqs = []
+        for i in range(24):
+            k = int(rng.integers(0, len(fields)))
+            dims, U, f = fields[k]
+            m = float(np.exp(rng.uniform(np.log(0.01), np.log(0.2))))
+            prec = [binding.FP32_RU, binding.FP16_RU, binding.FP64][i % 3]
+            src = inputs.gaussian_source(dims, 10000 + i)
+            b = gpu_ctx.pack(f, src)
+            x = gpu_ctx.new_fermion(f)
+            torch.cuda.synchronize()
+            t = gpu_ctx.submit(f, b, x, mass=m, tol=1e-10, precision=prec)
+            reqs.append((t, k, m, prec, src, b, x))
+        for t, k, m, prec, src, b, x in reqs:
+            info = gpu_ctx.wait(t)
+            assert info["rc"] == 0 and info["status"] == 0, info
+            assert info["seconds"] >= info["queue_seconds"] >= 0
+            gpu_ctx.release(t)
+            dims, U, f = fields[k]
+            xm = gpu_ctx.unpack(f, x).cpu().numpy()
+            assert oracle.true_residual(dims, U, m, src, xm) <= 1e-10
+            xa = gpu_ctx.new_fermion(f)
+            gpu_ctx.cg_solve(f, b, xa, mass=m, tol=1e-10, precision=prec)
+            assert rel(xm, gpu_ctx.unpack(f, xa).cpu().numpy()) < 1e-8
+        with pytest.raises(binding.StagError) as e:
+            gpu_ctx.poll(reqs[0][0])
+        assert e.value.code == binding.ENOENT
+    finally:
+        for _, _, f in fields:
+            gpu_ctx.free_gauge(f)
+
+
+def test_serving_admission_by_memory():
+    # Two 8^4 fields (8 MiB each with all precisions and tables) in an arena
+    # with 1.5 MiB to spare: the first field's two-slot FP32 batch (about
+    # 1.2 MB) fits, the second field's does not, so its requests wait until
+    # the first batch drains and its workspace is released, then run.
+    dims = (8, 8, 8, 8)
+    U = inputs.smooth_su3(dims, 0.5, 151)
+    Ud = torch.from_numpy(U).cuda()
+    with binding.Context(device=0, arena_bytes=(16 << 20) + (3 << 19)) as ctx:
+        ctx.serve_config(slots_per_field=2, epoch_iters=8)
+        f1 = ctx.set_gauge(dims, Ud)
+        f2 = ctx.set_gauge(dims, Ud)
+        srcs = [inputs.gaussian_source(dims, 160 + i) for i in range(4)]
+        bs = [ctx.pack(f1, s) for s in srcs]
+        xs = [ctx.new_fermion(f1) for _ in srcs]
+        torch.cuda.synchronize()
+        tickets = [ctx.submit(f1 if i < 2 else f2, bs[i], xs[i], mass=0.05, precision=binding.FP32_RU)
+                   for i in range(4)]
+        infos = [ctx.wait(t) for t in tickets]
+        for i, info in enumerate(infos):
+            assert info["status"] == 0, info
+            x = ctx.unpack(f1, xs[i]).cpu().numpy()
+            assert oracle.true_residual(dims, U, 0.05, srcs[i], x) <= 1e-10
+        # the second field's requests were admitted only after the first
+        # batch had finished (all four were submitted within a few ms)
+        first_done = max(infos[0]["seconds"], infos[1]["seconds"])
+        assert min(infos[2]["queue_seconds"], infos[3]["queue_seconds"]) >= first_done - 5e-3
+    # an arena with room for the field but for no workspace: ENOMEM
+    with binding.Context(device=0, arena_bytes=(8 << 20) + (320 << 10)) as ctx:
+        f = ctx.set_gauge(dims, Ud)
+        b = ctx.pack(f, inputs.gaussian_source(dims, 170))
+        x = ctx.new_fermion(f)
+        torch.cuda.synchronize()
+        info = ctx.wait(ctx.submit(f, b, x, mass=0.05, precision=binding.FP32_RU))
+        assert info["rc"] == binding.ENOMEM

@@ -1,0 +1,219 @@
+"""GPU parity of the CG solves against the CPU oracle.
+
+Bars:
+  FP64: ||x_gpu - x_oracle|| / ||x_oracle|| <= 1e-10, where the oracle runs
+        the same even-odd CG loop with the same stopping rule from x = 0;
+        iteration counts agree within 1.
+  every solve (FP64 and mixed): FP64 true residual ||b - A x|| / ||b|| <= tol,
+        recomputed by the oracle from the returned x.
+  mixed: the error against a tight oracle solve is reported by the test and
+        bounded by kappa-free slack (1e-8) as a sanity check."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import free_field
+from paper_1311_2719_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def solve(ctx, f, b_lex, want_y=False, **kw):
+    b = ctx.pack(f, b_lex)
+    x = ctx.new_fermion(f)
+    y = ctx.new_fermion(f) if want_y else None
+    info = ctx.cg_solve(f, b, x, y=y, check=False, **kw)
+    torch.cuda.synchronize()
+    xs = ctx.unpack(f, x).cpu().numpy()
+    ys = ctx.unpack(f, y).cpu().numpy() if want_y else None
+    return xs, ys, info
+
+
+def test_config0_fp64_matches_oracle(gpu_ctx):
+    # 4^4, Haar links (seed 101), m = 0.1, Gaussian source (seed 201), 1e-10
+    dims, m, tol = (4, 4, 4, 4), 0.1, 1e-10
+    U = inputs.haar_su3(dims, 101)
+    b = inputs.gaussian_source(dims, 201)
+    f = gpu_ctx.set_gauge(dims, U)
+    try:
+        x, y, info = solve(gpu_ctx, f, b, want_y=True, mass=m, tol=tol)
+        xr, yr, oi = oracle.cg_solve(dims, U, m, b, tol=tol, want_y=True)
+        assert info["status"] == 0
+        assert abs(info["iters"] - oi["iters"]) <= 1
+        assert rel(x, xr) <= 1e-10
+        assert oracle.true_residual(dims, U, m, b, x) <= tol
+        assert abs(info["true_rel_resid"] - oracle.true_residual(dims, U, m, b, x)) < 1e-12
+        assert rel(y, yr) <= 1e-10
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
+@pytest.mark.parametrize("par", [binding.EVEN, binding.ODD])
+def test_single_parity_and_second_half(gpu_ctx, par):
+    dims, m, tol = (4, 6, 4, 8), 0.2, 1e-10
+    U = inputs.haar_su3(dims, 71)
+    b = inputs.gaussian_source(dims, 72)
+    f = gpu_ctx.set_gauge(dims, U)
+    try:
+        x, y, info = solve(gpu_ctx, f, b, want_y=True, mass=m, tol=tol, parity=par)
+        xr, yr, oi = oracle.cg_solve(dims, U, m, b, tol=tol, parity=par, want_y=True)
+        V = int(np.prod(dims))
+        lex = np.arange(V)
+        p = (lex % 4 + (lex // 4) % 6 + (lex // 24) % 4 + lex // 96) & 1
+        assert info["status"] == 0 and abs(info["iters"] - oi["iters"]) <= 1
+        assert rel(x[p == par], xr[p == par]) <= 1e-10
+        assert not np.any(x[p != par])          # the other half is not written
+        assert rel(y[p != par], yr[p != par]) <= 1e-10  # y = D x on the other half
+        assert oracle.true_residual(dims, U, m, b, x, parity=par) <= tol
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
+def test_free_field_closed_form(gpu_ctx):
+    dims, m = (8, 8, 8, 8), 0.05
+    b = inputs.gaussian_source(dims, 81)
+    f = gpu_ctx.set_gauge(dims, inputs.unit_links(dims))
+    try:
+        x, _, info = solve(gpu_ctx, f, b, mass=m, tol=1e-12)
+        assert info["status"] == 0
+        assert rel(x, free_field.solve(dims, m, b)) <= 1e-10
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
+@pytest.mark.parametrize("k", [1, 2, 7])
+def test_iterates_match_step_by_step(gpu_ctx, k):
+    # with maxiter = k the GPU stops at the k-th iterate (ENOCONV); it must be
+    # the oracle's k-th iterate of the same loop
+    dims, m = (4, 4, 4, 4), 0.1
+    U = inputs.haar_su3(dims, 91)
+    b = inputs.gaussian_source(dims, 92)
+    f = gpu_ctx.set_gauge(dims, U)
+    try:
+        x, _, info = solve(gpu_ctx, f, b, mass=m, tol=1e-10, maxiter=k, parity=binding.EVEN)
+        assert info["status"] == binding.ENOCONV and info["iters"] == k
+        xr, oi = oracle.cg_pass(dims, U, m, b, tol=0.0, maxiter=k, parity=0)
+        assert oi["iters"] == k
+        assert rel(x, xr) <= 1e-12
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
+def test_config1_size_fp64(gpu_ctx):
+    # the benchmark's workload: 16^4, eps = 0.3 (seed 102), m = 0.05, source seed 202
+    dims, m, tol = (16, 16, 16, 16), 0.05, 1e-10
+    U = inputs.smooth_su3(dims, 0.3, 102)
+    b = inputs.gaussian_source(dims, 202)
+    f = gpu_ctx.set_gauge(dims, U)
+    try:
+        x, _, info = solve(gpu_ctx, f, b, mass=m, tol=tol)
+        xr, _, oi = oracle.cg_solve(dims, U, m, b, tol=tol)
+        assert info["status"] == 0 and abs(info["iters"] - oi["iters"]) <= 1
+        assert rel(x, xr) <= 1e-10
+        assert oracle.true_residual(dims, U, m, b, x) <= tol
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
+@pytest.mark.parametrize("prec", [binding.FP32_RU, binding.FP16_RU])
+@pytest.mark.parametrize("dims,m,eps", [((4, 4, 4, 4), 0.1, None), ((8, 8, 8, 8), 0.01, 0.5),
+                                        ((16, 16, 16, 16), 0.05, 0.3)])
+def test_mixed_precision_true_residual(gpu_ctx, prec, dims, m, eps):
+    tol = 1e-10
+    U = inputs.haar_su3(dims, 101) if eps is None else inputs.smooth_su3(dims, eps, 104)
+    b = inputs.gaussian_source(dims, 204)
+    f = gpu_ctx.set_gauge(dims, U)
+    try:
+        x, _, info = solve(gpu_ctx, f, b, mass=m, tol=tol, precision=prec)
+        assert info["status"] == 0
+        tr = oracle.true_residual(dims, U, m, b, x)
+        assert tr <= tol
+        assert abs(info["true_rel_resid"] - tr) <= 1e-3 * tol
+        assert info["reliable_updates"] >= 2
+        xt, ti = oracle.cg_full(dims, U, m, b, tol=1e-13)
+        err = rel(x, xt)
+        print("precision %d %s: iters %d, reliable updates %d, true residual %.2e, error vs tight %.2e"
+              % (prec, dims, info["iters"], info["reliable_updates"], tr, err))
+        assert err < 1e-8
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
+def test_edge_cases(gpu_ctx):
+    dims = (4, 4, 4, 4)
+    U = inputs.haar_su3(dims, 111)
+    f = gpu_ctx.set_gauge(dims, U)
+    try:
+        # zero source: x = 0, no iterations
+        x, _, info = solve(gpu_ctx, f, np.zeros((256, 3), np.complex128), mass=0.1)
+        assert info["status"] == 0 and info["iters"] == 0 and not np.any(x)
+        # iteration limit
+        b = inputs.gaussian_source(dims, 112)
+        for prec in (binding.FP64, binding.FP32_RU, binding.FP16_RU):
+            x, _, info = solve(gpu_ctx, f, b, mass=0.1, maxiter=5, precision=prec)
+            assert info["status"] == binding.ENOCONV and info["iters"] == 5
+            assert info["true_rel_resid"] > 1e-10
+            assert abs(info["true_rel_resid"] - oracle.true_residual(dims, U, 0.1, b, x)) < 1e-6
+        # non-finite source
+        bad = b.copy()
+        bad[3, 1] = np.inf
+        x, _, info = solve(gpu_ctx, f, bad, mass=0.1)
+        assert info["status"] == binding.ENONFINITE
+        # invalid parameters
+        bd = gpu_ctx.pack(f, b)
+        xd = gpu_ctx.new_fermion(f)
+        for kw in ({"mass": 0.0}, {"mass": 0.1, "tol": 0.0}, {"mass": 0.1, "parity": 5},
+                   {"mass": 0.1, "precision": 9}, {"mass": -1.0}):
+            with pytest.raises(binding.StagError) as e:
+                gpu_ctx.cg_solve(f, bd, xd, **kw)
+            assert e.value.code == binding.EINVAL
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
+def test_repeatable_bitwise(gpu_ctx):
+    # fixed reduction trees: the same solve twice gives the same bits
+    dims = (8, 8, 8, 8)
+    U = inputs.smooth_su3(dims, 0.5, 121)
+    b = inputs.gaussian_source(dims, 122)
+    f = gpu_ctx.set_gauge(dims, U)
+    try:
+        for prec in (binding.FP64, binding.FP32_RU, binding.FP16_RU):
+            x1, _, i1 = solve(gpu_ctx, f, b, mass=0.05, precision=prec)
+            x2, _, i2 = solve(gpu_ctx, f, b, mass=0.05, precision=prec)
+            assert i1["iters"] == i2["iters"] and np.array_equal(x1, x2)
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
+def test_graph_replay_matches_eager_launches():
+    # CG epochs are recorded once as HIP graphs and replayed many times per
+    # solve; eager (non-graph) launches of the same kernels must give the same
+    # bits, for several solves in a row with host work in between
+    import os
+
+    dims = (8, 8, 8, 8)
+    U = inputs.smooth_su3(dims, 0.5, 131)
+    srcs = [inputs.gaussian_source(dims, 132 + i) for i in range(3)]
+    results = {}
+    for mode in ("1", "0"):
+        os.environ["STAG_GRAPHS"] = mode
+        try:
+            with binding.Context(device=0, arena_bytes=256 << 20) as ctx:
+                f = ctx.set_gauge(dims, U)
+                out = []
+                for prec in (binding.FP64, binding.FP32_RU, binding.FP16_RU):
+                    for src in srcs:
+                        x, _, info = solve(ctx, f, src, mass=0.05, precision=prec)
+                        out.append((x, info["iters"], info["reliable_updates"]))
+                results[mode] = out
+        finally:
+            del os.environ["STAG_GRAPHS"]
+    for (xg, ig, rg), (xe, ie, re_) in zip(results["1"], results["0"]):
+        assert ig == ie and rg == re_ and np.array_equal(xg, xe)

@@ -1,0 +1,208 @@
+"""GPU parity of the HIP D_slash against the CPU oracle.
+
+Bar (FP64): per site, ||D_gpu chi(x) - D_oracle chi(x)||_2 <= 1e-13 * max(||D_oracle chi(x)||_2, 1e-3 * RMS site
+norm).  Sizes span several tiles and ragged tails; the 16^4 case is the
+benchmark's workload in the benchmark's launch configuration (the tuned
+kernel), compared on every site; the 32^4 case is compared on sampled sites."""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1311_2719_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-13
+
+
+def site_err(got, ref):
+    n = np.linalg.norm(ref, axis=1)
+    floor = 1e-3 * np.sqrt(np.mean(n ** 2))
+    return np.max(np.linalg.norm(got - ref, axis=1) / np.maximum(n, floor))
+
+
+def apply(ctx, f, chi_lex, **kw):
+    b = ctx.pack(f, chi_lex)
+    out = ctx.new_fermion(f)
+    ctx.dslash(f, b, out, **kw)
+    return ctx.unpack(f, out).cpu().numpy()
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 4, 4, 4), (2, 4, 6, 8), (6, 4, 2, 10), (8, 8, 8, 8)])
+@pytest.mark.parametrize("kind", ["haar", "smooth"])
+def test_dslash_matches_oracle(gpu_ctx, dims, kind):
+    U = inputs.haar_su3(dims, 11) if kind == "haar" else inputs.smooth_su3(dims, 0.5, 12)
+    chi = inputs.gaussian_source(dims, 13)
+    f = gpu_ctx.set_gauge(dims, U)
+    try:
+        got = apply(gpu_ctx, f, chi)
+        assert site_err(got, oracle.dslash(dims, U, chi)) <= TOL
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
+def test_periodic_t(gpu_ctx):
+    dims = (4, 4, 4, 6)
+    U = inputs.haar_su3(dims, 21)
+    chi = inputs.gaussian_source(dims, 22)
+    f = gpu_ctx.set_gauge(dims, U, antiperiodic_t=False)
+    try:
+        got = apply(gpu_ctx, f, chi)
+        assert site_err(got, oracle.dslash(dims, U, chi, antiperiodic_t=False)) <= TOL
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
+@pytest.mark.parametrize("par", [binding.EVEN, binding.ODD])
+def test_site_range_and_accumulate(gpu_ctx, par):
+    # the paper's matrix-vector(offset, local_length, v, w): a ragged range of
+    # one parity, accumulating into v; every other site untouched
+    dims = (4, 6, 4, 6)
+    V = int(np.prod(dims))
+    U = inputs.haar_su3(dims, 31)
+    chi = inputs.gaussian_source(dims, 32)
+    base = inputs.gaussian_source(dims, 33)
+    f = gpu_ctx.set_gauge(dims, U)
+    try:
+        b = gpu_ctx.pack(f, chi)
+        out = gpu_ctx.pack(f, base)
+        off, cnt = 37, 101
+        gpu_ctx.dslash(f, b, out, out_parity=par, offset=off, count=cnt, accumulate=True)
+        got = gpu_ctx.unpack(f, out).cpu().numpy()
+        ref_full = oracle.dslash(dims, U, chi)
+        # lexicographic sites of checkerboard indices [off, off+cnt) of parity par
+        lex = np.arange(V)
+        x = lex % dims[0]
+        y = (lex // dims[0]) % dims[1]
+        z = (lex // (dims[0] * dims[1])) % dims[2]
+        t = lex // (dims[0] * dims[1] * dims[2])
+        p = (x + y + z + t) & 1
+        cb = lex >> 1
+        inr = (p == par) & (cb >= off) & (cb < off + cnt)
+        assert inr.sum() == cnt
+        want = base.copy()
+        want[inr] += ref_full[inr]
+        assert np.array_equal(got[~inr], base[~inr])
+        assert site_err(got[inr] - base[inr], ref_full[inr]) <= 1e-12
+        # count = -1 runs to the end of the parity; count = 0 is a no-op
+        out2 = gpu_ctx.new_fermion(f)
+        gpu_ctx.dslash(f, b, out2, out_parity=par, offset=5, count=-1)
+        got2 = gpu_ctx.unpack(f, out2).cpu().numpy()
+        sel = (p == par) & (cb >= 5)
+        assert site_err(got2[sel], ref_full[sel]) <= TOL
+        assert not np.any(got2[~sel])
+        gpu_ctx.dslash(f, b, out2, out_parity=par, offset=V // 2, count=0)
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
+@pytest.mark.parametrize("cfg", ["1,64,1,0,0", "2,128,1,1,1", "4,256,1,0,1", "8,64,1,1,0", "8,256,1,0,1"])
+def test_every_kernel_shape(cfg):
+    # the tuner may pick any lanes-per-site / block / table / XCD-order
+    # combination: each must give the same operator
+    dims = (6, 4, 4, 10)
+    U = inputs.haar_su3(dims, 41)
+    chi = inputs.gaussian_source(dims, 42)
+    ref = oracle.dslash(dims, U, chi)
+    os.environ["STAG_KERNEL_CFG"] = cfg
+    try:
+        with binding.Context(device=0, arena_bytes=64 << 20) as ctx:
+            f = ctx.set_gauge(dims, U)
+            assert ctx.tune_info(f)["lanes_per_site"] == int(cfg.split(",")[0])
+            assert site_err(apply(ctx, f, chi), ref) <= TOL
+    finally:
+        del os.environ["STAG_KERNEL_CFG"]
+
+
+def test_anti_hermitian_on_gpu(gpu_ctx):
+    dims = (8, 8, 8, 8)
+    U = inputs.haar_su3(dims, 51)
+    psi = inputs.gaussian_source(dims, 52)
+    chi = inputs.gaussian_source(dims, 53)
+    f = gpu_ctx.set_gauge(dims, U)
+    try:
+        lhs = np.vdot(psi, apply(gpu_ctx, f, chi))
+        rhs = -np.vdot(apply(gpu_ctx, f, psi), chi)
+        assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
+def test_full_size_16(gpu_ctx):
+    # the benchmark's D_slash workload: 16^4, eps = 0.3, seed 102, every site
+    dims = (16, 16, 16, 16)
+    U = inputs.smooth_su3(dims, 0.3, 102)
+    chi = inputs.gaussian_source(dims, 202)
+    f = gpu_ctx.set_gauge(dims, U)
+    try:
+        assert site_err(apply(gpu_ctx, f, chi), oracle.dslash(dims, U, chi)) <= TOL
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
+def test_full_size_32_sampled(gpu_ctx):
+    dims = (32, 32, 32, 32)
+    V = int(np.prod(dims))
+    U = inputs.smooth_su3(dims, 0.5, 103)
+    chi = inputs.gaussian_source(dims, 203)
+    f = gpu_ctx.set_gauge(dims, U)
+    try:
+        got = apply(gpu_ctx, f, chi)
+        rng = np.random.default_rng(7)
+        sites = np.unique(np.concatenate([rng.integers(0, V, 4000), [0, 1, V - 2, V - 1],
+                                          np.arange(0, V, V // 64)]))
+        ref = oracle.dslash_sites(dims, U, chi, sites)
+        rms = np.sqrt(np.mean(np.linalg.norm(ref, axis=1) ** 2))
+        n = np.linalg.norm(ref, axis=1)
+        err = np.max(np.linalg.norm(got[sites] - ref, axis=1) / np.maximum(n, 1e-3 * rms))
+        assert err <= TOL
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
+def test_errors(gpu_ctx):
+    dims = (4, 4, 4, 4)
+    f = gpu_ctx.set_gauge(dims, inputs.unit_links(dims))
+    try:
+        b = gpu_ctx.new_fermion(f)
+        o = gpu_ctx.new_fermion(f)
+        with pytest.raises(binding.StagError) as e:
+            gpu_ctx.dslash(f, b, o, out_parity=3)
+        assert e.value.code == binding.EINVAL
+        with pytest.raises(binding.StagError) as e:
+            gpu_ctx.dslash(f, b, o, out_parity=0, offset=100, count=100)
+        assert e.value.code == binding.EINVAL
+        with pytest.raises(binding.StagError) as e:
+            gpu_ctx.dslash(f, b, b)
+        assert e.value.code == binding.EINVAL
+        with pytest.raises(binding.StagError) as e:
+            gpu_ctx.dslash(binding.Field(9999, dims), b, o)
+        assert e.value.code == binding.ENOENT
+        with pytest.raises(binding.StagError) as e:
+            gpu_ctx.set_gauge((3, 4, 4, 4), inputs.unit_links((3, 4, 4, 4)))
+        assert e.value.code == binding.EINVAL
+        bad = inputs.unit_links(dims)
+        bad[17, 2, 1, 1] = np.nan
+        with pytest.raises(binding.StagError) as e:
+            gpu_ctx.set_gauge(dims, bad)
+        assert e.value.code == binding.ENONFINITE
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
+def test_links_from_device_and_arena_accounting(gpu_ctx):
+    dims = (4, 4, 4, 8)
+    U = inputs.haar_su3(dims, 61)
+    chi = inputs.gaussian_source(dims, 62)
+    used0, total = gpu_ctx.arena_usage()
+    f = gpu_ctx.set_gauge(dims, torch.from_numpy(U).cuda())
+    used1, _ = gpu_ctx.arena_usage()
+    # FP64 + FP32 + FP16 links with back-links (1152 + 576 + 288 B/site) + tables (32 B/site)
+    assert used1 - used0 >= 2048 * int(np.prod(dims))
+    assert site_err(apply(gpu_ctx, f, chi), oracle.dslash(dims, U, chi)) <= TOL
+    gpu_ctx.free_gauge(f)
+    assert gpu_ctx.arena_usage()[0] == used0
