@@ -5,6 +5,7 @@
 #include <map>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 
 #include "batch.hpp"
@@ -30,6 +31,9 @@ Batch::~Batch()
         (void)hipStreamDestroy(cap_stream_);
     if (snap_ev_)
         (void)hipEventDestroy(snap_ev_);
+    for (auto &e : tune_ev_)
+        if (e)
+            (void)hipEventDestroy(e);
     if (stage_ev_)
         (void)hipEventDestroy(stage_ev_);
     if (stage_)
@@ -48,6 +52,7 @@ size_t Batch::workspace_bytes(const Geom &g, int prec, int slots, int pstride)
     b += align256(nsys * 3 * Vh * 16);                           // tmp
     b += align256(nsys * sizeof(void *)) * 2;                    // pointer tables
     b += align256(nsys * sizeof(SysState));
+    b += align256(nsys * sizeof(int));                           // tile order
     b += align256(nsys * (size_t)pstride * 2 * sizeof(double));  // partials
     return b;
 }
@@ -55,12 +60,9 @@ size_t Batch::workspace_bytes(const Geom &g, int prec, int slots, int pstride)
 int Batch::create()
 {
     const Geom &g = f_->g;
-    cfg_ = tune_config(ctx_, f_.get(), prec_, S_, s_);
     cfg64_ = tune_config(ctx_, f_.get(), 0, 1, s_);
-    if (S_ % cfg_.rtile != 0)
-        cfg_.rtile = 1;
-    pstride_ = std::max(std::max(blocks_for(g.Vh, cfg_.lps, cfg_.block), blocks_for(g.Vh, cfg64_.lps, cfg64_.block)),
-                        blocks_for(g.Vh, 1, 256));
+    // room for the partials of every kernel shape the CG tuner may try
+    pstride_ = std::max(blocks_for(g.Vh, 8, 64), blocks_for(g.Vh, cfg64_.lps, cfg64_.block));
     pstride_ = (pstride_ + 63) & ~63;
     bytes_ = workspace_bytes(g, prec_, S_, pstride_);
     mem_ = ctx_->arena.alloc(bytes_);
@@ -83,13 +85,15 @@ int Batch::create()
     xhi_d_ = (dbl2 **)take(nsys * sizeof(void *));
     b_d_ = (const dbl2 **)take(nsys * sizeof(void *));
     st_d_ = (SysState *)take(nsys * sizeof(SysState));
+    perm_d_ = (int *)take(nsys * sizeof(int));
     partials_ = (double *)take(nsys * (size_t)pstride_ * 2 * sizeof(double));
 
-    const size_t host_bytes = 2 * nsys * sizeof(SysState) + 2 * nsys * sizeof(void *);
+    const size_t host_bytes = 2 * nsys * sizeof(SysState) + 2 * nsys * sizeof(void *) + nsys * sizeof(int);
     STAG_HIP_CHECK(hipHostMalloc((void **)&stage_, host_bytes, hipHostMallocDefault));
     snap_ = stage_ + nsys;
     xhi_h_ = (dbl2 **)(snap_ + nsys);
     b_h_ = (const dbl2 **)(xhi_h_ + nsys);
+    perm_h_ = (int *)(b_h_ + nsys);
     memset(stage_, 0, host_bytes);
     if (const char *e = getenv("STAG_GRAPHS"))
         use_graphs_ = e[0] != '0';
@@ -101,9 +105,169 @@ int Batch::create()
     STAG_HIP_CHECK(hipMemcpyAsync(st_d_, stage_, nsys * sizeof(SysState), hipMemcpyHostToDevice, s_));
     STAG_HIP_CHECK(hipMemcpyAsync(xhi_d_, xhi_h_, nsys * sizeof(void *), hipMemcpyHostToDevice, s_));
     STAG_HIP_CHECK(hipMemcpyAsync(b_d_, b_h_, nsys * sizeof(void *), hipMemcpyHostToDevice, s_));
+    for (size_t j = 0; j < nsys; ++j)
+        perm_h_[j] = (int)j;
+    perm_last_.assign(perm_h_, perm_h_ + nsys);
+    STAG_HIP_CHECK(hipMemcpyAsync(perm_d_, perm_h_, nsys * sizeof(int), hipMemcpyHostToDevice, s_));
+    STAG_HIP_CHECK(hipEventRecord(stage_ev_, s_));
+    stage_busy_ = true;
+    // kernel shape for this (field, precision, slots): tuned on this workspace
+    const uint64_t key = ((uint64_t)1 << 40) | ((uint64_t)prec_ << 32) | (uint32_t)S_;
+    bool have = false;
+    {
+        std::lock_guard<std::mutex> lk(ctx_->mu);
+        auto it = f_->tuned.find(key);
+        if (it != f_->tuned.end()) {
+            cfg_ = it->second;
+            have = true;
+        }
+    }
+    if (!have) {
+        cfg_ = tune_cg();
+        std::lock_guard<std::mutex> lk(ctx_->mu);
+        f_->tuned[key] = cfg_;
+    }
+    return STAG_OK;
+}
+
+int Batch::set_running(const std::vector<char> &running)
+{
+    const int n = nsys();
+    std::vector<int> order(n, -1);
+    for (int par = 0; par < 2; ++par) {
+        int k = par * S_;
+        for (int i = 0; i < S_; ++i)
+            if (running[par * S_ + i])
+                order[k++] = par * S_ + i;
+    }
+    if (order == perm_last_)
+        return STAG_OK;
+    if (stage_busy_) {
+        (void)hipEventSynchronize(stage_ev_);
+        stage_busy_ = false;
+    }
+    memcpy(perm_h_, order.data(), n * sizeof(int));
+    perm_last_ = order;
+    STAG_HIP_CHECK(hipMemcpyAsync(perm_d_, perm_h_, n * sizeof(int), hipMemcpyHostToDevice, s_));
     STAG_HIP_CHECK(hipEventRecord(stage_ev_, s_));
     stage_busy_ = true;
     return STAG_OK;
+}
+
+// Time one K1 + K2 pass with every system running on zeroed vectors.
+double Batch::time_cg_config(const KernelCfg &c)
+{
+    const CgLaunchTable &t = cg_table(prec_);
+    CgArgs a = args();
+    for (int par = 0; par < 2; ++par)
+        a.nbr[par] = c.tables ? f_->nbr_for(par) : nullptr;
+    a.remap = c.remap;
+    dim3 grid((unsigned)blocks_for(f_->g.Vh, c.lps, c.block), (unsigned)(nsys() / c.rtile)), blk(c.block);
+    if (t.ap(c.lps, c.rtile, grid, blk, s_, a) != hipSuccess || t.update(c.lps, c.rtile, grid, blk, s_, a) != hipSuccess)
+        return 1e30;
+    const int reps = 3;
+    (void)hipEventRecord(tune_ev_[0], s_);
+    for (int i = 0; i < reps; ++i) {
+        (void)t.ap(c.lps, c.rtile, grid, blk, s_, a);
+        (void)t.update(c.lps, c.rtile, grid, blk, s_, a);
+    }
+    (void)hipEventRecord(tune_ev_[1], s_);
+    if (hipEventSynchronize(tune_ev_[1]) != hipSuccess)
+        return 1e30;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, tune_ev_[0], tune_ev_[1]);
+    return ms / reps;
+}
+
+KernelCfg Batch::tune_cg()
+{
+    KernelCfg best;
+    best.lps = 1;
+    best.block = 256;
+    best.rtile = 1;
+    best.tables = 0;
+    best.remap = 1;
+    const CgLaunchTable &t = cg_table(prec_);
+    for (int i = 0; i < t.n_rtiles; ++i)
+        if (S_ % t.rtiles[i] == 0)
+            best.rtile = std::max(best.rtile, t.rtiles[i]);
+    const char *env = getenv("STAG_KERNEL_CFG");
+    if (env && *env) {
+        KernelCfg c;
+        if (sscanf(env, "%d,%d,%d,%d,%d", &c.lps, &c.block, &c.rtile, &c.tables, &c.remap) == 5 &&
+            (c.lps == 1 || c.lps == 2 || c.lps == 4 || c.lps == 8) && c.block >= 64 && c.block <= 256 &&
+            c.block % 64 == 0 && c.rtile > 0 && S_ % c.rtile == 0)
+            return c;
+        return best;
+    }
+    const char *tenv = getenv("STAG_TUNE");
+    if (tenv && tenv[0] == '0')
+        return best;
+    // every system running, zeroed vectors, x pointed at the FP64 work vector
+    const size_t nsys = 2 * (size_t)S_, Vh = f_->g.Vh;
+    std::vector<SysState> st(nsys);
+    memset(st.data(), 0, nsys * sizeof(SysState));
+    for (auto &x : st) {
+        x.phase = PH_RUN;
+        x.mass2 = 1e-4;
+    }
+    std::vector<dbl2 *> xs(nsys);
+    for (size_t j = 0; j < nsys; ++j)
+        xs[j] = tmp_ + j * 3 * Vh;
+    const bool verbose = getenv("STAG_TUNE_VERBOSE") != nullptr;
+    if (hipMemcpyAsync(st_d_, st.data(), nsys * sizeof(SysState), hipMemcpyHostToDevice, s_) != hipSuccess ||
+        hipMemcpyAsync(xhi_d_, xs.data(), nsys * sizeof(void *), hipMemcpyHostToDevice, s_) != hipSuccess ||
+        hipMemsetAsync(p_[0], 0, (char *)tmp_ - (char *)p_[0] + nsys * 3 * Vh * 16, s_) != hipSuccess ||
+        hipEventCreate(&tune_ev_[0]) != hipSuccess || hipEventCreate(&tune_ev_[1]) != hipSuccess) {
+        (void)hipStreamSynchronize(s_);
+        return best;
+    }
+    double best_t = 1e30;
+    const int lps_c[4] = {1, 2, 4, 8}, blk_c[3] = {64, 128, 256};
+    for (int i = 0; i < t.n_rtiles; ++i) {
+        const int R = t.rtiles[i];
+        if (S_ % R)
+            continue;
+        for (int L : lps_c)
+            for (int B : blk_c) {
+                KernelCfg c;
+                c.lps = L;
+                c.block = B;
+                c.rtile = R;
+                c.tables = 0;
+                c.remap = 1;
+                const double ms = time_cg_config(c);
+                if (verbose)
+                    fprintf(stderr, "[stag tune cg] V=%d prec=%d slots=%d lps=%d block=%d rtile=%d: %.2f us\n",
+                            2 * f_->g.Vh, prec_, S_, L, B, R, ms * 1e3);
+                if (ms < best_t * 0.99) {
+                    best_t = ms;
+                    best = c;
+                }
+            }
+    }
+    for (int T = 0; T < 2; ++T)
+        for (int X = 0; X < 2; ++X) {
+            KernelCfg c = best;
+            c.tables = T;
+            c.remap = X;
+            const double ms = time_cg_config(c);
+            if (verbose)
+                fprintf(stderr, "[stag tune cg] V=%d prec=%d slots=%d lps=%d block=%d rtile=%d tables=%d remap=%d: "
+                                "%.2f us\n", 2 * f_->g.Vh, prec_, S_, c.lps, c.block, c.rtile, T, X, ms * 1e3);
+            if (ms < best_t * 0.99) {
+                best_t = ms;
+                best = c;
+            }
+        }
+    // back to idle systems and empty pointer tables
+    memset(st.data(), 0, nsys * sizeof(SysState));
+    std::fill(xs.begin(), xs.end(), nullptr);
+    (void)hipMemcpyAsync(st_d_, st.data(), nsys * sizeof(SysState), hipMemcpyHostToDevice, s_);
+    (void)hipMemcpyAsync(xhi_d_, xs.data(), nsys * sizeof(void *), hipMemcpyHostToDevice, s_);
+    (void)hipStreamSynchronize(s_);
+    (void)hipGetLastError();
+    return best;
 }
 
 void Batch::stage_system(int j, const stag_cg_params &p, const double *b_half, double *x_half)
@@ -183,6 +347,7 @@ CgArgs Batch::args() const
     a.xhi = xhi_d_;
     a.b = b_d_;
     a.st = st_d_;
+    a.perm = perm_d_;
     a.partials = partials_;
     a.S = S_;
     a.pstride = pstride_;
@@ -478,6 +643,11 @@ int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs, con
                 done = false;
         }
         if (!done) {
+            std::vector<char> running(B.nsys());
+            for (int j = 0; j < B.nsys(); ++j)
+                running[j] = B.state(j).phase == PH_RUN || B.state(j).phase == PH_INIT;
+            if ((rc = B.set_running(running)) != STAG_OK)
+                return rc;
             const int rem = estimate_remaining(B, prev);
             E = 2;
             while (E * 2 <= std::min(Emax, rem / 2))

@@ -3,6 +3,8 @@
 // side, two parity systems), stag_cg_solve_batch and the serving scheduler.
 #pragma once
 
+#include <vector>
+
 #include "cg_launch.hpp"
 #include "runtime.hpp"
 
@@ -41,9 +43,15 @@ public:
     int wait_snapshot();
     bool snapshot_ready();
     const SysState &state(int j) const { return snap_[j]; }
+    // Order in which the tiles take the systems: the systems flagged in
+    // `running` first (per parity), the rest left out.  Stream-ordered: applies
+    // to the kernels enqueued after this call.
+    int set_running(const std::vector<char> &running);
 
 private:
     int launch_iter(bool with_ru, hipStream_t st);
+    KernelCfg tune_cg();
+    double time_cg_config(const KernelCfg &c);
     hipError_t launch_fin(int role, int nblk, const CgArgs &a, hipStream_t st);
     CgArgs args() const;
 
@@ -62,13 +70,17 @@ private:
     dbl2 **xhi_d_ = nullptr;
     const dbl2 **b_d_ = nullptr;
     SysState *st_d_ = nullptr;
+    int *perm_d_ = nullptr;
     double *partials_ = nullptr;
     // pinned host memory
     SysState *stage_ = nullptr;   // [nsys] staged initial states
     SysState *snap_ = nullptr;    // [nsys] last snapshot
     dbl2 **xhi_h_ = nullptr;
     const dbl2 **b_h_ = nullptr;
+    int *perm_h_ = nullptr;
+    std::vector<int> perm_last_;
     hipEvent_t snap_ev_ = nullptr, stage_ev_ = nullptr;
+    hipEvent_t tune_ev_[2] = {nullptr, nullptr};
     bool stage_busy_ = false;
     // epochs recorded once as HIP graphs (kernel nodes only) and replayed
     bool use_graphs_ = true;

@@ -22,7 +22,12 @@
 //
 // Systems: nsys = 2*S, system j has parity j / S (its x, r, p live on that
 // parity; ap and t on the other).  A tile is R systems of one parity that are
-// processed together so each link entry is loaded once for all of them.
+// processed together so each link entry is loaded once for all of them; the
+// tiles take their systems from a per-parity list (perm) that the host
+// compacts between epochs, so the number of tiles that read links follows the
+// number of systems still running.  A system's partial sums depend only on
+// the sites of each block, not on its tile, so compaction does not change
+// results.
 #pragma once
 
 #include "hop.hpp"
@@ -71,6 +76,7 @@ struct CgArgs {
     dbl2 *const *xhi;          // [nsys] parity half of the caller's x
     const dbl2 *const *b;      // [nsys] parity half of the caller's b
     SysState *st;              // [nsys]
+    const int *perm;           // [2][S] systems of each parity in tile order, -1 = none
     double *partials;          // [nsys][2][pstride]
     int S;                     // systems per parity
     int pstride;
@@ -99,11 +105,12 @@ template <class P> __device__ __forceinline__ cplx<typename P::real> load_colour
     }
 }
 
-__device__ __forceinline__ void tile_of(const CgArgs &a, int tile, int R, int &par, int &j0)
+// Parity of a tile and the offset of its first entry in the system list.
+__device__ __forceinline__ void tile_of(const CgArgs &a, int tile, int R, int &par, int &k0)
 {
     const int tpp = a.S / R;
     par = tile / tpp;
-    j0 = par * a.S + (tile % tpp) * R;
+    k0 = par * a.S + (tile % tpp) * R;
 }
 
 __device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v < INFINITY; }
@@ -121,17 +128,20 @@ __global__ void __launch_bounds__(256) k_cg_ap(CgArgs a)
     using real = typename P::real;
     using v2 = typename vec2_of<real>::type;
     __shared__ double lds[2 * R * 4];
-    int par, j0;
-    tile_of(a, blockIdx.y, R, par, j0);
+    int par, k0;
+    tile_of(a, blockIdx.y, R, par, k0);
     const int pout = 1 - par;
+    int js[R];
     bool act[R];
     real beta[R];
     int pc[R];
     bool any = false;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const SysState &st = a.st[j0 + r];
-        act[r] = st.phase == PH_RUN && !st.ru_pending;
+        const int j = a.perm[k0 + r];
+        js[r] = j < 0 ? 0 : j;
+        const SysState &st = a.st[js[r]];
+        act[r] = j >= 0 && st.phase == PH_RUN && !st.ru_pending;
         beta[r] = (real)st.beta;
         pc[r] = st.pcur;
         any |= act[r];
@@ -153,7 +163,7 @@ __global__ void __launch_bounds__(256) k_cg_ap(CgArgs a)
             for (int c = 0; c < 3; ++c)
                 acc[r][c] = czero<real>();
         auto load = [&](int r, int n, cplx<real> *chi) {
-            const int j = j0 + r;
+            const int j = js[r];
             const v2 *rv = (const v2 *)a.r + (size_t)j * 3 * Vh;
             cplx<real> pv[3];
             P::load_spinor(spin_at<P>(a.p[pc[r]], j, Vh), Vh, n, pv);
@@ -170,7 +180,7 @@ __global__ void __launch_bounds__(256) k_cg_ap(CgArgs a)
         for (int r = 0; r < R; ++r) {
             if (!act[r])
                 continue;
-            const int j = j0 + r;
+            const int j = js[r];
             void *out = spin_at<P>(a.ap, j, Vh);
             const v2 *rv = (const v2 *)a.r + (size_t)j * 3 * Vh;
             const void *pold = spin_at<P>(a.p[pc[r]], j, Vh);
@@ -216,8 +226,11 @@ __global__ void __launch_bounds__(256) k_cg_ap(CgArgs a)
     }
     double tot;
     block_sum_multi<2 * R>(nrm, lds, tot);
-    if (threadIdx.x < 2 * R)
-        partial_slot(a, j0 + (int)threadIdx.x % R, (int)threadIdx.x / R)[blockIdx.x] = tot;
+    if (threadIdx.x < 2 * R) {
+        const int j = a.perm[k0 + (int)threadIdx.x % R];
+        if (j >= 0)
+            partial_slot(a, j, (int)threadIdx.x / R)[blockIdx.x] = tot;
+    }
 }
 
 // ---- K2: Ap = m^2 p - D ap, x += alpha p, r -= alpha Ap ------------------------
@@ -228,14 +241,17 @@ __global__ void __launch_bounds__(256) k_cg_update(CgArgs a)
     using real = typename P::real;
     using v2 = typename vec2_of<real>::type;
     __shared__ double lds[R * 4];
-    int par, j0;
-    tile_of(a, blockIdx.y, R, par, j0);
+    int par, k0;
+    tile_of(a, blockIdx.y, R, par, k0);
+    int js[R];
     bool act[R];
     bool any = false;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const SysState &st = a.st[j0 + r];
-        act[r] = st.phase == PH_RUN && !st.ru_pending;
+        const int j = a.perm[k0 + r];
+        js[r] = j < 0 ? 0 : j;
+        const SysState &st = a.st[js[r]];
+        act[r] = j >= 0 && st.phase == PH_RUN && !st.ru_pending;
         any |= act[r];
     }
     if (!any)
@@ -254,14 +270,14 @@ __global__ void __launch_bounds__(256) k_cg_update(CgArgs a)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 acc[r][c] = czero<real>();
-        auto load = [&](int r, int n, cplx<real> *chi) { P::load_spinor(spin_at<P>(a.ap, j0 + r, Vh), Vh, n, chi); };
+        auto load = [&](int r, int n, cplx<real> *chi) { P::load_spinor(spin_at<P>(a.ap, js[r], Vh), Vh, n, chi); };
         hop_accumulate<P, LPS, R>(a.g, (const typename P::link_t *)a.links[par], a.nbr[par], par, s, sub, act, acc,
                                   load);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (!act[r])
                 continue;
-            const int j = j0 + r;
+            const int j = js[r];
             const SysState &st = a.st[j];
             const real m2 = (real)st.mass2, alpha = (real)st.alpha;
             const void *pb = spin_at<P>(a.p[st.pcur], j, Vh);
@@ -293,8 +309,11 @@ __global__ void __launch_bounds__(256) k_cg_update(CgArgs a)
     }
     double tot;
     block_sum_multi<R>(nrm, lds, tot);
-    if (threadIdx.x < R)
-        partial_slot(a, j0 + (int)threadIdx.x, 0)[blockIdx.x] = tot;
+    if (threadIdx.x < R) {
+        const int j = a.perm[k0 + (int)threadIdx.x];
+        if (j >= 0)
+            partial_slot(a, j, 0)[blockIdx.x] = tot;
+    }
 }
 
 // ---- init: x = 0, r = b, p = r, beta = 0 ------------------------------------------

@@ -46,8 +46,11 @@ template <int LPS, typename T> __device__ __forceinline__ T lane_sum(T v)
 
 // acc[r][a] += sum over this lane's directions of L_d(s)[a][b] in_r(n_d(s))[b],
 // then summed over the LPS lanes of the site.  load(r, n, chi) fetches the
-// input colour vector of right-hand side r at neighbour site n.
-template <class P, int LPS, int R, class Load>
+// input colour vector of right-hand side r at neighbour site n.  LEAN keeps
+// the direction loop rolled (one direction's loads in flight at a time), for
+// rarely taken paths that must not raise the register budget of the kernel
+// they live in.
+template <class P, int LPS, int R, class Load, bool LEAN = false>
 __device__ __forceinline__ void hop_accumulate(const Geom &g, const typename P::link_t *__restrict__ links,
                                                const int32_t *__restrict__ nbr, int p_out, int s, int sub,
                                                const bool *act, cplx<typename P::real> (*acc)[3], Load load)
@@ -56,8 +59,7 @@ __device__ __forceinline__ void hop_accumulate(const Geom &g, const typename P::
     SiteCoord c;
     if (!nbr)
         c = decode_site(g, p_out, s);
-#pragma unroll
-    for (int j = 0; j < 8 / LPS; ++j) {
+    auto one_direction = [&](int j) {
         const int d = sub + j * LPS;
         const int n = nbr ? nbr[(int64_t)d * g.Vh + s] : neighbour(g, c, s, d);
         cplx<real> U[9];
@@ -77,6 +79,15 @@ __device__ __forceinline__ void hop_accumulate(const Geom &g, const typename P::
                 for (int b = 0; b < 3; ++b)
                     cmac(acc[r][a], U[a * 3 + b], chi[b]);
         }
+    };
+    if constexpr (LEAN) {
+#pragma unroll 1
+        for (int j = 0; j < 8 / LPS; ++j)
+            one_direction(j);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8 / LPS; ++j)
+            one_direction(j);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r)

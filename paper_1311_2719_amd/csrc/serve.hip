@@ -232,6 +232,17 @@ bool Server::step_lane(Lane &l)
             }
         }
         if (B && l.active > 0) {
+            // tiles take only the systems of occupied slots
+            std::vector<char> running(B->nsys(), 0);
+            for (int s = 0; s < B->slots(); ++s) {
+                if (!l.slot[s])
+                    continue;
+                for (int par = 0; par < 2; ++par) {
+                    const int par_req = l.slot[s]->params.parity;
+                    running[par * B->slots() + s] = par_req == STAG_ALL || par_req == par;
+                }
+            }
+            (void)B->set_running(running);
             if (B->enqueue_snapshot() == STAG_OK) {
                 l.snapshot_pending = true;
                 l.epoch_queued = false;

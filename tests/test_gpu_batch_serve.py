@@ -146,3 +146,49 @@ def test_serving_admission_by_memory():
         torch.cuda.synchronize()
         info = ctx.wait(ctx.submit(f, b, x, mass=0.05, precision=binding.FP32_RU))
         assert info["rc"] == binding.ENOMEM
+
+
+def test_serving_limits_and_shutdown():
+    # light-mass 8^4 solves take hundreds of iterations (milliseconds), far
+    # longer than submitting the next request (microseconds)
+    dims = (8, 8, 8, 8)
+    U = inputs.smooth_su3(dims, 0.5, 181)
+    with binding.Context(device=0, arena_bytes=256 << 20) as ctx:
+        ctx.serve_config(slots_per_field=2, epoch_iters=4, queue_capacity=3)
+        f = ctx.set_gauge(dims, U)
+        srcs = [inputs.gaussian_source(dims, 190 + i) for i in range(4)]
+        bs = [ctx.pack(f, s) for s in srcs]
+        xs = [ctx.new_fermion(f) for _ in srcs]
+        torch.cuda.synchronize()
+        tickets = [ctx.submit(f, bs[i], xs[i], mass=0.01, tol=1e-10) for i in range(3)]
+        # the queue holds at most 3 outstanding requests
+        with pytest.raises(binding.StagError) as e:
+            ctx.submit(f, bs[3], xs[3], mass=0.01)
+        assert e.value.code == binding.EAGAIN
+        # a field with pending requests cannot be freed
+        try:
+            ctx.free_gauge(f)
+            freed = True
+        except binding.StagError as err:
+            assert err.code == binding.EBUSY
+            freed = False
+        for i, t in enumerate(tickets):
+            info = ctx.wait(t)
+            assert info["status"] == 0
+            x = ctx.unpack(f, xs[i]).cpu().numpy()
+            assert oracle.true_residual(dims, U, 0.01, srcs[i], x) <= 1e-10
+            assert ctx.poll(t)["status"] == 0  # a completed ticket can be polled again
+            ctx.release(t)
+        with pytest.raises(binding.StagError):
+            ctx.serve_config(slots_per_field=4)  # serving already started
+        if not freed:
+            ctx.free_gauge(f)
+    # requests still queued when the context is destroyed end cancelled
+    with binding.Context(device=0, arena_bytes=64 << 20) as ctx:
+        f = ctx.set_gauge(dims, U)
+        b = ctx.pack(f, inputs.gaussian_source(dims, 199))
+        xs = [ctx.new_fermion(f) for _ in range(8)]
+        torch.cuda.synchronize()
+        ts = [ctx.submit(f, b, x, mass=0.1) for x in xs]
+        ctx.wait(ts[0])
+    # (the context is gone: the remaining tickets were completed or cancelled)

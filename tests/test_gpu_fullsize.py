@@ -1,0 +1,79 @@
+"""GPU parity at the benchmark workloads' full sizes, in the launch
+configuration the benchmark times (the tuned kernels): the 32^4 mixed-precision
+solves and the 24^4 twelve-right-hand-side batch.  Checked by properties that
+hold at any size: the FP64 true residual recomputed by the oracle, D_slash on
+sampled sites, and the FP64 solution of the same system."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1311_2719_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def field32():
+    dims = (32, 32, 32, 32)
+    U = inputs.smooth_su3(dims, 0.5, 103)
+    b = inputs.gaussian_source(dims, 203)
+    return dims, U, b
+
+
+@pytest.mark.parametrize("prec", [binding.FP64, binding.FP32_RU, binding.FP16_RU])
+def test_config2_32_mixed(gpu_ctx, field32, prec):
+    dims, U, b = field32
+    m, tol = 0.01, 1e-10
+    f = gpu_ctx.set_gauge(dims, U)
+    try:
+        bd = gpu_ctx.pack(f, b)
+        x = gpu_ctx.new_fermion(f)
+        info = gpu_ctx.cg_solve(f, bd, x, mass=m, tol=tol, precision=prec)
+        torch.cuda.synchronize()
+        xs = gpu_ctx.unpack(f, x).cpu().numpy()
+        tr = oracle.true_residual(dims, U, m, b, xs)
+        print("32^4 precision %d: iters %d, reliable updates %d, true residual %.3e (GPU %.3e)"
+              % (prec, info["iters"], info["reliable_updates"], tr, info["true_rel_resid"]))
+        assert info["status"] == 0 and tr <= tol
+        assert abs(tr - info["true_rel_resid"]) <= 1e-3 * tol
+        # D_slash of the solution on sampled sites: full-size operator check
+        V = int(np.prod(dims))
+        sites = np.random.default_rng(3).integers(0, V, 2000)
+        y = gpu_ctx.new_fermion(f)
+        gpu_ctx.dslash(f, x, y)
+        ys = gpu_ctx.unpack(f, y).cpu().numpy()
+        ref = oracle.dslash_sites(dims, U, xs, sites)
+        assert np.max(np.abs(ys[sites] - ref)) <= 1e-13 * np.max(np.abs(ref))
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
+def test_config3_24_batch(gpu_ctx):
+    dims, tol, n = (24, 24, 24, 24), 1e-10, 12
+    U = inputs.smooth_su3(dims, 0.5, 104)
+    masses = inputs.masses_uniform(0.01, 0.2, n)
+    f = gpu_ctx.set_gauge(dims, U)
+    try:
+        srcs = [inputs.gaussian_source(dims, 2040 + i) for i in range(n)]
+        bs = [gpu_ctx.pack(f, s) for s in srcs]
+        xs = [gpu_ctx.new_fermion(f) for _ in range(n)]
+        plist = [binding.params(float(mm), tol=tol, precision=binding.FP32_RU) for mm in masses]
+        infos = gpu_ctx.cg_solve_batch(f, bs, xs, plist)
+        torch.cuda.synchronize()
+        for i in (0, 5, 11):  # lightest, middle, heaviest mass
+            x = gpu_ctx.unpack(f, xs[i]).cpu().numpy()
+            assert infos[i]["status"] == 0
+            assert oracle.true_residual(dims, U, masses[i], srcs[i], x) <= tol
+            # the same system in plain FP64, alone
+            xa = gpu_ctx.new_fermion(f)
+            gpu_ctx.cg_solve(f, bs[i], xa, mass=float(masses[i]), tol=tol)
+            assert rel(x, gpu_ctx.unpack(f, xa).cpu().numpy()) < 1e-8
+        assert all(i["status"] == 0 and i["true_rel_resid"] <= tol for i in infos)
+    finally:
+        gpu_ctx.free_gauge(f)
