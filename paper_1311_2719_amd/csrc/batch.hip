@@ -51,18 +51,26 @@ size_t Batch::workspace_bytes(const Geom &g, int prec, int slots, int pstride)
     b += prec == 0 ? 0 : align256(nsys * 3 * Vh * 8);            // x_lo
     b += align256(nsys * 3 * Vh * 16);                           // tmp
     b += align256(nsys * sizeof(void *)) * 2;                    // pointer tables
-    b += align256(nsys * sizeof(SysState));
+    b += align256(nsys * sizeof(SysState)) * 2;                  // two state buffers
     b += align256(nsys * sizeof(int));                           // tile order
-    b += align256(nsys * (size_t)pstride * 2 * sizeof(double));  // partials
+    b += align256(2 * nsys * 3 * (size_t)pstride * sizeof(double));  // partials
     return b;
+}
+
+// Blocks per tile row: enough to cover the sites once, capped so that the
+// partial sums every block reads back in the next kernel's prologue stay small
+// (the kernels stride over the sites when capped).
+int Batch::grid_x(const KernelCfg &c) const
+{
+    const int need = blocks_for(f_->g.Vh, c.lps, c.block);
+    const int cap = std::max(128, 2048 / c.rtile);
+    return std::min(need, cap);
 }
 
 int Batch::create()
 {
     const Geom &g = f_->g;
-    cfg64_ = tune_config(ctx_, f_.get(), 0, 1, s_);
-    // room for the partials of every kernel shape the CG tuner may try
-    pstride_ = std::max(blocks_for(g.Vh, 8, 64), blocks_for(g.Vh, cfg64_.lps, cfg64_.block));
+    pstride_ = std::min(2048, blocks_for(g.Vh, 8, 64));
     pstride_ = (pstride_ + 63) & ~63;
     bytes_ = workspace_bytes(g, prec_, S_, pstride_);
     mem_ = ctx_->arena.alloc(bytes_);
@@ -84,14 +92,15 @@ int Batch::create()
     tmp_ = (dbl2 *)take(nsys * 3 * Vh * 16);
     xhi_d_ = (dbl2 **)take(nsys * sizeof(void *));
     b_d_ = (const dbl2 **)take(nsys * sizeof(void *));
-    st_d_ = (SysState *)take(nsys * sizeof(SysState));
+    st_d_[0] = (SysState *)take(nsys * sizeof(SysState));
+    st_d_[1] = (SysState *)take(nsys * sizeof(SysState));
     perm_d_ = (int *)take(nsys * sizeof(int));
-    partials_ = (double *)take(nsys * (size_t)pstride_ * 2 * sizeof(double));
+    partials_ = (double *)take(2 * nsys * 3 * (size_t)pstride_ * sizeof(double));
 
-    const size_t host_bytes = 2 * nsys * sizeof(SysState) + 2 * nsys * sizeof(void *) + nsys * sizeof(int);
+    const size_t host_bytes = 3 * nsys * sizeof(SysState) + 2 * nsys * sizeof(void *) + nsys * sizeof(int);
     STAG_HIP_CHECK(hipHostMalloc((void **)&stage_, host_bytes, hipHostMallocDefault));
     snap_ = stage_ + nsys;
-    xhi_h_ = (dbl2 **)(snap_ + nsys);
+    xhi_h_ = (dbl2 **)(snap_ + 2 * nsys);
     b_h_ = (const dbl2 **)(xhi_h_ + nsys);
     perm_h_ = (int *)(b_h_ + nsys);
     memset(stage_, 0, host_bytes);
@@ -101,16 +110,9 @@ int Batch::create()
         STAG_HIP_CHECK(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
     STAG_HIP_CHECK(hipEventCreateWithFlags(&snap_ev_, hipEventDisableTiming));
     STAG_HIP_CHECK(hipEventCreateWithFlags(&stage_ev_, hipEventDisableTiming));
-    // every system starts idle
-    STAG_HIP_CHECK(hipMemcpyAsync(st_d_, stage_, nsys * sizeof(SysState), hipMemcpyHostToDevice, s_));
-    STAG_HIP_CHECK(hipMemcpyAsync(xhi_d_, xhi_h_, nsys * sizeof(void *), hipMemcpyHostToDevice, s_));
-    STAG_HIP_CHECK(hipMemcpyAsync(b_d_, b_h_, nsys * sizeof(void *), hipMemcpyHostToDevice, s_));
     for (size_t j = 0; j < nsys; ++j)
         perm_h_[j] = (int)j;
     perm_last_.assign(perm_h_, perm_h_ + nsys);
-    STAG_HIP_CHECK(hipMemcpyAsync(perm_d_, perm_h_, nsys * sizeof(int), hipMemcpyHostToDevice, s_));
-    STAG_HIP_CHECK(hipEventRecord(stage_ev_, s_));
-    stage_busy_ = true;
     // kernel shape for this (field, precision, slots): tuned on this workspace
     const uint64_t key = ((uint64_t)1 << 40) | ((uint64_t)prec_ << 32) | (uint32_t)S_;
     bool have = false;
@@ -127,6 +129,14 @@ int Batch::create()
         std::lock_guard<std::mutex> lk(ctx_->mu);
         f_->tuned[key] = cfg_;
     }
+    // every system starts idle, all systems listed
+    STAG_HIP_CHECK(hipMemcpyAsync(st_d_[0], stage_, nsys * sizeof(SysState), hipMemcpyHostToDevice, s_));
+    STAG_HIP_CHECK(hipMemcpyAsync(st_d_[1], stage_, nsys * sizeof(SysState), hipMemcpyHostToDevice, s_));
+    STAG_HIP_CHECK(hipMemcpyAsync(xhi_d_, xhi_h_, nsys * sizeof(void *), hipMemcpyHostToDevice, s_));
+    STAG_HIP_CHECK(hipMemcpyAsync(b_d_, b_h_, nsys * sizeof(void *), hipMemcpyHostToDevice, s_));
+    STAG_HIP_CHECK(hipMemcpyAsync(perm_d_, perm_h_, nsys * sizeof(int), hipMemcpyHostToDevice, s_));
+    STAG_HIP_CHECK(hipEventRecord(stage_ev_, s_));
+    stage_busy_ = true;
     return STAG_OK;
 }
 
@@ -154,7 +164,7 @@ int Batch::set_running(const std::vector<char> &running)
     return STAG_OK;
 }
 
-// Time one K1 + K2 pass with every system running on zeroed vectors.
+// Time K1 + K2 of one step with every system in a CG step on filled vectors.
 double Batch::time_cg_config(const KernelCfg &c)
 {
     const CgLaunchTable &t = cg_table(prec_);
@@ -162,14 +172,15 @@ double Batch::time_cg_config(const KernelCfg &c)
     for (int par = 0; par < 2; ++par)
         a.nbr[par] = c.tables ? f_->nbr_for(par) : nullptr;
     a.remap = c.remap;
-    dim3 grid((unsigned)blocks_for(f_->g.Vh, c.lps, c.block), (unsigned)(nsys() / c.rtile)), blk(c.block);
-    if (t.ap(c.lps, c.rtile, grid, blk, s_, a) != hipSuccess || t.update(c.lps, c.rtile, grid, blk, s_, a) != hipSuccess)
+    dim3 grid((unsigned)grid_x(c), (unsigned)(nsys() / c.rtile)), blk(c.block);
+    if (t.step1(c.lps, c.rtile, grid, blk, s_, a, 0) != hipSuccess ||
+        t.step2(c.lps, c.rtile, grid, blk, s_, a, 0) != hipSuccess)
         return 1e30;
     const int reps = 3;
     (void)hipEventRecord(tune_ev_[0], s_);
     for (int i = 0; i < reps; ++i) {
-        (void)t.ap(c.lps, c.rtile, grid, blk, s_, a);
-        (void)t.update(c.lps, c.rtile, grid, blk, s_, a);
+        (void)t.step1(c.lps, c.rtile, grid, blk, s_, a, 0);
+        (void)t.step2(c.lps, c.rtile, grid, blk, s_, a, 0);
     }
     (void)hipEventRecord(tune_ev_[1], s_);
     if (hipEventSynchronize(tune_ev_[1]) != hipSuccess)
@@ -203,21 +214,30 @@ KernelCfg Batch::tune_cg()
     const char *tenv = getenv("STAG_TUNE");
     if (tenv && tenv[0] == '0')
         return best;
-    // every system running, zeroed vectors, x pointed at the FP64 work vector
+    // Every system in a CG step; vectors and the partial sums the first
+    // prologue reads filled with a small positive pattern (bytes 0x3f), so the
+    // state stays in CG steps and every kernel does its full work.  x points at
+    // the FP64 work vector.
     const size_t nsys = 2 * (size_t)S_, Vh = f_->g.Vh;
     std::vector<SysState> st(nsys);
     memset(st.data(), 0, nsys * sizeof(SysState));
     for (auto &x : st) {
-        x.phase = PH_RUN;
+        x.mode = M_CG;
         x.mass2 = 1e-4;
+        x.rr = 1.0;
+        x.maxiter = 1 << 30;
+        x.mixed = prec_ != STAG_FP64;
     }
     std::vector<dbl2 *> xs(nsys);
     for (size_t j = 0; j < nsys; ++j)
         xs[j] = tmp_ + j * 3 * Vh;
     const bool verbose = getenv("STAG_TUNE_VERBOSE") != nullptr;
-    if (hipMemcpyAsync(st_d_, st.data(), nsys * sizeof(SysState), hipMemcpyHostToDevice, s_) != hipSuccess ||
+    const size_t vec_bytes = (char *)tmp_ - (char *)p_[0] + nsys * 3 * Vh * 16;
+    if (hipMemcpyAsync(st_d_[0], st.data(), nsys * sizeof(SysState), hipMemcpyHostToDevice, s_) != hipSuccess ||
         hipMemcpyAsync(xhi_d_, xs.data(), nsys * sizeof(void *), hipMemcpyHostToDevice, s_) != hipSuccess ||
-        hipMemsetAsync(p_[0], 0, (char *)tmp_ - (char *)p_[0] + nsys * 3 * Vh * 16, s_) != hipSuccess ||
+        hipMemcpyAsync(perm_d_, perm_h_, nsys * sizeof(int), hipMemcpyHostToDevice, s_) != hipSuccess ||
+        hipMemsetAsync(p_[0], 0x3f, vec_bytes, s_) != hipSuccess ||
+        hipMemsetAsync(partials_, 0x3f, 2 * nsys * 3 * (size_t)pstride_ * sizeof(double), s_) != hipSuccess ||
         hipEventCreate(&tune_ev_[0]) != hipSuccess || hipEventCreate(&tune_ev_[1]) != hipSuccess) {
         (void)hipStreamSynchronize(s_);
         return best;
@@ -260,11 +280,6 @@ KernelCfg Batch::tune_cg()
                 best = c;
             }
         }
-    // back to idle systems and empty pointer tables
-    memset(st.data(), 0, nsys * sizeof(SysState));
-    std::fill(xs.begin(), xs.end(), nullptr);
-    (void)hipMemcpyAsync(st_d_, st.data(), nsys * sizeof(SysState), hipMemcpyHostToDevice, s_);
-    (void)hipMemcpyAsync(xhi_d_, xs.data(), nsys * sizeof(void *), hipMemcpyHostToDevice, s_);
     (void)hipStreamSynchronize(s_);
     (void)hipGetLastError();
     return best;
@@ -279,12 +294,12 @@ void Batch::stage_system(int j, const stag_cg_params &p, const double *b_half, d
     SysState &st = stage_[j];
     memset(&st, 0, sizeof(st));
     if (!b_half || !x_half) {
-        st.phase = PH_IDLE;
+        st.mode = M_IDLE;
         xhi_h_[j] = nullptr;
         b_h_[j] = nullptr;
         return;
     }
-    st.phase = PH_INIT;
+    st.mode = M_INIT;
     st.mass2 = p.mass * p.mass;
     st.tol2 = p.tol * p.tol;
     st.maxiter = p.maxiter;
@@ -299,7 +314,9 @@ void Batch::stage_system(int j, const stag_cg_params &p, const double *b_half, d
 int Batch::upload_and_init(const std::vector<int> &systems)
 {
     for (int j : systems) {
-        STAG_HIP_CHECK(hipMemcpyAsync(st_d_ + j, stage_ + j, sizeof(SysState), hipMemcpyHostToDevice, s_));
+        // the staged state goes into both buffers: the first step reads buffer 0
+        STAG_HIP_CHECK(hipMemcpyAsync(st_d_[0] + j, stage_ + j, sizeof(SysState), hipMemcpyHostToDevice, s_));
+        STAG_HIP_CHECK(hipMemcpyAsync(st_d_[1] + j, stage_ + j, sizeof(SysState), hipMemcpyHostToDevice, s_));
         STAG_HIP_CHECK(hipMemcpyAsync(xhi_d_ + j, xhi_h_ + j, sizeof(void *), hipMemcpyHostToDevice, s_));
         STAG_HIP_CHECK(hipMemcpyAsync(b_d_ + j, b_h_ + j, sizeof(void *), hipMemcpyHostToDevice, s_));
     }
@@ -307,25 +324,11 @@ int Batch::upload_and_init(const std::vector<int> &systems)
     stage_busy_ = true;
     const CgArgs a = args();
     const CgLaunchTable &t = cg_table(prec_);
-    dim3 grid((unsigned)blocks_for(f_->g.Vh, 1, 256), (unsigned)nsys());
-    hipError_t e = t.init(grid, dim3(256), s_, a);
-    if (e == hipSuccess)
-        e = launch_fin(FIN_INIT, (int)grid.x, a, s_);
+    dim3 grid((unsigned)grid_x(cfg_), (unsigned)nsys());
+    hipError_t e = t.init(grid, dim3(cfg_.block), s_, a, cfg_.lps);
     if (e != hipSuccess)
         return set_error(STAG_EHIP, "init launch failed: %s", hipGetErrorString(e));
     return STAG_OK;
-}
-
-hipError_t Batch::launch_fin(int role, int nblk, const CgArgs &a, hipStream_t st)
-{
-    dim3 grid((unsigned)nsys()), block(256);
-    switch (role) {
-    case FIN_INIT: hipLaunchKernelGGL((k_cg_fin<FIN_INIT>), grid, block, 0, st, a, nblk); break;
-    case FIN_AP: hipLaunchKernelGGL((k_cg_fin<FIN_AP>), grid, block, 0, st, a, nblk); break;
-    case FIN_UPDATE: hipLaunchKernelGGL((k_cg_fin<FIN_UPDATE>), grid, block, 0, st, a, nblk); break;
-    default: hipLaunchKernelGGL((k_cg_fin<FIN_RU>), grid, block, 0, st, a, nblk); break;
-    }
-    return hipGetLastError();
 }
 
 CgArgs Batch::args() const
@@ -346,7 +349,8 @@ CgArgs Batch::args() const
     a.tmp = tmp_;
     a.xhi = xhi_d_;
     a.b = b_d_;
-    a.st = st_d_;
+    a.st[0] = st_d_[0];
+    a.st[1] = st_d_[1];
     a.perm = perm_d_;
     a.partials = partials_;
     a.S = S_;
@@ -355,43 +359,26 @@ CgArgs Batch::args() const
     return a;
 }
 
-int Batch::launch_iter(bool with_ru, hipStream_t st)
+int Batch::launch_step(int ver, hipStream_t st)
 {
-    const Geom &g = f_->g;
     const CgLaunchTable &t = cg_table(prec_);
-    CgArgs a = args();
+    const CgArgs a = args();
     const int R = cfg_.rtile;
-    dim3 grid_h((unsigned)blocks_for(g.Vh, cfg_.lps, cfg_.block), (unsigned)(nsys() / R));
-    dim3 blk(cfg_.block);
-    hipError_t e = t.ap(cfg_.lps, R, grid_h, blk, st, a);
+    dim3 grid((unsigned)grid_x(cfg_), (unsigned)(nsys() / R)), blk(cfg_.block);
+    hipError_t e = t.step1(cfg_.lps, R, grid, blk, st, a, ver);
     if (e == hipSuccess)
-        e = launch_fin(FIN_AP, (int)grid_h.x, a, st);
-    if (e == hipSuccess)
-        e = t.update(cfg_.lps, R, grid_h, blk, st, a);
-    if (e == hipSuccess)
-        e = launch_fin(FIN_UPDATE, (int)grid_h.x, a, st);
-    if (e == hipSuccess && with_ru) {
-        CgArgs a64 = a;
-        a64.nbr[0] = cfg64_.tables ? f_->nbr_for(0) : nullptr;
-        a64.nbr[1] = cfg64_.tables ? f_->nbr_for(1) : nullptr;
-        a64.remap = cfg64_.remap;
-        dim3 grid64((unsigned)blocks_for(g.Vh, cfg64_.lps, cfg64_.block), (unsigned)nsys());
-        e = launch_ru_dx(cfg64_.lps, prec_ != 0, grid64, dim3(cfg64_.block), st, a64);
-        if (e == hipSuccess)
-            e = t.ru_residual(cfg64_.lps, grid64, dim3(cfg64_.block), st, a64);
-        if (e == hipSuccess)
-            e = launch_fin(FIN_RU, (int)grid64.x, a64, st);
-    }
+        e = t.step2(cfg_.lps, R, grid, blk, st, a, ver);
     if (e != hipSuccess)
         return set_error(STAG_EHIP, "CG kernel launch failed: %s", hipGetErrorString(e));
     return STAG_OK;
 }
 
-int Batch::enqueue_epoch(int iters, int ru_interval)
+int Batch::enqueue_epoch(int steps)
 {
+    steps += steps & 1;
     if (!use_graphs_) {
-        for (int k = 0; k < iters; ++k) {
-            int rc = launch_iter((k + 1) % ru_interval == 0 || k == iters - 1, s_);
+        for (int k = 0; k < steps; ++k) {
+            int rc = launch_step(k & 1, s_);
             if (rc != STAG_OK)
                 return rc;
         }
@@ -400,15 +387,14 @@ int Batch::enqueue_epoch(int iters, int ru_interval)
     // The kernel arguments of an epoch depend only on this workspace, so an
     // epoch of a given length is recorded once and replayed: the launches of
     // all its kernels cost one graph launch on the host.
-    const auto key = std::make_pair(iters, std::min(ru_interval, iters + 1));
-    auto it = graphs_.find(key);
+    auto it = graphs_.find(steps);
     if (it == graphs_.end()) {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         STAG_HIP_CHECK(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
         int rc = STAG_OK;
-        for (int k = 0; k < iters && rc == STAG_OK; ++k)
-            rc = launch_iter((k + 1) % ru_interval == 0 || k == iters - 1, cap_stream_);
+        for (int k = 0; k < steps && rc == STAG_OK; ++k)
+            rc = launch_step(k & 1, cap_stream_);
         hipError_t e = hipStreamEndCapture(cap_stream_, &graph);
         if (rc != STAG_OK) {
             if (graph)
@@ -421,7 +407,7 @@ int Batch::enqueue_epoch(int iters, int ru_interval)
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess)
             return set_error(STAG_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
-        it = graphs_.emplace(key, exec).first;
+        it = graphs_.emplace(steps, exec).first;
     }
     STAG_HIP_CHECK(hipGraphLaunch(it->second, s_));
     return STAG_OK;
@@ -429,7 +415,8 @@ int Batch::enqueue_epoch(int iters, int ru_interval)
 
 int Batch::enqueue_snapshot()
 {
-    STAG_HIP_CHECK(hipMemcpyAsync(snap_, st_d_, nsys() * sizeof(SysState), hipMemcpyDeviceToHost, s_));
+    STAG_HIP_CHECK(hipMemcpyAsync(snap_, st_d_[0], nsys() * sizeof(SysState), hipMemcpyDeviceToHost, s_));
+    STAG_HIP_CHECK(hipMemcpyAsync(snap_ + nsys(), st_d_[1], nsys() * sizeof(SysState), hipMemcpyDeviceToHost, s_));
     STAG_HIP_CHECK(hipEventRecord(snap_ev_, s_));
     return STAG_OK;
 }
@@ -480,10 +467,10 @@ void fill_info(const Batch &B, int slot, stag_cg_info *info)
     bool any = false;
     for (int par = 0; par < 2; ++par) {
         const SysState &st = B.state(par * S + slot);
-        if (st.phase == PH_IDLE)
+        if (st.mode == M_IDLE)
             continue;
         any = true;
-        status = worse(status, st.phase == PH_DONE ? st.status : STAG_ENOCONV);
+        status = worse(status, st.mode == M_DONE ? st.status : STAG_ENOCONV);
         iters = std::max(iters, st.iters);
         nru += st.n_ru;
         rst = std::max(rst, st.restarts);
@@ -563,7 +550,7 @@ static int estimate_remaining(const Batch &B, std::vector<std::pair<int, double>
     bool known = true;
     for (int j = 0; j < B.nsys(); ++j) {
         const SysState &st = B.state(j);
-        if (st.phase != PH_RUN) {
+        if (st.mode != M_CG && st.mode != M_RU) {
             prev[j] = {st.iters, st.rr};
             continue;
         }
@@ -615,37 +602,31 @@ int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs, con
     }
     if ((rc = B.upload_and_init(systems)) != STAG_OK)
         return rc;
-    // residual recomputations are requested on the device; their kernels run
-    // every ru_interval iterations (mixed precision) or at the end of an
-    // epoch (FP64, where they only serve the final check)
-    int ru_interval = prec != STAG_FP64 ? 2 : 1 << 30;
-    if (const char *e = getenv("STAG_RU_INTERVAL"))
-        ru_interval = std::max(1, atoi(e));
     int E = 8, Emax = 64;
     if (const char *e = getenv("STAG_EPOCH"))
         E = Emax = std::max(1, atoi(e));
     std::vector<std::pair<int, double>> prev(B.nsys(), {0, 0.0});
     // pipelined: epoch n+1 is queued before the state after epoch n is read
-    if ((rc = B.enqueue_epoch(E, ru_interval)) != STAG_OK || (rc = B.enqueue_snapshot()) != STAG_OK)
+    if ((rc = B.enqueue_epoch(E)) != STAG_OK || (rc = B.enqueue_snapshot()) != STAG_OK)
         return rc;
     int64_t budget = (int64_t)(max_iter + 1) * (int64_t)(2 + params[0].max_restarts) + 4096;
     bool done = false;
     while (!done && budget > 0) {
-        if ((rc = B.enqueue_epoch(E, ru_interval)) != STAG_OK)
+        if ((rc = B.enqueue_epoch(E)) != STAG_OK)
             return rc;
         budget -= E;
         if ((rc = B.wait_snapshot()) != STAG_OK)
             return rc;
         done = true;
         for (int j = 0; j < B.nsys(); ++j) {
-            const int ph = B.state(j).phase;
-            if (ph == PH_RUN || ph == PH_INIT)
+            const int md = B.state(j).mode;
+            if (md == M_INIT || md == M_CG || md == M_RU)
                 done = false;
         }
         if (!done) {
             std::vector<char> running(B.nsys());
             for (int j = 0; j < B.nsys(); ++j)
-                running[j] = B.state(j).phase == PH_RUN || B.state(j).phase == PH_INIT;
+                running[j] = B.state(j).mode == M_INIT || B.state(j).mode == M_CG || B.state(j).mode == M_RU;
             if ((rc = B.set_running(running)) != STAG_OK)
                 return rc;
             const int rem = estimate_remaining(B, prev);

@@ -34,32 +34,37 @@ public:
     void stage_system(int j, const stag_cg_params &p, const double *b_half, double *x_half);
     // Copy staged systems [j0, j0 + n) to the device and run the init kernel.
     int upload_and_init(const std::vector<int> &systems);
-    // Enqueue `iters` CG iterations; the residual-recomputation kernels run
-    // after every ru_interval-th iteration and after the last one.
-    int enqueue_epoch(int iters, int ru_interval);
+    // Enqueue `steps` CG steps (rounded up to an even number, so that every
+    // epoch starts from state buffer 0).
+    int enqueue_epoch(int steps);
     // Enqueue a copy of the device state into the host snapshot and record an
     // event; wait_snapshot blocks until it has arrived.
     int enqueue_snapshot();
     int wait_snapshot();
     bool snapshot_ready();
-    const SysState &state(int j) const { return snap_[j]; }
+    // Latest state of system j in the last snapshot (the newer of its two buffers).
+    const SysState &state(int j) const
+    {
+        const SysState &a = snap_[j], &b = snap_[nsys() + j];
+        return b.step > a.step ? b : a;
+    }
     // Order in which the tiles take the systems: the systems flagged in
     // `running` first (per parity), the rest left out.  Stream-ordered: applies
     // to the kernels enqueued after this call.
     int set_running(const std::vector<char> &running);
 
 private:
-    int launch_iter(bool with_ru, hipStream_t st);
+    int launch_step(int ver, hipStream_t st);
+    int grid_x(const KernelCfg &c) const;
     KernelCfg tune_cg();
     double time_cg_config(const KernelCfg &c);
-    hipError_t launch_fin(int role, int nblk, const CgArgs &a, hipStream_t st);
     CgArgs args() const;
 
     Ctx *ctx_;
     std::shared_ptr<GaugeField> f_;
     int prec_, S_;
     hipStream_t s_;
-    KernelCfg cfg_, cfg64_;
+    KernelCfg cfg_;
     int pstride_ = 0;
     void *mem_ = nullptr;
     size_t bytes_ = 0;
@@ -69,12 +74,12 @@ private:
     dbl2 *tmp_ = nullptr;
     dbl2 **xhi_d_ = nullptr;
     const dbl2 **b_d_ = nullptr;
-    SysState *st_d_ = nullptr;
+    SysState *st_d_[2] = {nullptr, nullptr};
     int *perm_d_ = nullptr;
     double *partials_ = nullptr;
     // pinned host memory
     SysState *stage_ = nullptr;   // [nsys] staged initial states
-    SysState *snap_ = nullptr;    // [nsys] last snapshot
+    SysState *snap_ = nullptr;    // [2][nsys] last snapshot of both state buffers
     dbl2 **xhi_h_ = nullptr;
     const dbl2 **b_h_ = nullptr;
     int *perm_h_ = nullptr;
@@ -85,7 +90,7 @@ private:
     // epochs recorded once as HIP graphs (kernel nodes only) and replayed
     bool use_graphs_ = true;
     hipStream_t cap_stream_ = nullptr;
-    std::map<std::pair<int, int>, hipGraphExec_t> graphs_;
+    std::map<int, hipGraphExec_t> graphs_;
 };
 
 }  // namespace stag

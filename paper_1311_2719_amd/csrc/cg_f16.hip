@@ -8,30 +8,30 @@ namespace {
 using P = PrecF16;
 const int kTiles[] = {1, 2, 3, 4, 6, 8, 12};
 
-hipError_t ap(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a)
+hipError_t step1(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a, int ver)
 {
     switch (R) {
-    case 1: return RLaunch<P, 1>::ap(lps, grid, block, s, a);
-    case 2: return RLaunch<P, 2>::ap(lps, grid, block, s, a);
-    case 3: return RLaunch<P, 3>::ap(lps, grid, block, s, a);
-    case 4: return RLaunch<P, 4>::ap(lps, grid, block, s, a);
-    case 6: return RLaunch<P, 6>::ap(lps, grid, block, s, a);
-    case 8: return RLaunch<P, 8>::ap(lps, grid, block, s, a);
-    case 12: return RLaunch<P, 12>::ap(lps, grid, block, s, a);
+    case 1: return RLaunch<P, 1>::step1(lps, grid, block, s, a, ver);
+    case 2: return RLaunch<P, 2>::step1(lps, grid, block, s, a, ver);
+    case 3: return RLaunch<P, 3>::step1(lps, grid, block, s, a, ver);
+    case 4: return RLaunch<P, 4>::step1(lps, grid, block, s, a, ver);
+    case 6: return RLaunch<P, 6>::step1(lps, grid, block, s, a, ver);
+    case 8: return RLaunch<P, 8>::step1(lps, grid, block, s, a, ver);
+    case 12: return RLaunch<P, 12>::step1(lps, grid, block, s, a, ver);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t update(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a)
+hipError_t step2(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a, int ver)
 {
     switch (R) {
-    case 1: return RLaunch<P, 1>::update(lps, grid, block, s, a);
-    case 2: return RLaunch<P, 2>::update(lps, grid, block, s, a);
-    case 3: return RLaunch<P, 3>::update(lps, grid, block, s, a);
-    case 4: return RLaunch<P, 4>::update(lps, grid, block, s, a);
-    case 6: return RLaunch<P, 6>::update(lps, grid, block, s, a);
-    case 8: return RLaunch<P, 8>::update(lps, grid, block, s, a);
-    case 12: return RLaunch<P, 12>::update(lps, grid, block, s, a);
+    case 1: return RLaunch<P, 1>::step2(lps, grid, block, s, a, ver);
+    case 2: return RLaunch<P, 2>::step2(lps, grid, block, s, a, ver);
+    case 3: return RLaunch<P, 3>::step2(lps, grid, block, s, a, ver);
+    case 4: return RLaunch<P, 4>::step2(lps, grid, block, s, a, ver);
+    case 6: return RLaunch<P, 6>::step2(lps, grid, block, s, a, ver);
+    case 8: return RLaunch<P, 8>::step2(lps, grid, block, s, a, ver);
+    case 12: return RLaunch<P, 12>::step2(lps, grid, block, s, a, ver);
     default: return hipErrorInvalidValue;
     }
 }
@@ -55,7 +55,7 @@ hipError_t probe(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const Geo
 
 const CgLaunchTable &cg_table_f16()
 {
-    static const CgLaunchTable t = {ap, update, PLaunch<P>::init, PLaunch<P>::ru_residual,
+    static const CgLaunchTable t = {step1, step2, PLaunch<P>::init,
                                     probe, kTiles, (int)(sizeof(kTiles) / sizeof(kTiles[0]))};
     return t;
 }

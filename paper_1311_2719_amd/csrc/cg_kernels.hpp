@@ -2,39 +2,41 @@
 // batched over systems that share a gauge field.
 //
 // The iteration is the loop of the paper's Sec. 4 with the mass explicit,
-// rearranged into two kernels so that every vector is streamed once and every
-// scalar stays on the device:
-//   K1  p' = r + beta p (formed on the fly at every gathered neighbour, and
-//       stored once at the partner site), ap = D p' on the other parity,
-//       <ap,ap> and <p',p'>;          finalize: alpha = rr / (m^2 <p',p'> + <ap,ap>)
-//   K2  Ap = m^2 p' - D ap; x += alpha p'; r -= alpha Ap; <r,r>   (Ap never stored)
-//                                     finalize: stopping test, beta = rn / rr
-// p and p' alternate between two buffers per system (pcur).
-// FP64 residual recomputation (reliable updates in mixed precision, and the
-// final true-residual check in every mode):
-//   RU2 t = D x on the other parity in FP64 (x = x_hi + x_lo)
-//   RU3 x_hi += x_lo, x_lo = 0, r = b - m^2 x_hi + D t in FP64, <r,r>
-// Each main kernel writes per-block partial sums; a one-block-per-system
-// finalize kernel (k_cg_fin) launched right after it reduces them in a fixed
-// order and evaluates the scalar recurrences and the stopping test of its
-// system, so the host never reads a scalar inside the loop and no cross-block
-// synchronisation (fence or atomic) is needed inside a kernel.
+// arranged as two kernels per step so that every vector is streamed once,
+// every scalar stays on the device and no other kernel is needed:
+//   K1  prologue: reduce the previous step's partial sums and advance the
+//       system's scalar state (beta, the stopping test, reliable-update
+//       decisions); then, for a CG step, p' = r + beta p (formed on the fly at
+//       every gathered neighbour and stored once at the partner site),
+//       ap = D p' on the other parity, <ap,ap> and <p',p'>;
+//   K2  prologue: alpha = rr / (m^2 <p',p'> + <ap,ap>) from K1's partials;
+//       then Ap = m^2 p' - D ap; x += alpha p'; r -= alpha Ap; <r,r>
+//       (Ap is never stored).
+// A step of a system can instead be a residual recomputation in FP64
+// (reliable update in mixed precision, the final true-residual check in every
+// mode): K1 forms t = D (x_hi + x_lo) on the other parity, K2 forms
+// x_hi += x_lo, x_lo = 0, r = b - m^2 x_hi + D t and <r,r>.
 //
-// Systems: nsys = 2*S, system j has parity j / S (its x, r, p live on that
-// parity; ap and t on the other).  A tile is R systems of one parity that are
-// processed together so each link entry is loaded once for all of them; the
-// tiles take their systems from a per-parity list (perm) that the host
-// compacts between epochs, so the number of tiles that read links follows the
-// number of systems still running.  A system's partial sums depend only on
-// the sites of each block, not on its tile, so compaction does not change
-// results.
+// Every block of a kernel derives the same scalars from the same partials
+// (fixed summation order), so no block waits for another and no fence or
+// atomic is used; the state advanced by K1 is written by one block into the
+// other of two state buffers, which the following kernels read.  Partial sums
+// alternate between two buffers the same way.
+//
+// Systems: nsys = 2*S, system j has parity j / S (x, r, p on that parity; ap
+// and t on the other).  A tile is R systems of one parity processed together
+// so each link entry is loaded once for all of them; tiles take their systems
+// from a per-parity list that the host compacts between epochs.  A system's
+// partial sums depend only on the sites of each block, not on its tile, so
+// compaction never changes results.
 #pragma once
 
 #include "hop.hpp"
 
 namespace stag {
 
-enum Phase : int32_t { PH_IDLE = 0, PH_INIT = 1, PH_RUN = 2, PH_DONE = 3 };
+// What the step a state describes did (or, for INIT, what produced it).
+enum Mode : int32_t { M_IDLE = 0, M_INIT = 1, M_CG = 2, M_RU = 3, M_DONE = 4 };
 
 struct SysState {
     double mass2;
@@ -42,17 +44,16 @@ struct SysState {
     double stop2;    // tol^2 <b,b>
     double bb;
     double rr;       // <r,r> of the current (iterated) residual
-    double pp;       // <p,p> of the stored search direction
+    double pp;       // <p,p> of the last search direction
     double alpha;
     double beta;
     double maxr2;    // largest <r,r> since the last residual recomputation
     double delta2;   // reliable-update threshold squared (0: final check only)
     double true_rr;  // <r,r> of the last FP64 residual recomputation
     double pad0;
-    int32_t phase;
-    int32_t ru_pending;  // residual recomputation requested
-    int32_t stopping;    // status to report if the recomputation does not converge
-    int32_t status;      // final status (phase == PH_DONE)
+    int32_t mode;        // Mode
+    int32_t stopping;    // status to report if the next recomputation does not converge
+    int32_t status;      // final status (mode == M_DONE)
     int32_t iters;
     int32_t maxiter;
     int32_t n_ru;
@@ -60,6 +61,7 @@ struct SysState {
     int32_t max_restarts;
     int32_t mixed;
     int32_t pcur;        // which of the two p buffers holds the current direction
+    int32_t step;        // steps taken (the newer of the two state buffers has the larger value)
     int32_t pad1;
 };
 
@@ -75,9 +77,9 @@ struct CgArgs {
     dbl2 *tmp;                 // [nsys][3][Vh] FP64 work vector (other parity)
     dbl2 *const *xhi;          // [nsys] parity half of the caller's x
     const dbl2 *const *b;      // [nsys] parity half of the caller's b
-    SysState *st;              // [nsys]
+    SysState *st[2];           // [nsys] each: two state buffers
     const int *perm;           // [2][S] systems of each parity in tile order, -1 = none
-    double *partials;          // [nsys][2][pstride]
+    double *partials;          // [2 buffers][nsys][3 slots][pstride]
     int S;                     // systems per parity
     int pstride;
     int remap;
@@ -105,232 +107,626 @@ template <class P> __device__ __forceinline__ cplx<typename P::real> load_colour
     }
 }
 
-// Parity of a tile and the offset of its first entry in the system list.
-__device__ __forceinline__ void tile_of(const CgArgs &a, int tile, int R, int &par, int &k0)
+// Partial sums: slot 0 <ap,ap>, slot 1 <p',p'>, slot 2 <r,r> (CG, residual
+// recomputation or the source norm at initialisation).
+__device__ __forceinline__ double *partial_slot(const CgArgs &a, int buf, int j, int slot)
 {
-    const int tpp = a.S / R;
-    par = tile / tpp;
-    k0 = par * a.S + (tile % tpp) * R;
+    const size_t nsys = 2 * (size_t)a.S;
+    return a.partials + (((size_t)buf * nsys + j) * 3 + slot) * a.pstride;
 }
 
 __device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v < INFINITY; }
 
-__device__ __forceinline__ double *partial_slot(const CgArgs &a, int j, int which)
-{
-    return a.partials + ((size_t)j * 2 + which) * a.pstride;
-}
+// ---- step prologue ------------------------------------------------------------------
+// Every step kernel starts from the same few scalars per system: the state
+// written by the previous kernel and the totals of its partial sums.  All of
+// those loads are issued together, right after the tile's system list is read,
+// so a prologue costs one memory round trip after that list: the states
+// travel through LDS (16-byte vector loads, one thread per piece), the
+// partial sums are loaded in unrolled groups before any of them is added.
 
-// ---- K1: p' = r + beta p, ap = D p' ---------------------------------------------
-
-template <class P, int LPS, int R>
-__global__ void __launch_bounds__(256) k_cg_ap(CgArgs a)
+// The tile's systems (-1 = empty place); false when the tile is empty.
+template <int R> __device__ __forceinline__ bool tile_systems(const int *tile, int (&js)[R], bool (&valid)[R])
 {
-    using real = typename P::real;
-    using v2 = typename vec2_of<real>::type;
-    __shared__ double lds[2 * R * 4];
-    int par, k0;
-    tile_of(a, blockIdx.y, R, par, k0);
-    const int pout = 1 - par;
-    int js[R];
-    bool act[R];
-    real beta[R];
-    int pc[R];
     bool any = false;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int j = a.perm[k0 + r];
-        js[r] = j < 0 ? 0 : j;
-        const SysState &st = a.st[js[r]];
-        act[r] = j >= 0 && st.phase == PH_RUN && !st.ru_pending;
-        beta[r] = (real)st.beta;
-        pc[r] = st.pcur;
-        any |= act[r];
+        const int j = tile[r];
+        valid[r] = j >= 0;
+        js[r] = valid[r] ? j : 0;
+        any |= valid[r];
     }
-    if (!any)
+    return any;
+}
+
+constexpr int kStateVec = sizeof(SysState) / 16;
+static_assert(sizeof(SysState) % 16 == 0, "state must be a whole number of 16-byte pieces");
+
+// Per-thread strided sums of NS partial slots (slots 0 .. NS-1) of R systems:
+// thread t adds entries t, t + blockDim, ... in increasing order, so the
+// totals do not depend on the unroll depth.  The states of the R systems are
+// loaded on the way and stored to `sst` once the sums' loads are in flight.
+template <int R, int NS>
+__device__ __forceinline__ void load_prologue(const CgArgs &a, int pbuf, const SysState *states, const int *tile,
+                                              const int *js, const bool *valid, int nblk, SysState *sst,
+                                              double (&v)[NS * R])
+{
+    constexpr int U = (NS * R >= 24) ? 1 : 24 / (NS * R);
+    // states: kStateVec pieces per system, at most two pieces per thread (R * kStateVec <= 2 * 64)
+    static_assert(R * kStateVec <= 128, "state staging assumes at most two pieces per thread");
+    const int t0 = threadIdx.x, t1 = threadIdx.x + blockDim.x;
+    const int n_pieces = R * kStateVec;
+    uint4 q0{}, q1{};
+    if (t0 < n_pieces) {
+        const int j = tile[t0 / kStateVec];
+        if (j >= 0)
+            q0 = ((const uint4 *)(states + j))[t0 % kStateVec];
+    }
+    if (t1 < n_pieces) {
+        const int j = tile[t1 / kStateVec];
+        if (j >= 0)
+            q1 = ((const uint4 *)(states + j))[t1 % kStateVec];
+    }
+    const double *base[NS * R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+            base[r * NS + k] = partial_slot(a, pbuf, js[r], k);
+#pragma unroll
+    for (int k = 0; k < NS * R; ++k)
+        v[k] = 0.0;
+    for (int i0 = threadIdx.x; i0 < nblk; i0 += U * blockDim.x) {
+        double buf[U][NS * R];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * blockDim.x;
+#pragma unroll
+            for (int k = 0; k < NS * R; ++k)
+                buf[u][k] = (i < nblk && valid[k / NS]) ? base[k][i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < NS * R; ++k)
+                v[k] += buf[u][k];
+    }
+    if (t0 < n_pieces)
+        ((uint4 *)sst)[t0] = q0;
+    if (t1 < n_pieces)
+        ((uint4 *)sst)[t1] = q1;
+}
+
+// Values read from LDS that are the same in every lane, moved to scalar
+// registers so that branches and addresses derived from them stay scalar.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uniform(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u), hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Wave sums of the per-thread sums into lds[k * nw + w]; after the barrier,
+// thread r (< R) owns system r and reads its NS totals with wave_totals.
+template <int N> __device__ __forceinline__ void wave_sums_to_lds(const double (&v)[N], double *lds)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const double t = wave_sum(v[k]);
+        if (lane == 0)
+            lds[k * nw + w] = t;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ double wave_total(const double *lds, int k)
+{
+    const int nw = blockDim.x >> 6;
+    double out = 0.0;
+    for (int i = 0; i < nw; ++i)
+        out += lds[k * nw + i];
+    return out;
+}
+
+// Advance a system's state over the step whose partial sums are `t`.
+__device__ __forceinline__ void advance(SysState &s, const double (&t)[3])
+{
+    s.step += 1;
+    switch (s.mode) {
+    case M_INIT: {
+        const double bb = t[2];
+        s.bb = bb;
+        s.stop2 = s.tol2 * bb;
+        s.rr = bb;
+        s.pp = bb;
+        s.maxr2 = bb;
+        s.true_rr = bb;
+        s.beta = 0.0;
+        s.alpha = 0.0;
+        s.pcur = 0;
+        s.iters = 0;
+        s.n_ru = 0;
+        s.restarts = 0;
+        s.stopping = 0;
+        if (!(bb < INFINITY)) {
+            s.mode = M_DONE;
+            s.status = STAG_ENONFINITE;
+        } else if (bb == 0.0) {
+            s.mode = M_DONE;
+            s.status = STAG_OK;
+            s.true_rr = 0.0;
+        } else {
+            s.mode = M_CG;
+        }
+        break;
+    }
+    case M_CG: {
+        s.pcur ^= 1;  // the previous K1 stored p' in the other buffer
+        const double apap = t[0], pp = t[1];
+        s.pp = pp;
+        const double pap = s.mass2 * pp + apap;
+        if (!finite_pos(pap)) {  // K2 skipped this system's update
+            s.stopping = STAG_EBREAKDOWN;
+            s.mode = M_RU;
+            break;
+        }
+        s.alpha = s.rr / pap;
+        const double rn = t[2];
+        s.iters += 1;
+        if (!(rn < INFINITY)) {
+            s.stopping = STAG_EBREAKDOWN;
+            s.mode = M_RU;
+            break;
+        }
+        const bool conv = rn < s.stop2;
+        s.maxr2 = rn > s.maxr2 ? rn : s.maxr2;
+        bool recompute = conv || rn < s.delta2 * s.maxr2;
+        if (!conv && s.iters >= s.maxiter) {
+            s.stopping = STAG_ENOCONV;
+            recompute = true;
+        }
+        if (recompute) {
+            s.mode = M_RU;  // rr keeps the previous value as the denominator of beta
+        } else {
+            s.beta = rn / s.rr;
+            s.rr = rn;
+            s.mode = M_CG;
+        }
+        break;
+    }
+    case M_RU: {
+        const double trr = t[2];
+        s.n_ru += 1;
+        s.true_rr = trr;
+        if (trr <= s.stop2) {
+            s.mode = M_DONE;
+            s.status = STAG_OK;
+        } else if (s.stopping) {
+            s.mode = M_DONE;
+            s.status = s.stopping;
+        } else if (!s.mixed) {
+            // FP64: the recursive residual claimed convergence but the true one
+            // disagrees: restart CG from the current x (fresh search direction)
+            s.restarts += 1;
+            if (s.restarts > s.max_restarts) {
+                s.mode = M_DONE;
+                s.status = STAG_ENOCONV;
+            } else {
+                s.beta = 0.0;
+                s.rr = trr;
+                s.maxr2 = trr;
+                s.mode = M_CG;
+            }
+        } else {
+            // reliable update: keep the search direction, continue from the true residual
+            s.beta = trr / s.rr;
+            s.rr = trr;
+            s.maxr2 = trr;
+            s.mode = M_CG;
+        }
+        break;
+    }
+    default:
+        break;
+    }
+}
+
+// First site index handled by this thread in grid-stride round `it`.
+__device__ __forceinline__ int64_t round_base(int it, int remap)
+{
+    return ((int64_t)it * gridDim.x + logical_block(blockIdx.x, gridDim.x, remap)) * blockDim.x + threadIdx.x;
+}
+
+// ---- K1 -----------------------------------------------------------------------------
+
+template <class P, int LPS, int R>
+__global__ void __launch_bounds__(256) k_cg_step1(CgArgs a, int ver)
+{
+    using real = typename P::real;
+    using v2 = typename vec2_of<real>::type;
+    __shared__ double lds[3 * R * 4];
+    const int tpp = a.S / R;
+    const int par = blockIdx.y / tpp, k0 = par * a.S + (blockIdx.y % tpp) * R, pout = 1 - par;
+    const int Vh = a.g.Vh, nblk = gridDim.x;
+    int js[R];
+    bool valid[R];
+    if (!tile_systems<R>(a.perm + k0, js, valid))
         return;
-    const int Vh = a.g.Vh;
-    int s, sub;
-    site_of_thread<LPS>(logical_block(blockIdx.x, gridDim.x, a.remap) * blockDim.x + threadIdx.x, s, sub);
+    // the previous step's totals and states; thread r (< R) advances system r
+    __shared__ SysState sst[R];
+    {
+        double v[3 * R];
+        load_prologue<R, 3>(a, ver, a.st[ver], a.perm + k0, js, valid, nblk, sst, v);
+        wave_sums_to_lds<3 * R>(v, lds);
+        const int r = threadIdx.x;
+        if (r < R) {
+            const int j = a.perm[k0 + r];
+            SysState st = sst[r];
+            if (j >= 0 && st.mode != M_IDLE && st.mode != M_DONE) {
+                const double tot[3] = {wave_total(lds, 3 * r), wave_total(lds, 3 * r + 1), wave_total(lds, 3 * r + 2)};
+                advance(st, tot);
+                if (blockIdx.x == 0)
+                    a.st[ver ^ 1][j] = st;
+            } else {
+                st.mode = M_IDLE;  // not running: nothing to do in this step
+            }
+            sst[r] = st;
+        }
+        __syncthreads();
+    }
+    bool cg[R], ru[R];
+    real beta[R];
+    int pc[R];
+    bool anycg = false, anyru = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int mode = valid[r] ? uniform(sst[r].mode) : (int)M_IDLE;
+        cg[r] = mode == M_CG;
+        ru[r] = mode == M_RU;
+        beta[r] = (real)uniform(sst[r].beta);
+        pc[r] = uniform(sst[r].pcur);
+        anycg |= cg[r];
+        anyru |= ru[r];
+    }
+    if (!anycg && !anyru)
+        return;
     double nrm[2 * R];
 #pragma unroll
     for (int r = 0; r < 2 * R; ++r)
         nrm[r] = 0.0;
-    if (s < Vh) {
-        cplx<real> acc[R][3];
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                acc[r][c] = czero<real>();
-        auto load = [&](int r, int n, cplx<real> *chi) {
-            const int j = js[r];
-            const v2 *rv = (const v2 *)a.r + (size_t)j * 3 * Vh;
-            cplx<real> pv[3];
-            P::load_spinor(spin_at<P>(a.p[pc[r]], j, Vh), Vh, n, pv);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const v2 t = rv[(int64_t)c * Vh + n];
-                chi[c].re = fma(beta[r], pv[c].re, t.x);
-                chi[c].im = fma(beta[r], pv[c].im, t.y);
-            }
-        };
-        hop_accumulate<P, LPS, R>(a.g, (const typename P::link_t *)a.links[pout], a.nbr[pout], pout, s, sub, act,
-                                  acc, load);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (!act[r])
+    const int64_t nthreads = (int64_t)Vh * LPS;
+    if (anycg) {
+        for (int it = 0;; ++it) {
+            const int64_t gt = round_base(it, a.remap);
+            if (gt - threadIdx.x >= nthreads)
+                break;
+            int s, sub;
+            site_of_thread<LPS>((int)gt, s, sub);
+            if (s >= Vh)
                 continue;
-            const int j = js[r];
-            void *out = spin_at<P>(a.ap, j, Vh);
-            const v2 *rv = (const v2 *)a.r + (size_t)j * 3 * Vh;
-            const void *pold = spin_at<P>(a.p[pc[r]], j, Vh);
-            void *pnew = spin_at<P>(a.p[pc[r] ^ 1], j, Vh);
-            if constexpr (P::id == 2) {
-                if (sub == 0) {
-                    P::store_spinor(out, Vh, s, acc[r]);
-                    // the new direction at the partner site (same index, parity par)
-                    cplx<real> pv[3];
-                    P::load_spinor(pold, Vh, s, pv);
+            cplx<real> acc[R][3];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    acc[r][c] = czero<real>();
+            auto load = [&](int r, int n, cplx<real> *chi) {
+                const int j = js[r];
+                const v2 *rv = (const v2 *)a.r + (size_t)j * 3 * Vh;
+                cplx<real> pv[3];
+                P::load_spinor(spin_at<P>(a.p[pc[r]], j, Vh), Vh, n, pv);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const v2 t = rv[(int64_t)c * Vh + n];
+                    chi[c].re = fma(beta[r], pv[c].re, t.x);
+                    chi[c].im = fma(beta[r], pv[c].im, t.y);
+                }
+            };
+            hop_accumulate<P, LPS, R>(a.g, (const typename P::link_t *)a.links[pout], a.nbr[pout], pout, s, sub,
+                                      cg, acc, load);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (!cg[r])
+                    continue;
+                const int j = js[r];
+                void *out = spin_at<P>(a.ap, j, Vh);
+                const v2 *rv = (const v2 *)a.r + (size_t)j * 3 * Vh;
+                const void *pold = spin_at<P>(a.p[pc[r]], j, Vh);
+                void *pnew = spin_at<P>(a.p[pc[r] ^ 1], j, Vh);
+                if constexpr (P::id == 2) {
+                    if (sub == 0) {
+                        P::store_spinor(out, Vh, s, acc[r]);
+                        // the new direction at the partner site (same index, parity par)
+                        cplx<real> pv[3];
+                        P::load_spinor(pold, Vh, s, pv);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            const v2 t = rv[(int64_t)c * Vh + s];
+                            pv[c].re = fma(beta[r], pv[c].re, t.x);
+                            pv[c].im = fma(beta[r], pv[c].im, t.y);
+                        }
+                        P::store_spinor(pnew, Vh, s, pv);
+                        P::load_spinor(pnew, Vh, s, pv);  // the norm of the value D will read
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            nrm[R + r] += (double)pv[c].re * pv[c].re + (double)pv[c].im * pv[c].im;
+                    }
+                } else {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        const v2 t = rv[(int64_t)c * Vh + s];
-                        pv[c].re = fma(beta[r], pv[c].re, t.x);
-                        pv[c].im = fma(beta[r], pv[c].im, t.y);
+                        if (!owns_colour<LPS>(sub, c))
+                            continue;
+                        const int64_t o = (int64_t)c * Vh + s;
+                        ((v2 *)out)[o] = v2{acc[r][c].re, acc[r][c].im};
+                        const v2 po = ((const v2 *)pold)[o];
+                        const v2 t = rv[o];
+                        const v2 pn = v2{fma(beta[r], po.x, t.x), fma(beta[r], po.y, t.y)};
+                        ((v2 *)pnew)[o] = pn;
+                        nrm[R + r] += (double)pn.x * pn.x + (double)pn.y * pn.y;
                     }
-                    P::store_spinor(pnew, Vh, s, pv);
-                    P::load_spinor(pnew, Vh, s, pv);  // the norm of the value D will read
+                }
+                if (sub == 0) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
-                        nrm[R + r] += (double)pv[c].re * pv[c].re + (double)pv[c].im * pv[c].im;
+                        nrm[r] += (double)acc[r][c].re * acc[r][c].re + (double)acc[r][c].im * acc[r][c].im;
                 }
-            } else {
+            }
+        }
+    }
+    if (anyru) {
+        for (int it = 0;; ++it) {
+            const int64_t gt = round_base(it, a.remap);
+            if (gt - threadIdx.x >= nthreads)
+                break;
+            int s, sub;
+            site_of_thread<LPS>((int)gt, s, sub);
+            if (s >= Vh)
+                continue;
+            // residual recomputation: t = D (x_hi + x_lo) in FP64, one system at a time
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (!ru[r])
+                    continue;
+                const int j = js[r];
+                const dbl2 *xh = a.xhi[j];
+                const flt2 *xl = a.xlo ? a.xlo + (size_t)j * 3 * Vh : nullptr;
+                const bool one[1] = {true};
+                cplx<double> acc[1][3] = {{czero<double>(), czero<double>(), czero<double>()}};
+                auto load = [&](int, int n, cplx<double> *chi) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        dbl2 v = xh[(int64_t)c * Vh + n];
+                        if (xl) {
+                            const flt2 w = xl[(int64_t)c * Vh + n];
+                            v.x += (double)w.x;
+                            v.y += (double)w.y;
+                        }
+                        chi[c] = {v.x, v.y};
+                    }
+                };
+                hop_accumulate<PrecF64, LPS, 1, decltype(load), true>(a.g, a.links64[pout], a.nbr[pout], pout, s,
+                                                                      sub, one, acc, load);
+                dbl2 *t = a.tmp + (size_t)j * 3 * Vh;
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    if (owns_colour<LPS>(sub, c))
+                        t[(int64_t)c * Vh + s] = dbl2{acc[0][c].re, acc[0][c].im};
+            }
+        }
+    }
+    if (!anycg)
+        return;
+    double tot2;
+    block_sum_multi<2 * R>(nrm, lds, tot2);
+    if (threadIdx.x < 2 * R) {
+        const int r = (int)threadIdx.x % R;
+        const int j = a.perm[k0 + r];
+        if (j >= 0)
+            partial_slot(a, ver ^ 1, j, (int)threadIdx.x / R)[blockIdx.x] = tot2;
+    }
+}
+
+// ---- K2 -----------------------------------------------------------------------------
+
+template <class P, int LPS, int R>
+__global__ void __launch_bounds__(256) k_cg_step2(CgArgs a, int ver)
+{
+    using real = typename P::real;
+    using v2 = typename vec2_of<real>::type;
+    __shared__ double lds[3 * R * 4];
+    const int tpp = a.S / R;
+    const int par = blockIdx.y / tpp, k0 = par * a.S + (blockIdx.y % tpp) * R;
+    const int Vh = a.g.Vh, nblk = gridDim.x;
+    const int cur = ver ^ 1;  // the state K1 of this step wrote
+    int js[R];
+    bool valid[R];
+    if (!tile_systems<R>(a.perm + k0, js, valid))
+        return;
+    // alpha from K1's partial sums (slots 0 and 1); thread r (< R) decides for system r
+    __shared__ SysState sst[R];
+    {
+        double v[2 * R];
+        load_prologue<R, 2>(a, cur, a.st[cur], a.perm + k0, js, valid, nblk, sst, v);
+        wave_sums_to_lds<2 * R>(v, lds);
+        const int r = threadIdx.x;
+        if (r < R) {
+            const int j = a.perm[k0 + r];
+            SysState st = sst[r];
+            int mode = M_IDLE;
+            double alpha = 0.0;
+            if (j >= 0 && st.mode == M_CG) {
+                const double pap = st.mass2 * wave_total(lds, 2 * r + 1) + wave_total(lds, 2 * r);
+                if (finite_pos(pap)) {  // otherwise K1 of the next step reports the breakdown
+                    mode = M_CG;
+                    alpha = st.rr / pap;
+                }
+            } else if (j >= 0 && st.mode == M_RU) {
+                mode = M_RU;
+            }
+            sst[r].mode = mode;
+            sst[r].alpha = alpha;
+        }
+        __syncthreads();
+    }
+    bool cg[R], ru[R];
+    real alpha[R], m2[R];
+    int pnew[R];
+    bool anycg = false, anyru = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int mode = valid[r] ? uniform(sst[r].mode) : (int)M_IDLE;
+        cg[r] = mode == M_CG;
+        ru[r] = mode == M_RU;
+        alpha[r] = (real)uniform(sst[r].alpha);
+        m2[r] = (real)uniform(sst[r].mass2);
+        pnew[r] = uniform(sst[r].pcur) ^ 1;  // p' written by K1 of this step
+        anycg |= cg[r];
+        anyru |= ru[r];
+    }
+    if (!anycg && !anyru)
+        return;
+    double nrm[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        nrm[r] = 0.0;
+    const int64_t nthreads = (int64_t)Vh * LPS;
+    if (anycg) {
+        for (int it = 0;; ++it) {
+            const int64_t gt = round_base(it, a.remap);
+            if (gt - threadIdx.x >= nthreads)
+                break;
+            int s, sub;
+            site_of_thread<LPS>((int)gt, s, sub);
+            if (s >= Vh)
+                continue;
+            cplx<real> acc[R][3];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    acc[r][c] = czero<real>();
+            auto load = [&](int r, int n, cplx<real> *chi) {
+                P::load_spinor(spin_at<P>(a.ap, js[r], Vh), Vh, n, chi);
+            };
+            hop_accumulate<P, LPS, R>(a.g, (const typename P::link_t *)a.links[par], a.nbr[par], par, s, sub, cg,
+                                      acc, load);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (!cg[r])
+                    continue;
+                const int j = js[r];
+                const void *pb = spin_at<P>(a.p[pnew[r]], j, Vh);
+                v2 *rv = (v2 *)a.r + (size_t)j * 3 * Vh;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if (!owns_colour<LPS>(sub, c))
+                        continue;
+                    const cplx<real> pv = load_colour<P>(pb, Vh, s, c);
+                    const int64_t o = (int64_t)c * Vh + s;
+                    if constexpr (P::id == 0) {
+                        dbl2 *x = a.xhi[j];
+                        const dbl2 xv = x[o];
+                        x[o] = dbl2{fma(alpha[r], pv.re, xv.x), fma(alpha[r], pv.im, xv.y)};
+                    } else {
+                        flt2 *xl = a.xlo + (size_t)j * 3 * Vh;
+                        const flt2 xv = xl[o];
+                        xl[o] = flt2{fmaf(alpha[r], pv.re, xv.x), fmaf(alpha[r], pv.im, xv.y)};
+                    }
+                    const real apr = m2[r] * pv.re - acc[r][c].re;
+                    const real api = m2[r] * pv.im - acc[r][c].im;
+                    v2 rr = rv[o];
+                    rr.x = fma(-alpha[r], apr, rr.x);
+                    rr.y = fma(-alpha[r], api, rr.y);
+                    rv[o] = rr;
+                    nrm[r] += (double)rr.x * rr.x + (double)rr.y * rr.y;
+                }
+            }
+        }
+    }
+    if (anyru) {
+        for (int it = 0;; ++it) {
+            const int64_t gt = round_base(it, a.remap);
+            if (gt - threadIdx.x >= nthreads)
+                break;
+            int s, sub;
+            site_of_thread<LPS>((int)gt, s, sub);
+            if (s >= Vh)
+                continue;
+            // residual recomputation: x_hi += x_lo, r = b - m^2 x_hi + D t in FP64
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (!ru[r])
+                    continue;
+                const int j = js[r];
+                const dbl2 *t = a.tmp + (size_t)j * 3 * Vh;
+                const bool one[1] = {true};
+                cplx<double> acc[1][3] = {{czero<double>(), czero<double>(), czero<double>()}};
+                auto load = [&](int, int n, cplx<double> *chi) { PrecF64::load_spinor(t, Vh, n, chi); };
+                hop_accumulate<PrecF64, LPS, 1, decltype(load), true>(a.g, a.links64[par], a.nbr[par], par, s, sub,
+                                                                      one, acc, load);
+                const double m2d = uniform(sst[r].mass2);
+                dbl2 *x = a.xhi[j];
+                const dbl2 *b = a.b[j];
+                v2 *rv = (v2 *)a.r + (size_t)j * 3 * Vh;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     if (!owns_colour<LPS>(sub, c))
                         continue;
                     const int64_t o = (int64_t)c * Vh + s;
-                    ((v2 *)out)[o] = v2{acc[r][c].re, acc[r][c].im};
-                    const v2 po = ((const v2 *)pold)[o];
-                    const v2 t = rv[o];
-                    const v2 pn = v2{fma(beta[r], po.x, t.x), fma(beta[r], po.y, t.y)};
-                    ((v2 *)pnew)[o] = pn;
-                    nrm[R + r] += (double)pn.x * pn.x + (double)pn.y * pn.y;
+                    dbl2 xv = x[o];
+                    if constexpr (P::id != 0) {
+                        const flt2 w = a.xlo[(size_t)j * 3 * Vh + o];
+                        xv.x += (double)w.x;
+                        xv.y += (double)w.y;
+                        x[o] = xv;
+                        a.xlo[(size_t)j * 3 * Vh + o] = flt2{0.f, 0.f};
+                    }
+                    const dbl2 bv = b[o];
+                    const double rre = bv.x - m2d * xv.x + acc[0][c].re;
+                    const double rim = bv.y - m2d * xv.y + acc[0][c].im;
+                    rv[o] = v2{(real)rre, (real)rim};
+                    nrm[r] += rre * rre + rim * rim;
                 }
-            }
-            if (sub == 0) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    nrm[r] += (double)acc[r][c].re * acc[r][c].re + (double)acc[r][c].im * acc[r][c].im;
             }
         }
     }
-    double tot;
-    block_sum_multi<2 * R>(nrm, lds, tot);
-    if (threadIdx.x < 2 * R) {
-        const int j = a.perm[k0 + (int)threadIdx.x % R];
-        if (j >= 0)
-            partial_slot(a, j, (int)threadIdx.x / R)[blockIdx.x] = tot;
-    }
-}
-
-// ---- K2: Ap = m^2 p - D ap, x += alpha p, r -= alpha Ap ------------------------
-
-template <class P, int LPS, int R>
-__global__ void __launch_bounds__(256) k_cg_update(CgArgs a)
-{
-    using real = typename P::real;
-    using v2 = typename vec2_of<real>::type;
-    __shared__ double lds[R * 4];
-    int par, k0;
-    tile_of(a, blockIdx.y, R, par, k0);
-    int js[R];
-    bool act[R];
-    bool any = false;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int j = a.perm[k0 + r];
-        js[r] = j < 0 ? 0 : j;
-        const SysState &st = a.st[js[r]];
-        act[r] = j >= 0 && st.phase == PH_RUN && !st.ru_pending;
-        any |= act[r];
-    }
-    if (!any)
-        return;
-    const int Vh = a.g.Vh;
-    int s, sub;
-    site_of_thread<LPS>(logical_block(blockIdx.x, gridDim.x, a.remap) * blockDim.x + threadIdx.x, s, sub);
-    double nrm[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-        nrm[r] = 0.0;
-    if (s < Vh) {
-        cplx<real> acc[R][3];
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                acc[r][c] = czero<real>();
-        auto load = [&](int r, int n, cplx<real> *chi) { P::load_spinor(spin_at<P>(a.ap, js[r], Vh), Vh, n, chi); };
-        hop_accumulate<P, LPS, R>(a.g, (const typename P::link_t *)a.links[par], a.nbr[par], par, s, sub, act, acc,
-                                  load);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (!act[r])
-                continue;
-            const int j = js[r];
-            const SysState &st = a.st[j];
-            const real m2 = (real)st.mass2, alpha = (real)st.alpha;
-            const void *pb = spin_at<P>(a.p[st.pcur], j, Vh);
-            v2 *rv = (v2 *)a.r + (size_t)j * 3 * Vh;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                if (!owns_colour<LPS>(sub, c))
-                    continue;
-                const cplx<real> pv = load_colour<P>(pb, Vh, s, c);
-                const int64_t o = (int64_t)c * Vh + s;
-                if constexpr (P::id == 0) {
-                    dbl2 *x = a.xhi[j];
-                    const dbl2 xv = x[o];
-                    x[o] = dbl2{fma(alpha, pv.re, xv.x), fma(alpha, pv.im, xv.y)};
-                } else {
-                    flt2 *xl = a.xlo + (size_t)j * 3 * Vh;
-                    const flt2 xv = xl[o];
-                    xl[o] = flt2{fmaf(alpha, pv.re, xv.x), fmaf(alpha, pv.im, xv.y)};
-                }
-                const real apr = m2 * pv.re - acc[r][c].re;
-                const real api = m2 * pv.im - acc[r][c].im;
-                v2 rr = rv[o];
-                rr.x = fma(-alpha, apr, rr.x);
-                rr.y = fma(-alpha, api, rr.y);
-                rv[o] = rr;
-                nrm[r] += (double)rr.x * rr.x + (double)rr.y * rr.y;
-            }
-        }
-    }
-    double tot;
-    block_sum_multi<R>(nrm, lds, tot);
+    double tot2;
+    block_sum_multi<R>(nrm, lds, tot2);
     if (threadIdx.x < R) {
         const int j = a.perm[k0 + (int)threadIdx.x];
         if (j >= 0)
-            partial_slot(a, j, 0)[blockIdx.x] = tot;
+            partial_slot(a, cur, j, 2)[blockIdx.x] = tot2;
     }
 }
 
-// ---- init: x = 0, r = b, p = r, beta = 0 ------------------------------------------
+// ---- initialisation: x = 0, r = b, p = r; <b,b> into slot 2 of buffer 0 -------------
+// Same grid shape as the step kernels (so the same number of partials), one
+// grid row per system; systems in mode M_INIT only.
 
 template <class P>
-__global__ void __launch_bounds__(256) k_cg_init(CgArgs a)
+__global__ void __launch_bounds__(256) k_cg_init(CgArgs a, int lps)
 {
     using real = typename P::real;
     using v2 = typename vec2_of<real>::type;
     __shared__ double lds[4];
     const int j = blockIdx.y;
-    if (a.st[j].phase != PH_INIT)
+    if (a.st[0][j].mode != M_INIT)
         return;
     const int Vh = a.g.Vh;
-    const int s = logical_block(blockIdx.x, gridDim.x, a.remap) * blockDim.x + threadIdx.x;
     double nrm[1] = {0.0};
-    if (s < Vh) {
+    // one thread per site; the grid covers Vh * lps threads per round like the step kernels
+    const int64_t nthreads = (int64_t)Vh * lps;
+    for (int it = 0;; ++it) {
+        const int64_t gt = round_base(it, a.remap);
+        if (gt - threadIdx.x >= nthreads)
+            break;
+        if (gt % lps)
+            continue;
+        const int s = (int)(gt / lps);
+        if (s >= Vh)
+            continue;
         const dbl2 *b = a.b[j];
         dbl2 *x = a.xhi[j];
         v2 *rv = (v2 *)a.r + (size_t)j * 3 * Vh;
@@ -351,226 +747,7 @@ __global__ void __launch_bounds__(256) k_cg_init(CgArgs a)
     double tot;
     block_sum_multi<1>(nrm, lds, tot);
     if (threadIdx.x == 0)
-        partial_slot(a, j, 0)[blockIdx.x] = tot;
-}
-
-// ---- RU2: t = D (x_hi + x_lo) on the other parity, FP64 -----------------------------
-
-template <int LPS, bool MIXED>
-__global__ void __launch_bounds__(256) k_ru_dx(CgArgs a)
-{
-    const int j = blockIdx.y;
-    {
-        const SysState &st = a.st[j];
-        if (!(st.phase == PH_RUN && st.ru_pending))
-            return;
-    }
-    const int par = j / a.S, pout = 1 - par;
-    const int Vh = a.g.Vh;
-    int s, sub;
-    site_of_thread<LPS>(logical_block(blockIdx.x, gridDim.x, a.remap) * blockDim.x + threadIdx.x, s, sub);
-    if (s >= Vh)
-        return;
-    const dbl2 *xh = a.xhi[j];
-    const flt2 *xl = a.xlo + (size_t)j * 3 * Vh;
-    const bool act[1] = {true};
-    cplx<double> acc[1][3] = {{czero<double>(), czero<double>(), czero<double>()}};
-    auto load = [&](int, int n, cplx<double> *chi) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            dbl2 v = xh[(int64_t)c * Vh + n];
-            if constexpr (MIXED) {
-                const flt2 w = xl[(int64_t)c * Vh + n];
-                v.x += (double)w.x;
-                v.y += (double)w.y;
-            }
-            chi[c] = {v.x, v.y};
-        }
-    };
-    hop_accumulate<PrecF64, LPS, 1>(a.g, a.links64[pout], a.nbr[pout], pout, s, sub, act, acc, load);
-    dbl2 *t = a.tmp + (size_t)j * 3 * Vh;
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-        if (owns_colour<LPS>(sub, c))
-            t[(int64_t)c * Vh + s] = dbl2{acc[0][c].re, acc[0][c].im};
-}
-
-// ---- RU3: x_hi += x_lo, r = b - m^2 x_hi + D t in FP64 ----------------------------------
-
-template <class P, int LPS>
-__global__ void __launch_bounds__(256) k_ru_residual(CgArgs a)
-{
-    using real = typename P::real;
-    using v2 = typename vec2_of<real>::type;
-    constexpr bool MIXED = P::id != 0;
-    __shared__ double lds[4];
-    const int j = blockIdx.y;
-    {
-        const SysState &st = a.st[j];
-        if (!(st.phase == PH_RUN && st.ru_pending))
-            return;
-    }
-    const int par = j / a.S;
-    const int Vh = a.g.Vh;
-    int s, sub;
-    site_of_thread<LPS>(logical_block(blockIdx.x, gridDim.x, a.remap) * blockDim.x + threadIdx.x, s, sub);
-    double nrm[1] = {0.0};
-    if (s < Vh) {
-        const dbl2 *t = a.tmp + (size_t)j * 3 * Vh;
-        const bool act[1] = {true};
-        cplx<double> acc[1][3] = {{czero<double>(), czero<double>(), czero<double>()}};
-        auto load = [&](int, int n, cplx<double> *chi) { PrecF64::load_spinor(t, Vh, n, chi); };
-        hop_accumulate<PrecF64, LPS, 1>(a.g, a.links64[par], a.nbr[par], par, s, sub, act, acc, load);
-        const double m2 = a.st[j].mass2;
-        dbl2 *x = a.xhi[j];
-        const dbl2 *b = a.b[j];
-        v2 *rv = (v2 *)a.r + (size_t)j * 3 * Vh;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            if (!owns_colour<LPS>(sub, c))
-                continue;
-            const int64_t o = (int64_t)c * Vh + s;
-            dbl2 xv = x[o];
-            if constexpr (MIXED) {
-                const flt2 w = a.xlo[(size_t)j * 3 * Vh + o];
-                xv.x += (double)w.x;
-                xv.y += (double)w.y;
-                x[o] = xv;
-                a.xlo[(size_t)j * 3 * Vh + o] = flt2{0.f, 0.f};
-            }
-            const dbl2 bv = b[o];
-            const double rre = bv.x - m2 * xv.x + acc[0][c].re;
-            const double rim = bv.y - m2 * xv.y + acc[0][c].im;
-            rv[o] = v2{(real)rre, (real)rim};
-            nrm[0] += rre * rre + rim * rim;
-        }
-    }
-    double tot;
-    block_sum_multi<1>(nrm, lds, tot);
-    if (threadIdx.x == 0)
-        partial_slot(a, j, 0)[blockIdx.x] = tot;
-}
-
-// ---- finalize kernels: one block per system ---------------------------------------
-//
-// Launched right after the main kernel of the same role, with the main
-// kernel's block count.  The main kernels do not modify the state, so the
-// finalize kernel re-evaluates exactly the activity test the main kernel
-// used.
-
-enum FinRole { FIN_INIT = 0, FIN_AP = 1, FIN_UPDATE = 2, FIN_RU = 3 };
-
-template <int ROLE>
-__global__ void __launch_bounds__(256) k_cg_fin(CgArgs a, int nblk)
-{
-    __shared__ double lds[4];
-    const int j = blockIdx.x;
-    SysState &st = a.st[j];
-    bool act;
-    if (ROLE == FIN_INIT)
-        act = st.phase == PH_INIT;
-    else if (ROLE == FIN_RU)
-        act = st.phase == PH_RUN && st.ru_pending;
-    else
-        act = st.phase == PH_RUN && !st.ru_pending;
-    if (!act)
-        return;
-    const double v0 = reduce_partials(partial_slot(a, j, 0), nblk, lds);
-    double v1 = 0.0;
-    if (ROLE == FIN_AP)
-        v1 = reduce_partials(partial_slot(a, j, 1), nblk, lds);
-    if (threadIdx.x != 0)
-        return;
-    if (ROLE == FIN_INIT) {
-        const double bb = v0;
-        st.bb = bb;
-        st.stop2 = st.tol2 * bb;
-        st.rr = bb;
-        st.pp = bb;
-        st.maxr2 = bb;
-        st.iters = 0;
-        st.n_ru = 0;
-        st.restarts = 0;
-        st.ru_pending = 0;
-        st.stopping = 0;
-        st.beta = 0.0;
-        st.alpha = 0.0;
-        st.pcur = 0;
-        st.true_rr = bb;
-        if (!(bb < INFINITY)) {
-            st.phase = PH_DONE;
-            st.status = STAG_ENONFINITE;
-        } else if (bb == 0.0) {
-            st.phase = PH_DONE;
-            st.status = STAG_OK;
-            st.true_rr = 0.0;
-        } else {
-            st.phase = PH_RUN;
-        }
-    } else if (ROLE == FIN_AP) {
-        const double apap = v0, pp = v1;
-        st.pcur ^= 1;
-        st.pp = pp;
-        const double pap = st.mass2 * pp + apap;
-        if (!finite_pos(pap)) {
-            st.ru_pending = 1;
-            st.stopping = STAG_EBREAKDOWN;
-        } else {
-            st.alpha = st.rr / pap;
-        }
-    } else if (ROLE == FIN_UPDATE) {
-        const double rn = v0;
-        st.iters += 1;
-        if (!(rn < INFINITY)) {
-            st.ru_pending = 1;
-            st.stopping = STAG_EBREAKDOWN;
-        } else {
-            const bool conv = rn < st.stop2;
-            st.maxr2 = rn > st.maxr2 ? rn : st.maxr2;
-            bool recompute = conv || rn < st.delta2 * st.maxr2;
-            if (!conv && st.iters >= st.maxiter) {
-                st.stopping = STAG_ENOCONV;
-                recompute = true;
-            }
-            if (recompute) {
-                // beta is formed from the recomputed residual; rr keeps the
-                // previous iteration's value as its denominator
-                st.ru_pending = 1;
-            } else {
-                st.beta = rn / st.rr;
-                st.rr = rn;
-            }
-        }
-    } else {
-        const double trr = v0;
-        st.n_ru += 1;
-        st.ru_pending = 0;
-        st.true_rr = trr;
-        if (trr <= st.stop2) {
-            st.phase = PH_DONE;
-            st.status = STAG_OK;
-        } else if (st.stopping) {
-            st.phase = PH_DONE;
-            st.status = st.stopping;
-        } else if (!st.mixed) {
-            // FP64: the recursive residual claimed convergence but the true one
-            // disagrees: restart CG from the current x (fresh search direction).
-            st.restarts += 1;
-            if (st.restarts > st.max_restarts) {
-                st.phase = PH_DONE;
-                st.status = STAG_ENOCONV;
-            } else {
-                st.beta = 0.0;
-                st.rr = trr;
-                st.maxr2 = trr;
-            }
-        } else {
-            // reliable update: keep the search direction, continue from the true residual
-            st.beta = trr / st.rr;
-            st.rr = trr;
-            st.maxr2 = trr;
-        }
-    }
+        partial_slot(a, 0, j, 2)[blockIdx.x] = tot;
 }
 
 // ---- tuning probe: out_r = D in_r for R systems, no reductions -------------------

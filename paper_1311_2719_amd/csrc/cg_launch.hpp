@@ -8,11 +8,11 @@
 namespace stag {
 
 struct CgLaunchTable {
-    // K1 / K2 / probe take (lanes per site, right-hand sides per tile)
-    hipError_t (*ap)(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a);
-    hipError_t (*update)(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a);
-    hipError_t (*init)(dim3 grid, dim3 block, hipStream_t s, const CgArgs &a);
-    hipError_t (*ru_residual)(int lps, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a);
+    // K1 / K2 / probe take (lanes per site, right-hand sides per tile); ver
+    // selects the state and partial-sum buffers the step reads
+    hipError_t (*step1)(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a, int ver);
+    hipError_t (*step2)(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a, int ver);
+    hipError_t (*init)(dim3 grid, dim3 block, hipStream_t s, const CgArgs &a, int lps);
     // out_r = D in_r over grid.y tiles of R right-hand sides (tiles alternate parity)
     hipError_t (*probe)(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const Geom &g, const void *links,
                         const int32_t *nbr, const void *in, void *out, int remap);
@@ -21,7 +21,6 @@ struct CgLaunchTable {
 };
 
 const CgLaunchTable &cg_table(int prec);
-hipError_t launch_ru_dx(int lps, bool mixed, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a);
 
 // The table entries for one precision, generated from the kernel templates.
 #define STAG_LPS_SWITCH(KERNEL, P, R, ...)                                                     \
@@ -34,14 +33,14 @@ hipError_t launch_ru_dx(int lps, bool mixed, dim3 grid, dim3 block, hipStream_t 
     }
 
 template <class P, int R> struct RLaunch {
-    static hipError_t ap(int lps, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a)
+    static hipError_t step1(int lps, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a, int ver)
     {
-        STAG_LPS_SWITCH(k_cg_ap, P, R, a);
+        STAG_LPS_SWITCH(k_cg_step1, P, R, a, ver);
         return hipGetLastError();
     }
-    static hipError_t update(int lps, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a)
+    static hipError_t step2(int lps, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a, int ver)
     {
-        STAG_LPS_SWITCH(k_cg_update, P, R, a);
+        STAG_LPS_SWITCH(k_cg_step2, P, R, a, ver);
         return hipGetLastError();
     }
     static hipError_t probe(int lps, dim3 grid, dim3 block, hipStream_t s, const Geom &g, const void *links,
@@ -53,20 +52,9 @@ template <class P, int R> struct RLaunch {
 };
 
 template <class P> struct PLaunch {
-    static hipError_t init(dim3 grid, dim3 block, hipStream_t s, const CgArgs &a)
+    static hipError_t init(dim3 grid, dim3 block, hipStream_t s, const CgArgs &a, int lps)
     {
-        hipLaunchKernelGGL((k_cg_init<P>), grid, block, 0, s, a);
-        return hipGetLastError();
-    }
-    static hipError_t ru_residual(int lps, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a)
-    {
-        switch (lps) {
-        case 1: hipLaunchKernelGGL((k_ru_residual<P, 1>), grid, block, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_ru_residual<P, 2>), grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_ru_residual<P, 4>), grid, block, 0, s, a); break;
-        case 8: hipLaunchKernelGGL((k_ru_residual<P, 8>), grid, block, 0, s, a); break;
-        default: return hipErrorInvalidValue;
-        }
+        hipLaunchKernelGGL((k_cg_init<P>), grid, block, 0, s, a, lps);
         return hipGetLastError();
     }
 };

@@ -58,24 +58,6 @@ k_dslash64(Geom g, const dbl2 *__restrict__ links, const int32_t *__restrict__ n
 
 }  // namespace
 
-hipError_t launch_ru_dx(int lps, bool mixed, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a)
-{
-#define STAG_RU_DX(L)                                                                   \
-    if (mixed)                                                                          \
-        hipLaunchKernelGGL((k_ru_dx<L, true>), grid, block, 0, s, a);                  \
-    else                                                                                \
-        hipLaunchKernelGGL((k_ru_dx<L, false>), grid, block, 0, s, a);
-    switch (lps) {
-    case 1: STAG_RU_DX(1); break;
-    case 2: STAG_RU_DX(2); break;
-    case 4: STAG_RU_DX(4); break;
-    case 8: STAG_RU_DX(8); break;
-    default: return hipErrorInvalidValue;
-    }
-#undef STAG_RU_DX
-    return hipGetLastError();
-}
-
 static hipError_t launch_dslash64(const KernelCfg &cfg, const GaugeField *f, int par_fixed, int nparity, int offset,
                                   int count, const double *in, double *out, int accumulate, hipStream_t s)
 {

@@ -103,12 +103,33 @@ template <int LPS> __device__ __forceinline__ bool owns_colour(int sub, int c) {
 
 // ---- block reductions (deterministic: fixed shuffle tree, fixed LDS order) ----
 
+// A double moved across lanes by a DPP control (two 32-bit moves).
+template <int CTRL> __device__ __forceinline__ double dpp_move(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, lane), hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over the 64 lanes of a wavefront (every lane must be active), returned
+// in every lane.  Within each row of 16 lanes the sum is formed by DPP moves
+// (pairs, quads, half-row mirror, row mirror: no LDS round trips), then the
+// four row sums are added in a fixed order.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
-        v += __shfl_xor(v, o);
-    return v;
+    v += dpp_move<0xb1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_move<0x4e>(v);   // quad_perm [2,3,0,1]
+    v += dpp_move<0x141>(v);  // row_half_mirror
+    v += dpp_move<0x140>(v);  // row_mirror
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 // Sum v[r] over the block; thread r (< R) receives the total of column r.

@@ -174,8 +174,7 @@ bool Server::step_lane(Lane &l)
     Batch *B = l.batch.get();
     // keep one epoch queued beyond the outstanding snapshot
     if (B && l.active > 0 && !l.epoch_queued) {
-        const int ru_interval = l.prec != STAG_FP64 ? 2 : 1 << 30;
-        if (B->enqueue_epoch(ctx_->epoch_iters, ru_interval) == STAG_OK)
+        if (B->enqueue_epoch(ctx_->epoch_iters) == STAG_OK)
             l.epoch_queued = true;
         progress = true;
     }
@@ -187,8 +186,8 @@ bool Server::step_lane(Lane &l)
                 continue;
             bool done = true;
             for (int par = 0; par < 2; ++par) {
-                const int ph = B->state(par * B->slots() + s).phase;
-                done &= ph == PH_DONE || ph == PH_IDLE;
+                const int md = B->state(par * B->slots() + s).mode;
+                done &= md == M_DONE || md == M_IDLE;
             }
             if (done)
                 retire(l, s, STAG_OK);

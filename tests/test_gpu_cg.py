@@ -195,13 +195,15 @@ def test_repeatable_bitwise(gpu_ctx):
 def test_graph_replay_matches_eager_launches():
     # CG epochs are recorded once as HIP graphs and replayed many times per
     # solve; eager (non-graph) launches of the same kernels must give the same
-    # bits, for several solves in a row with host work in between
+    # bits, for several solves in a row with host work in between.  The kernel
+    # shape is pinned so both contexts run the same kernels.
     import os
 
     dims = (8, 8, 8, 8)
     U = inputs.smooth_su3(dims, 0.5, 131)
     srcs = [inputs.gaussian_source(dims, 132 + i) for i in range(3)]
     results = {}
+    os.environ["STAG_KERNEL_CFG"] = "2,128,1,0,1"
     for mode in ("1", "0"):
         os.environ["STAG_GRAPHS"] = mode
         try:
@@ -215,5 +217,6 @@ def test_graph_replay_matches_eager_launches():
                 results[mode] = out
         finally:
             del os.environ["STAG_GRAPHS"]
+    del os.environ["STAG_KERNEL_CFG"]
     for (xg, ig, rg), (xe, ie, re_) in zip(results["1"], results["0"]):
         assert ig == ie and rg == re_ and np.array_equal(xg, xe)
