@@ -14,8 +14,9 @@ solves/s over the K timed steps.
 The same line reports:
   roofline      the FP64 D_slash kernel: 100 full-lattice applications per
                 run, each bracketed by HIP events on the library's stream;
-                achieved = 1248 B per output site (8 links + 1 gathered input
-                vector + 1 output vector) x V / mean duration;
+                achieved = algorithmic bytes per output site (8 links + 1
+                gathered input vector + 1 output vector: 864 B with two
+                stored link rows, 1248 B with three) x V / mean duration;
   mixed         FP32 and FP16 (reliable-update) solves/s on the same system;
   cpu_baseline  the FP64 CPU oracle solving the same system on the host cores.
 
@@ -39,7 +40,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "CG solves/s to 1e-10 (mixed vs FP64) + D_slash HBM GB/s % of peak; p99"
 HBM_PEAK_GBS = 8000.0
-DSLASH_BYTES_PER_SITE = 1248  # FP64: 8 x 144 B links + 48 B gathered input + 48 B output
+def dslash_bytes_per_site(rows: int) -> int:
+    """FP64 D_slash algorithmic bytes per output site: 8 links of 3 x rows
+    complex entries, one gathered input vector and one output vector."""
+    return 8 * 3 * rows * 16 + 48 + 48
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_f64_16x16x16x16_traffic.txt")
 KERNEL_SOURCES = ["dslash.hip", "hop.hpp", "stag_types.hpp"]
 
@@ -98,31 +102,61 @@ def timed_solves(ctx, f, b, x, steps, warmup, **kw):
     return time.perf_counter() - t0, infos
 
 
-def dslash_timing(ctx, f, b, reps):
-    """Per-launch durations (s) of the full-lattice FP64 D_slash, from HIP
-    events recorded on the stream the library launches on."""
+def dslash_timing(ctx, f, b, reps, **kw):
+    """Per-launch durations (s) of the FP64 D_slash (full lattice unless kw
+    names a parity and site range), from HIP events recorded on the stream
+    the library launches on; and the mean over the same launches back to
+    back under one event pair."""
     import torch
 
     out = ctx.new_fermion(f)
     s = ctx.stream
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
     for _ in range(10):
-        ctx.dslash(f, b, out)
+        ctx.dslash(f, b, out, **kw)
     torch.cuda.synchronize()
     for e0, e1 in ev:
         e0.record(s)
-        ctx.dslash(f, b, out)
+        ctx.dslash(f, b, out, **kw)
         e1.record(s)
     torch.cuda.synchronize()
     per_launch = np.array([e0.elapsed_time(e1) * 1e-3 for e0, e1 in ev])
-    # the same launches back to back, one event pair around all of them
     a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a0.record(s)
     for _ in range(reps):
-        ctx.dslash(f, b, out)
+        ctx.dslash(f, b, out, **kw)
     a1.record(s)
     torch.cuda.synchronize()
     return per_launch, a0.elapsed_time(a1) * 1e-3 / reps
+
+
+def dslash_cold(ctx, dims, copies, reps):
+    """Mean duration (s) of a full-lattice FP64 D_slash when consecutive
+    launches cycle over `copies` distinct fields and sources of shape dims
+    (their working set exceeds the 256 MB Infinity Cache)."""
+    import torch
+
+    from paper_1311_2719_amd import inputs
+
+    fields, ins, outs = [], [], []
+    for i in range(copies):
+        f = ctx.set_gauge(dims, inputs.smooth_su3(dims, 0.3, seed=500 + i))
+        fields.append(f)
+        ins.append(ctx.pack(f, inputs.gaussian_source(dims, seed=600 + i)))
+        outs.append(ctx.new_fermion(f))
+    for i in range(2 * copies):
+        ctx.dslash(fields[i % copies], ins[i % copies], outs[i % copies])
+    torch.cuda.synchronize()
+    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a0.record(ctx.stream)
+    for i in range(reps):
+        ctx.dslash(fields[i % copies], ins[i % copies], outs[i % copies])
+    a1.record(ctx.stream)
+    torch.cuda.synchronize()
+    rows = ctx.link_rows(fields[0])
+    for f in fields:
+        ctx.free_gauge(f)
+    return a0.elapsed_time(a1) * 1e-3 / reps, rows
 
 
 def cpu_baseline(dims, U, b, m, tol, gpu_iters):
@@ -135,7 +169,7 @@ def cpu_baseline(dims, U, b, m, tol, gpu_iters):
         x, _, info = oracle.cg_solve(dims, U, m, b, tol=tol)
         n += 1
         it = info["iters"]
-        if time.perf_counter() - t0 > 5.0 or n >= 10:
+        if time.perf_counter() - t0 > 12.0 or n >= 40:
             break
     dt = (time.perf_counter() - t0) / n
     return {"value": 1.0 / dt, "unit": "solves/s", "cores": oracle.max_threads(), "kind": "oracle",
@@ -166,7 +200,8 @@ def run_default(args):
 
     print("bench: D_slash x%d" % args.dslash_reps, file=sys.stderr, flush=True)
     durs, mean = dslash_timing(ctx, f, b, args.dslash_reps)
-    algo_bytes = DSLASH_BYTES_PER_SITE * V
+    rows = ctx.link_rows(f)
+    algo_bytes = dslash_bytes_per_site(rows) * V
     achieved = algo_bytes / mean / 1e9
     traffic = read_traffic(V)
     tune = ctx.tune_info(f)
@@ -182,10 +217,17 @@ def run_default(args):
                            "reliable_updates": inf2[-1]["reliable_updates"],
                            "true_rel_resid": inf2[-1]["true_rel_resid"], "ok": ok}
 
-    d32 = None
+    d32 = cold = shard = None
     if not args.no_dslash32:
-        # 32^4: a working set (1.3 GB per application) far beyond the 256 MB
-        # Infinity Cache, so the bandwidth here is HBM bandwidth
+        # cold: 8 distinct 16^4 fields cycled, so consecutive launches do not
+        # find their links in the Infinity Cache
+        print("bench: D_slash 16^4 cold (8 fields)", file=sys.stderr, flush=True)
+        cmean, crows = dslash_cold(ctx, dims, 8, 80)
+        cold = {"lattice": list(dims), "fields": 8, "mean_us": cmean * 1e6,
+                "gbs": dslash_bytes_per_site(crows) * V / cmean / 1e9,
+                "frac": dslash_bytes_per_site(crows) * V / cmean / 1e9 / HBM_PEAK_GBS, "link_rows": crows}
+        # 32^4: a working set (0.9 GB per application with two link rows) far
+        # beyond the Infinity Cache, so the bandwidth here is HBM bandwidth
         print("bench: D_slash 32^4", file=sys.stderr, flush=True)
         dims32 = (32, 32, 32, 32)
         U32 = inputs.unit_links(dims32)
@@ -194,10 +236,19 @@ def run_default(args):
         b32 = ctx.pack(f32, inputs.gaussian_source(dims32, seed=203))
         d, dmean = dslash_timing(ctx, f32, b32, 50)
         V32 = int(np.prod(dims32))
+        r32 = ctx.link_rows(f32)
         d32 = {"lattice": list(dims32), "mean_us": dmean * 1e6, "p99_us": float(np.percentile(d, 99) * 1e6),
-               "gbs": DSLASH_BYTES_PER_SITE * V32 / dmean / 1e9,
-               "frac": DSLASH_BYTES_PER_SITE * V32 / dmean / 1e9 / HBM_PEAK_GBS,
-               "config": ctx.tune_info(f32)}
+               "gbs": dslash_bytes_per_site(r32) * V32 / dmean / 1e9,
+               "frac": dslash_bytes_per_site(r32) * V32 / dmean / 1e9 / HBM_PEAK_GBS,
+               "link_rows": r32, "config": ctx.tune_info(f32)}
+        # one GPU's share of a 16-GPU split of the 32^4 operator (the paper's
+        # site-range decomposition): odd-parity sites [0, V/16), full input
+        print("bench: D_slash 32^4 one share of 16", file=sys.stderr, flush=True)
+        n_share = V32 // 16
+        d, smean = dslash_timing(ctx, f32, b32, 50, out_parity=binding.ODD, offset=0, count=n_share)
+        shard = {"lattice": list(dims32), "out_parity": "odd", "sites": n_share, "mean_us": smean * 1e6,
+                 "p99_us": float(np.percentile(d, 99) * 1e6),
+                 "gbs": dslash_bytes_per_site(r32) * n_share / smean / 1e9}
         ctx.free_gauge(f32)
         del b32
 
@@ -225,7 +276,7 @@ def run_default(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_dslash64 (full lattice, FP64)", "algorithmic_bytes_per_launch": algo_bytes,
-                     "mean_us": mean * 1e6},
+                     "bytes_per_site": dslash_bytes_per_site(rows), "link_rows": rows, "mean_us": mean * 1e6},
         "dslash": {"p50_us": float(np.percentile(durs, 50) * 1e6), "p99_us": float(np.percentile(durs, 99) * 1e6),
                    "mean_event_pair_us": float(durs.mean() * 1e6), "launches": int(len(durs)), "config": tune,
                    "timing": "mean_us: one event pair around %d back-to-back launches; p50/p99: an event pair "
@@ -233,7 +284,9 @@ def run_default(args):
         "solve": {"iters": info["iters"], "reliable_updates": info["reliable_updates"],
                   "true_rel_resid": info["true_rel_resid"]},
         "mixed": mixed,
+        "dslash_16_cold": cold,
         "dslash_32": d32,
+        "dslash_32_share": shard,
         "cpu_baseline": cpu,
     }
     ctx.close()

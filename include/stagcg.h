@@ -138,7 +138,11 @@ int stag_arena_usage(const stag_ctx *ctx, size_t *used, size_t *total);
  * builds the daggered backward links (the paper's `ud`) stored at the site
  * that uses them, reorders everything into a checkerboard
  * structure-of-arrays layout, and keeps FP64, FP32 and FP16 copies plus the
- * iup/idn neighbour tables resident in the arena.
+ * iup/idn neighbour tables resident in the arena.  When every link is
+ * special unitary (each stored matrix then has row 2 = conj(row 0 x row 1)
+ * divided by its folded factor, to within 1e-14 absolute), only two rows
+ * are kept and the kernels rebuild the third; otherwise all three rows are
+ * kept.  The environment variable STAG_LINK_ROWS=3 keeps three rows always.
  * Errors: EINVAL (bad dims), ENOMEM, ENONFINITE (NaN/Inf in the links).
  * Synchronous.
  */
@@ -151,6 +155,10 @@ int stag_free_gauge(stag_ctx *ctx, int32_t gauge_id);
 
 /* Lattice extents of a registered field. */
 int stag_gauge_dims(stag_ctx *ctx, int32_t gauge_id, int32_t dims[4]);
+
+/* Link rows stored for a registered field: 2 (third row rebuilt in the
+ * kernels) or 3.  Errors: EINVAL (NULL), ENOENT (unknown id). */
+int stag_gauge_link_rows(stag_ctx *ctx, int32_t gauge_id, int32_t *rows);
 
 /* ---- layout conversion ----------------------------------------------- */
 

@@ -87,6 +87,7 @@ def load():
             "stag_set_gauge": ([P, P, P, I32, I32, ctypes.POINTER(I32)], ctypes.c_int),
             "stag_free_gauge": ([P, I32], ctypes.c_int),
             "stag_gauge_dims": ([P, I32, P], ctypes.c_int),
+            "stag_gauge_link_rows": ([P, I32, ctypes.POINTER(I32)], ctypes.c_int),
             "stag_pack_fermion": ([P, P, P, P, P], ctypes.c_int),
             "stag_unpack_fermion": ([P, P, P, P, P], ctypes.c_int),
             "stag_dslash": ([P, I32, I32, I64, I64, P, P, I32, P], ctypes.c_int),
@@ -114,7 +115,7 @@ def exported_symbols():
     """Names of the C ABI entry points the binding expects."""
     return [
         "stag_create", "stag_destroy", "stag_last_error", "stag_arena_usage", "stag_set_gauge",
-        "stag_free_gauge", "stag_gauge_dims", "stag_pack_fermion", "stag_unpack_fermion", "stag_dslash",
+        "stag_free_gauge", "stag_gauge_dims", "stag_gauge_link_rows", "stag_pack_fermion", "stag_unpack_fermion", "stag_dslash",
         "stag_cg_solve", "stag_cg_solve_batch", "stag_submit", "stag_poll", "stag_wait",
         "stag_release_ticket", "stag_serve_config", "stag_tune_info", "stag_version",
     ]
@@ -213,6 +214,12 @@ class Context:
         f = Field(gid.value, tuple(int(v) for v in d))
         self.fields[gid.value] = f
         return f
+
+    def link_rows(self, field: Field) -> int:
+        """Link rows the library stores for `field` (2: third row rebuilt, or 3)."""
+        rows = ctypes.c_int32()
+        _check(self.lib.stag_gauge_link_rows(self.h, field.gauge_id, ctypes.byref(rows)), "stag_gauge_link_rows")
+        return rows.value
 
     def free_gauge(self, field: Field):
         _check(self.lib.stag_free_gauge(self.h, field.gauge_id), "stag_free_gauge")

@@ -92,8 +92,9 @@ int Batch::create()
     tmp_ = (dbl2 *)take(nsys * 3 * Vh * 16);
     xhi_d_ = (dbl2 **)take(nsys * sizeof(void *));
     b_d_ = (const dbl2 **)take(nsys * sizeof(void *));
-    st_d_[0] = (SysState *)take(nsys * sizeof(SysState));
-    st_d_[1] = (SysState *)take(nsys * sizeof(SysState));
+    // the two state buffers are adjacent, so one copy takes a snapshot of both
+    st_d_[0] = (SysState *)take(2 * nsys * sizeof(SysState));
+    st_d_[1] = st_d_[0] ? st_d_[0] + nsys : nullptr;
     perm_d_ = (int *)take(nsys * sizeof(int));
     partials_ = (double *)take(2 * nsys * 3 * (size_t)pstride_ * sizeof(double));
 
@@ -137,6 +138,13 @@ int Batch::create()
     STAG_HIP_CHECK(hipMemcpyAsync(perm_d_, perm_h_, nsys * sizeof(int), hipMemcpyHostToDevice, s_));
     STAG_HIP_CHECK(hipEventRecord(stage_ev_, s_));
     stage_busy_ = true;
+    // record the epochs the solve driver chooses from (powers of two) now,
+    // outside any solve
+    for (int E = 2; use_graphs_ && E <= kEpochMax; E *= 2) {
+        int rc = record_epoch(E);
+        if (rc != STAG_OK)
+            return rc;
+    }
     return STAG_OK;
 }
 
@@ -167,7 +175,7 @@ int Batch::set_running(const std::vector<char> &running)
 // Time K1 + K2 of one step with every system in a CG step on filled vectors.
 double Batch::time_cg_config(const KernelCfg &c)
 {
-    const CgLaunchTable &t = cg_table(prec_);
+    const CgLaunchTable &t = cg_table(prec_, f_->rows);
     CgArgs a = args();
     for (int par = 0; par < 2; ++par)
         a.nbr[par] = c.tables ? f_->nbr_for(par) : nullptr;
@@ -198,7 +206,7 @@ KernelCfg Batch::tune_cg()
     best.rtile = 1;
     best.tables = 0;
     best.remap = 1;
-    const CgLaunchTable &t = cg_table(prec_);
+    const CgLaunchTable &t = cg_table(prec_, f_->rows);
     for (int i = 0; i < t.n_rtiles; ++i)
         if (S_ % t.rtiles[i] == 0)
             best.rtile = std::max(best.rtile, t.rtiles[i]);
@@ -323,7 +331,7 @@ int Batch::upload_and_init(const std::vector<int> &systems)
     STAG_HIP_CHECK(hipEventRecord(stage_ev_, s_));
     stage_busy_ = true;
     const CgArgs a = args();
-    const CgLaunchTable &t = cg_table(prec_);
+    const CgLaunchTable &t = cg_table(prec_, f_->rows);
     dim3 grid((unsigned)grid_x(cfg_), (unsigned)nsys());
     hipError_t e = t.init(grid, dim3(cfg_.block), s_, a, cfg_.lps);
     if (e != hipSuccess)
@@ -361,7 +369,7 @@ CgArgs Batch::args() const
 
 int Batch::launch_step(int ver, hipStream_t st)
 {
-    const CgLaunchTable &t = cg_table(prec_);
+    const CgLaunchTable &t = cg_table(prec_, f_->rows);
     const CgArgs a = args();
     const int R = cfg_.rtile;
     dim3 grid((unsigned)grid_x(cfg_), (unsigned)(nsys() / R)), blk(cfg_.block);
@@ -370,6 +378,32 @@ int Batch::launch_step(int ver, hipStream_t st)
         e = t.step2(cfg_.lps, R, grid, blk, st, a, ver);
     if (e != hipSuccess)
         return set_error(STAG_EHIP, "CG kernel launch failed: %s", hipGetErrorString(e));
+    return STAG_OK;
+}
+
+int Batch::record_epoch(int steps)
+{
+    if (graphs_.count(steps))
+        return STAG_OK;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    STAG_HIP_CHECK(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
+    int rc = STAG_OK;
+    for (int k = 0; k < steps && rc == STAG_OK; ++k)
+        rc = launch_step(k & 1, cap_stream_);
+    hipError_t e = hipStreamEndCapture(cap_stream_, &graph);
+    if (rc != STAG_OK) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess)
+        return set_error(STAG_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess)
+        return set_error(STAG_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+    graphs_.emplace(steps, exec);
     return STAG_OK;
 }
 
@@ -387,28 +421,10 @@ int Batch::enqueue_epoch(int steps)
     // The kernel arguments of an epoch depend only on this workspace, so an
     // epoch of a given length is recorded once and replayed: the launches of
     // all its kernels cost one graph launch on the host.
+    int rc = record_epoch(steps);
+    if (rc != STAG_OK)
+        return rc;
     auto it = graphs_.find(steps);
-    if (it == graphs_.end()) {
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        STAG_HIP_CHECK(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
-        int rc = STAG_OK;
-        for (int k = 0; k < steps && rc == STAG_OK; ++k)
-            rc = launch_step(k & 1, cap_stream_);
-        hipError_t e = hipStreamEndCapture(cap_stream_, &graph);
-        if (rc != STAG_OK) {
-            if (graph)
-                (void)hipGraphDestroy(graph);
-            return rc;
-        }
-        if (e != hipSuccess)
-            return set_error(STAG_EHIP, "graph capture failed: %s", hipGetErrorString(e));
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (e != hipSuccess)
-            return set_error(STAG_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
-        it = graphs_.emplace(steps, exec).first;
-    }
     STAG_HIP_CHECK(hipGraphLaunch(it->second, s_));
     return STAG_OK;
 }
@@ -542,29 +558,44 @@ void drop_cached_batches(Ctx *ctx, int32_t gauge_id)
     dead.clear();
 }
 
-// Iterations left for the slowest running system, from the decrease of its
-// residual since the previous snapshot (large when unknown).
-static int estimate_remaining(const Batch &B, std::vector<std::pair<int, double>> &prev)
+// Iterations left for the slowest running system.  A system's rate of
+// convergence (decrease of log <r,r> per iteration) is the larger of its mean
+// rate since the start of the solve and its rate over the iterations since
+// the previous look, if there were at least 8 (the CG residual is not
+// monotonic, so a shorter span says little); with neither known the result
+// is kUnknownRemaining.
+struct ConvergenceTrack {
+    int iters = 0;
+    double rr = 0.0;
+};
+constexpr int kUnknownRemaining = 1 << 20;
+
+static int estimate_remaining(const Batch &B, std::vector<ConvergenceTrack> &track)
 {
     double worst = 0;
     bool known = true;
     for (int j = 0; j < B.nsys(); ++j) {
         const SysState &st = B.state(j);
-        if (st.mode != M_CG && st.mode != M_RU) {
-            prev[j] = {st.iters, st.rr};
-            continue;
+        ConvergenceTrack &t = track[j];
+        const bool running = st.mode == M_CG || st.mode == M_RU;
+        if (running) {
+            double rate = 0.0;
+            if (st.iters > 0 && st.bb > st.rr && st.rr > 0)
+                rate = std::log(st.bb / st.rr) / st.iters;
+            const int di = st.iters - t.iters;
+            if (di >= 8 && t.rr > st.rr && st.rr > 0)
+                rate = std::max(rate, std::log(t.rr / st.rr) / di);
+            if (rate > 0 && st.stop2 > 0)
+                worst = std::max(worst, std::log(std::max(st.rr / st.stop2, 1.0)) / rate);
+            else
+                known = false;
         }
-        const int di = st.iters - prev[j].first;
-        if (di > 0 && st.rr > 0 && prev[j].second > st.rr && st.stop2 > 0) {
-            const double rate = std::log(prev[j].second / st.rr) / di;
-            const double rem = std::log(st.rr / st.stop2) / rate;
-            worst = std::max(worst, rem);
-        } else {
-            known = false;
+        if (!running || st.iters - t.iters >= 8) {
+            t.iters = st.iters;
+            t.rr = st.rr;
         }
-        prev[j] = {st.iters, st.rr};
     }
-    return known ? (int)std::ceil(worst) : 1 << 20;
+    return known ? (int)std::ceil(worst) : kUnknownRemaining;
 }
 
 int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs, const stag_cg_params *params,
@@ -602,10 +633,12 @@ int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs, con
     }
     if ((rc = B.upload_and_init(systems)) != STAG_OK)
         return rc;
-    int E = 8, Emax = 64;
-    if (const char *e = getenv("STAG_EPOCH"))
-        E = Emax = std::max(1, atoi(e));
-    std::vector<std::pair<int, double>> prev(B.nsys(), {0, 0.0});
+    int E = 8, Emax = kEpochMax;
+    const bool fixed_epoch = getenv("STAG_EPOCH") != nullptr;
+    const bool epoch_log = getenv("STAG_EPOCH_VERBOSE") != nullptr;
+    if (fixed_epoch)
+        E = Emax = std::max(1, atoi(getenv("STAG_EPOCH")));
+    std::vector<ConvergenceTrack> track(B.nsys());
     // pipelined: epoch n+1 is queued before the state after epoch n is read
     if ((rc = B.enqueue_epoch(E)) != STAG_OK || (rc = B.enqueue_snapshot()) != STAG_OK)
         return rc;
@@ -614,6 +647,7 @@ int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs, con
     while (!done && budget > 0) {
         if ((rc = B.enqueue_epoch(E)) != STAG_OK)
             return rc;
+        const int inflight = E;
         budget -= E;
         if ((rc = B.wait_snapshot()) != STAG_OK)
             return rc;
@@ -629,12 +663,21 @@ int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs, con
                 running[j] = B.state(j).mode == M_INIT || B.state(j).mode == M_CG || B.state(j).mode == M_RU;
             if ((rc = B.set_running(running)) != STAG_OK)
                 return rc;
-            const int rem = estimate_remaining(B, prev);
+            // steps still needed after the state just read (CG steps to the
+            // stopping test plus the final FP64 check), less the epoch in
+            // flight; the next epoch covers about half of them (an epoch too
+            // short costs a look at the state, which overlaps the epoch in
+            // flight; one too long costs idle steps).  The shortest epoch is
+            // 2 steps; 16 while the rate of convergence is not known yet.
+            const int rem = estimate_remaining(B, track);
+            const int ahead = rem == kUnknownRemaining ? 32 : rem + 1 - inflight;
             E = 2;
-            while (E * 2 <= std::min(Emax, rem / 2))
+            while (E * 2 <= std::min(Emax, ahead / 2))
                 E *= 2;
-            if (getenv("STAG_EPOCH"))
+            if (fixed_epoch)
                 E = Emax;
+            if (epoch_log)
+                fprintf(stderr, "[stag epoch] in flight %d, remaining %d, next %d\n", inflight, rem, E);
             if ((rc = B.enqueue_snapshot()) != STAG_OK)
                 return rc;
         }

@@ -10,6 +10,9 @@
 
 namespace stag {
 
+// Longest epoch (CG steps between two looks at the state) of a solve.
+constexpr int kEpochMax = 64;
+
 class Batch {
 public:
     Batch(Ctx *ctx, std::shared_ptr<GaugeField> f, int prec, int slots, hipStream_t s);
@@ -37,6 +40,8 @@ public:
     // Enqueue `steps` CG steps (rounded up to an even number, so that every
     // epoch starts from state buffer 0).
     int enqueue_epoch(int steps);
+    // Record (once) the graph of an epoch of `steps` steps.
+    int record_epoch(int steps);
     // Enqueue a copy of the device state into the host snapshot and record an
     // event; wait_snapshot blocks until it has arrived.
     int enqueue_snapshot();

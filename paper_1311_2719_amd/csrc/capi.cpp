@@ -117,11 +117,40 @@ int stag_set_gauge(stag_ctx *ctx, const int32_t dims[4], const double *links, in
     memcpy(f->dims, dims, sizeof(f->dims));
     f->tap = t_antiperiodic ? 1 : 0;
     f->g = make_geom(dims);
+    f->g.tap = f->tap;
     const size_t Vh = f->g.Vh;
-    const size_t lbytes[3] = {2 * 8 * 9 * Vh * 16, 2 * 8 * 9 * Vh * 8, 2 * 8 * 9 * Vh * 4};
+    hipStream_t s = c->stream;
+    // the caller's links on the device (staged through the arena if on the host)
+    const size_t in_bytes = 2 * Vh * 4 * 9 * 16;
+    const double *src = links;
+    void *staging = nullptr;
+    if (!links_on_device) {
+        staging = c->arena.alloc(in_bytes);
+        if (!staging)
+            return set_error(STAG_ENOMEM, "stag_set_gauge: arena exhausted (staging %zu bytes)", in_bytes);
+        hipError_t e = hipMemcpyAsync(staging, links, in_bytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) {
+            c->arena.release(staging);
+            return set_error(STAG_EHIP, "stag_set_gauge: copy failed: %s", hipGetErrorString(e));
+        }
+        src = (const double *)staging;
+    }
+    struct StagingGuard {
+        Arena &arena;
+        void *p;
+        ~StagingGuard() { arena.release(p); }
+    } staging_guard{c->arena, staging};
+    // two stored rows when every folded link admits it (STAG_LINK_ROWS=3 keeps all three)
+    bool two_rows = false;
+    int rc = gauge_check(c, f->g, src, s, two_rows);
+    if (rc != STAG_OK)
+        return rc;
+    const char *rows_env = getenv("STAG_LINK_ROWS");
+    f->rows = two_rows && !(rows_env && atoi(rows_env) == 3) ? 2 : 3;
     for (int p = 0; p < 3; ++p) {
-        f->links[p] = c->arena.alloc(lbytes[p]);
-        f->bytes += lbytes[p];
+        const size_t lb = (size_t)2 * link_parity_entries(f->rows, (int)Vh) * link_entry_bytes_of(p);
+        f->links[p] = c->arena.alloc(lb);
+        f->bytes += lb;
     }
     f->nbr = (int32_t *)c->arena.alloc(2 * 8 * Vh * sizeof(int32_t));
     f->bytes += 2 * 8 * Vh * sizeof(int32_t);
@@ -134,27 +163,7 @@ int stag_set_gauge(stag_ctx *ctx, const int32_t dims[4], const double *links, in
         release_all();
         return set_error(STAG_ENOMEM, "stag_set_gauge: arena exhausted (%zu bytes needed)", f->bytes);
     }
-    const size_t in_bytes = 2 * Vh * 4 * 9 * 16;
-    const double *src = links;
-    void *staging = nullptr;
-    hipStream_t s = c->stream;
-    if (!links_on_device) {
-        staging = c->arena.alloc(in_bytes);
-        if (!staging) {
-            release_all();
-            return set_error(STAG_ENOMEM, "stag_set_gauge: arena exhausted (staging %zu bytes)", in_bytes);
-        }
-        hipError_t e = hipMemcpyAsync(staging, links, in_bytes, hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) {
-            c->arena.release(staging);
-            release_all();
-            return set_error(STAG_EHIP, "stag_set_gauge: copy failed: %s", hipGetErrorString(e));
-        }
-        src = (const double *)staging;
-    }
-    int rc = gauge_prepare(c, f.get(), src, s);
-    if (staging)
-        c->arena.release(staging);
+    rc = gauge_prepare(f.get(), src, s);
     if (rc != STAG_OK) {
         release_all();
         return rc;
@@ -206,6 +215,17 @@ int stag_gauge_dims(stag_ctx *ctx, int32_t gauge_id, int32_t dims[4])
     if (!f)
         return set_error(STAG_ENOENT, "unknown gauge id %d", gauge_id);
     memcpy(dims, f->dims, sizeof(f->dims));
+    return STAG_OK;
+}
+
+int stag_gauge_link_rows(stag_ctx *ctx, int32_t gauge_id, int32_t *rows)
+{
+    if (!ctx || !rows)
+        return set_error(STAG_EINVAL, "NULL argument");
+    auto f = reinterpret_cast<Ctx *>(ctx)->field(gauge_id);
+    if (!f)
+        return set_error(STAG_ENOENT, "unknown gauge id %d", gauge_id);
+    *rows = f->rows;
     return STAG_OK;
 }
 

@@ -1,63 +1,9 @@
-// Kernel instantiations and launch table for the F16 working precision.
+// CG step kernels, initialisation and tuning probe for the F16 working
+// precision, all three link rows stored.
 #include "cg_launch.hpp"
 
 namespace stag {
 
-namespace {
-
-using P = PrecF16;
-const int kTiles[] = {1, 2, 3, 4, 6, 8, 12};
-
-hipError_t step1(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a, int ver)
-{
-    switch (R) {
-    case 1: return RLaunch<P, 1>::step1(lps, grid, block, s, a, ver);
-    case 2: return RLaunch<P, 2>::step1(lps, grid, block, s, a, ver);
-    case 3: return RLaunch<P, 3>::step1(lps, grid, block, s, a, ver);
-    case 4: return RLaunch<P, 4>::step1(lps, grid, block, s, a, ver);
-    case 6: return RLaunch<P, 6>::step1(lps, grid, block, s, a, ver);
-    case 8: return RLaunch<P, 8>::step1(lps, grid, block, s, a, ver);
-    case 12: return RLaunch<P, 12>::step1(lps, grid, block, s, a, ver);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t step2(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a, int ver)
-{
-    switch (R) {
-    case 1: return RLaunch<P, 1>::step2(lps, grid, block, s, a, ver);
-    case 2: return RLaunch<P, 2>::step2(lps, grid, block, s, a, ver);
-    case 3: return RLaunch<P, 3>::step2(lps, grid, block, s, a, ver);
-    case 4: return RLaunch<P, 4>::step2(lps, grid, block, s, a, ver);
-    case 6: return RLaunch<P, 6>::step2(lps, grid, block, s, a, ver);
-    case 8: return RLaunch<P, 8>::step2(lps, grid, block, s, a, ver);
-    case 12: return RLaunch<P, 12>::step2(lps, grid, block, s, a, ver);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t probe(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const Geom &g, const void *links,
-                 const int32_t *nbr, const void *in, void *out, int remap)
-{
-    switch (R) {
-    case 1: return RLaunch<P, 1>::probe(lps, grid, block, s, g, links, nbr, in, out, remap);
-    case 2: return RLaunch<P, 2>::probe(lps, grid, block, s, g, links, nbr, in, out, remap);
-    case 3: return RLaunch<P, 3>::probe(lps, grid, block, s, g, links, nbr, in, out, remap);
-    case 4: return RLaunch<P, 4>::probe(lps, grid, block, s, g, links, nbr, in, out, remap);
-    case 6: return RLaunch<P, 6>::probe(lps, grid, block, s, g, links, nbr, in, out, remap);
-    case 8: return RLaunch<P, 8>::probe(lps, grid, block, s, g, links, nbr, in, out, remap);
-    case 12: return RLaunch<P, 12>::probe(lps, grid, block, s, g, links, nbr, in, out, remap);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-}  // namespace
-
-const CgLaunchTable &cg_table_f16()
-{
-    static const CgLaunchTable t = {step1, step2, PLaunch<P>::init,
-                                    probe, kTiles, (int)(sizeof(kTiles) / sizeof(kTiles[0]))};
-    return t;
-}
+const CgLaunchTable &cg_table_f16() { return TileTable<PrecF16, 3, 1, 2, 3, 4, 6, 8, 12>::table(); }
 
 }  // namespace stag

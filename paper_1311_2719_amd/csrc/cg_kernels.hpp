@@ -203,7 +203,8 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 __device__ __forceinline__ double uniform(double v)
 {
     const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u), hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
@@ -341,7 +342,7 @@ __device__ __forceinline__ int64_t round_base(int it, int remap)
 
 // ---- K1 -----------------------------------------------------------------------------
 
-template <class P, int LPS, int R>
+template <class P, int LPS, int R, int ROWS>
 __global__ void __launch_bounds__(256) k_cg_step1(CgArgs a, int ver)
 {
     using real = typename P::real;
@@ -364,14 +365,17 @@ __global__ void __launch_bounds__(256) k_cg_step1(CgArgs a, int ver)
         if (r < R) {
             const int j = a.perm[k0 + r];
             SysState st = sst[r];
-            if (j >= 0 && st.mode != M_IDLE && st.mode != M_DONE) {
+            const bool live = j >= 0 && st.mode != M_IDLE && st.mode != M_DONE;
+            if (live) {
                 const double tot[3] = {wave_total(lds, 3 * r), wave_total(lds, 3 * r + 1), wave_total(lds, 3 * r + 2)};
                 advance(st, tot);
-                if (blockIdx.x == 0)
-                    a.st[ver ^ 1][j] = st;
-            } else {
-                st.mode = M_IDLE;  // not running: nothing to do in this step
             }
+            // the state K2 of this step reads: advanced, or the same idle/done
+            // state (never the stale one of two kernels ago)
+            if (j >= 0 && blockIdx.x == 0)
+                a.st[ver ^ 1][j] = st;
+            if (!live)
+                st.mode = M_IDLE;  // not running: nothing to do in this step
             sst[r] = st;
         }
         __syncthreads();
@@ -424,8 +428,8 @@ __global__ void __launch_bounds__(256) k_cg_step1(CgArgs a, int ver)
                     chi[c].im = fma(beta[r], pv[c].im, t.y);
                 }
             };
-            hop_accumulate<P, LPS, R>(a.g, (const typename P::link_t *)a.links[pout], a.nbr[pout], pout, s, sub,
-                                      cg, acc, load);
+            hop_accumulate<P, LPS, R, decltype(load), false, ROWS>(a.g, (const typename P::link_t *)a.links[pout],
+                                                                   a.nbr[pout], pout, s, sub, cg, acc, load);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 if (!cg[r])
@@ -506,8 +510,8 @@ __global__ void __launch_bounds__(256) k_cg_step1(CgArgs a, int ver)
                         chi[c] = {v.x, v.y};
                     }
                 };
-                hop_accumulate<PrecF64, LPS, 1, decltype(load), true>(a.g, a.links64[pout], a.nbr[pout], pout, s,
-                                                                      sub, one, acc, load);
+                hop_accumulate<PrecF64, LPS, 1, decltype(load), true, ROWS>(a.g, a.links64[pout], a.nbr[pout], pout,
+                                                                            s, sub, one, acc, load);
                 dbl2 *t = a.tmp + (size_t)j * 3 * Vh;
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
@@ -530,7 +534,7 @@ __global__ void __launch_bounds__(256) k_cg_step1(CgArgs a, int ver)
 
 // ---- K2 -----------------------------------------------------------------------------
 
-template <class P, int LPS, int R>
+template <class P, int LPS, int R, int ROWS>
 __global__ void __launch_bounds__(256) k_cg_step2(CgArgs a, int ver)
 {
     using real = typename P::real;
@@ -610,8 +614,8 @@ __global__ void __launch_bounds__(256) k_cg_step2(CgArgs a, int ver)
             auto load = [&](int r, int n, cplx<real> *chi) {
                 P::load_spinor(spin_at<P>(a.ap, js[r], Vh), Vh, n, chi);
             };
-            hop_accumulate<P, LPS, R>(a.g, (const typename P::link_t *)a.links[par], a.nbr[par], par, s, sub, cg,
-                                      acc, load);
+            hop_accumulate<P, LPS, R, decltype(load), false, ROWS>(a.g, (const typename P::link_t *)a.links[par],
+                                                                   a.nbr[par], par, s, sub, cg, acc, load);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 if (!cg[r])
@@ -664,8 +668,8 @@ __global__ void __launch_bounds__(256) k_cg_step2(CgArgs a, int ver)
                 const bool one[1] = {true};
                 cplx<double> acc[1][3] = {{czero<double>(), czero<double>(), czero<double>()}};
                 auto load = [&](int, int n, cplx<double> *chi) { PrecF64::load_spinor(t, Vh, n, chi); };
-                hop_accumulate<PrecF64, LPS, 1, decltype(load), true>(a.g, a.links64[par], a.nbr[par], par, s, sub,
-                                                                      one, acc, load);
+                hop_accumulate<PrecF64, LPS, 1, decltype(load), true, ROWS>(a.g, a.links64[par], a.nbr[par], par, s,
+                                                                            sub, one, acc, load);
                 const double m2d = uniform(sst[r].mass2);
                 dbl2 *x = a.xhi[j];
                 const dbl2 *b = a.b[j];
@@ -753,7 +757,7 @@ __global__ void __launch_bounds__(256) k_cg_init(CgArgs a, int lps)
 // ---- tuning probe: out_r = D in_r for R systems, no reductions -------------------
 // blockIdx.y = tile; tiles alternate output parity like the CG kernels' tiles.
 
-template <class P, int LPS, int R>
+template <class P, int LPS, int R, int ROWS>
 __global__ void __launch_bounds__(256) k_hop_probe(Geom g, const void *links, const int32_t *nbr, const void *in,
                                                     void *out, int remap)
 {
@@ -778,8 +782,9 @@ __global__ void __launch_bounds__(256) k_hop_probe(Geom g, const void *links, co
         for (int c = 0; c < 3; ++c)
             acc[r][c] = czero<real>();
     auto load = [&](int r, int n, cplx<real> *chi) { P::load_spinor(inb + r * vb, Vh, n, chi); };
-    const typename P::link_t *lk = (const typename P::link_t *)links + (size_t)pout * 72 * Vh;
-    hop_accumulate<P, LPS, R>(g, lk, nbr ? nbr + (size_t)pout * 8 * Vh : nullptr, pout, s, sub, act, acc, load);
+    const typename P::link_t *lk = (const typename P::link_t *)links + link_parity_entries(ROWS, Vh) * pout;
+    hop_accumulate<P, LPS, R, decltype(load), false, ROWS>(g, lk, nbr ? nbr + (size_t)pout * 8 * Vh : nullptr, pout, s,
+                                                           sub, act, acc, load);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         void *o = outb + r * vb;

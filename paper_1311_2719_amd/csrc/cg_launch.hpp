@@ -1,6 +1,7 @@
-// Launch tables for the CG / hop kernels of one working precision.  Each
-// precision's kernels are instantiated in their own translation unit
-// (cg_f64.hip, cg_f32.hip, cg_f16.hip) and reached through cg_table(prec).
+// Launch tables for the CG / hop kernels of one working precision and link
+// format.  Each (precision, link rows) pair is instantiated in its own
+// translation unit (cg_f64.hip, cg_f64_r2.hip, ...) and reached through
+// cg_table(prec, rows).
 #pragma once
 
 #include "cg_kernels.hpp"
@@ -20,33 +21,33 @@ struct CgLaunchTable {
     int n_rtiles;
 };
 
-const CgLaunchTable &cg_table(int prec);
+const CgLaunchTable &cg_table(int prec, int rows);
 
-// The table entries for one precision, generated from the kernel templates.
-#define STAG_LPS_SWITCH(KERNEL, P, R, ...)                                                     \
-    switch (lps) {                                                                          \
-    case 1: hipLaunchKernelGGL((KERNEL<P, 1, R>), grid, block, 0, s, __VA_ARGS__); break;   \
-    case 2: hipLaunchKernelGGL((KERNEL<P, 2, R>), grid, block, 0, s, __VA_ARGS__); break;   \
-    case 4: hipLaunchKernelGGL((KERNEL<P, 4, R>), grid, block, 0, s, __VA_ARGS__); break;   \
-    case 8: hipLaunchKernelGGL((KERNEL<P, 8, R>), grid, block, 0, s, __VA_ARGS__); break;   \
-    default: return hipErrorInvalidValue;                                                   \
+// One kernel of the table for every lanes-per-site value.
+#define STAG_LPS_SWITCH(KERNEL, P, R, ROWS, ...)                                                    \
+    switch (lps) {                                                                                 \
+    case 1: hipLaunchKernelGGL((KERNEL<P, 1, R, ROWS>), grid, block, 0, s, __VA_ARGS__); break;    \
+    case 2: hipLaunchKernelGGL((KERNEL<P, 2, R, ROWS>), grid, block, 0, s, __VA_ARGS__); break;    \
+    case 4: hipLaunchKernelGGL((KERNEL<P, 4, R, ROWS>), grid, block, 0, s, __VA_ARGS__); break;    \
+    case 8: hipLaunchKernelGGL((KERNEL<P, 8, R, ROWS>), grid, block, 0, s, __VA_ARGS__); break;    \
+    default: return hipErrorInvalidValue;                                                          \
     }
 
-template <class P, int R> struct RLaunch {
+template <class P, int R, int ROWS> struct RLaunch {
     static hipError_t step1(int lps, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a, int ver)
     {
-        STAG_LPS_SWITCH(k_cg_step1, P, R, a, ver);
+        STAG_LPS_SWITCH(k_cg_step1, P, R, ROWS, a, ver);
         return hipGetLastError();
     }
     static hipError_t step2(int lps, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a, int ver)
     {
-        STAG_LPS_SWITCH(k_cg_step2, P, R, a, ver);
+        STAG_LPS_SWITCH(k_cg_step2, P, R, ROWS, a, ver);
         return hipGetLastError();
     }
     static hipError_t probe(int lps, dim3 grid, dim3 block, hipStream_t s, const Geom &g, const void *links,
                             const int32_t *nbr, const void *in, void *out, int remap)
     {
-        STAG_LPS_SWITCH(k_hop_probe, P, R, g, links, nbr, in, out, remap);
+        STAG_LPS_SWITCH(k_hop_probe, P, R, ROWS, g, links, nbr, in, out, remap);
         return hipGetLastError();
     }
 };
@@ -56,6 +57,39 @@ template <class P> struct PLaunch {
     {
         hipLaunchKernelGGL((k_cg_init<P>), grid, block, 0, s, a, lps);
         return hipGetLastError();
+    }
+};
+
+// The table of precision P, link rows ROWS and right-hand-side tiles Rs...:
+// a tile size not in Rs is rejected with hipErrorInvalidValue.
+template <class P, int ROWS, int... Rs> struct TileTable {
+    static constexpr int tiles[] = {Rs...};
+
+    static hipError_t step1(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a, int ver)
+    {
+        hipError_t e = hipErrorInvalidValue;
+        (void)((R == Rs && ((e = RLaunch<P, Rs, ROWS>::step1(lps, grid, block, s, a, ver)), true)) || ...);
+        return e;
+    }
+    static hipError_t step2(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const CgArgs &a, int ver)
+    {
+        hipError_t e = hipErrorInvalidValue;
+        (void)((R == Rs && ((e = RLaunch<P, Rs, ROWS>::step2(lps, grid, block, s, a, ver)), true)) || ...);
+        return e;
+    }
+    static hipError_t probe(int lps, int R, dim3 grid, dim3 block, hipStream_t s, const Geom &g, const void *links,
+                            const int32_t *nbr, const void *in, void *out, int remap)
+    {
+        hipError_t e = hipErrorInvalidValue;
+        (void)((R == Rs && ((e = RLaunch<P, Rs, ROWS>::probe(lps, grid, block, s, g, links, nbr, in, out, remap)),
+                            true)) ||
+               ...);
+        return e;
+    }
+    static const CgLaunchTable &table()
+    {
+        static const CgLaunchTable t = {step1, step2, PLaunch<P>::init, probe, tiles, (int)sizeof...(Rs)};
+        return t;
     }
 };
 

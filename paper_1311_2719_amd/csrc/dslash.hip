@@ -16,9 +16,14 @@ namespace stag {
 const CgLaunchTable &cg_table_f64();
 const CgLaunchTable &cg_table_f32();
 const CgLaunchTable &cg_table_f16();
+const CgLaunchTable &cg_table_f64_r2();
+const CgLaunchTable &cg_table_f32_r2();
+const CgLaunchTable &cg_table_f16_r2();
 
-const CgLaunchTable &cg_table(int prec)
+const CgLaunchTable &cg_table(int prec, int rows)
 {
+    if (rows == 2)
+        return prec == 0 ? cg_table_f64_r2() : prec == 1 ? cg_table_f32_r2() : cg_table_f16_r2();
     return prec == 0 ? cg_table_f64() : prec == 1 ? cg_table_f32() : cg_table_f16();
 }
 
@@ -26,7 +31,7 @@ namespace {
 
 // out(x) (+)= (D in)(x) for checkerboard sites [offset, offset + count) of the
 // output parity (blockIdx.y selects the parity when par_fixed < 0).
-template <int LPS>
+template <int LPS, int ROWS>
 __global__ void __launch_bounds__(256)
 k_dslash64(Geom g, const dbl2 *__restrict__ links, const int32_t *__restrict__ nbr, const dbl2 *__restrict__ in,
            dbl2 *__restrict__ out, int par_fixed, int offset, int count, int accumulate, int remap)
@@ -42,8 +47,9 @@ k_dslash64(Geom g, const dbl2 *__restrict__ links, const int32_t *__restrict__ n
     const bool act[1] = {true};
     cplx<double> acc[1][3] = {{czero<double>(), czero<double>(), czero<double>()}};
     auto load = [&](int, int n, cplx<double> *chi) { PrecF64::load_spinor(src, Vh, n, chi); };
-    hop_accumulate<PrecF64, LPS, 1>(g, links + (size_t)p * 72 * Vh, nbr ? nbr + (size_t)p * 8 * Vh : nullptr, p, s,
-                                    sub, act, acc, load);
+    hop_accumulate<PrecF64, LPS, 1, decltype(load), false, ROWS>(g, links + link_parity_entries(ROWS, Vh) * p,
+                                                                 nbr ? nbr + (size_t)p * 8 * Vh : nullptr, p, s, sub,
+                                                                 act, acc, load);
     dbl2 *o = out + (size_t)p * 3 * Vh;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -66,25 +72,22 @@ static hipError_t launch_dslash64(const KernelCfg &cfg, const GaugeField *f, int
     dim3 block(cfg.block);
     const dbl2 *lk = (const dbl2 *)f->links[0];
     const int32_t *nb = cfg.tables ? f->nbr : nullptr;
-    switch (cfg.lps) {
-    case 1:
-        hipLaunchKernelGGL((k_dslash64<1>), grid, block, 0, s, f->g, lk, nb, (const dbl2 *)in, (dbl2 *)out, par_fixed,
-                           offset, count, accumulate, cfg.remap);
-        break;
-    case 2:
-        hipLaunchKernelGGL((k_dslash64<2>), grid, block, 0, s, f->g, lk, nb, (const dbl2 *)in, (dbl2 *)out, par_fixed,
-                           offset, count, accumulate, cfg.remap);
-        break;
-    case 4:
-        hipLaunchKernelGGL((k_dslash64<4>), grid, block, 0, s, f->g, lk, nb, (const dbl2 *)in, (dbl2 *)out, par_fixed,
-                           offset, count, accumulate, cfg.remap);
-        break;
-    case 8:
-        hipLaunchKernelGGL((k_dslash64<8>), grid, block, 0, s, f->g, lk, nb, (const dbl2 *)in, (dbl2 *)out, par_fixed,
-                           offset, count, accumulate, cfg.remap);
-        break;
+#define STAG_DSLASH_CASE(L, ROWS)                                                                                    \
+    hipLaunchKernelGGL((k_dslash64<L, ROWS>), grid, block, 0, s, f->g, lk, nb, (const dbl2 *)in, (dbl2 *)out,      \
+                       par_fixed, offset, count, accumulate, cfg.remap)
+    const int key = cfg.lps * 4 + f->rows;
+    switch (key) {
+    case 1 * 4 + 3: STAG_DSLASH_CASE(1, 3); break;
+    case 2 * 4 + 3: STAG_DSLASH_CASE(2, 3); break;
+    case 4 * 4 + 3: STAG_DSLASH_CASE(4, 3); break;
+    case 8 * 4 + 3: STAG_DSLASH_CASE(8, 3); break;
+    case 1 * 4 + 2: STAG_DSLASH_CASE(1, 2); break;
+    case 2 * 4 + 2: STAG_DSLASH_CASE(2, 2); break;
+    case 4 * 4 + 2: STAG_DSLASH_CASE(4, 2); break;
+    case 8 * 4 + 2: STAG_DSLASH_CASE(8, 2); break;
     default: return hipErrorInvalidValue;
     }
+#undef STAG_DSLASH_CASE
     return hipGetLastError();
 }
 
@@ -141,7 +144,7 @@ KernelCfg tune_config(Ctx *ctx, GaugeField *f, int prec, int nrhs, hipStream_t s
         if (it != f->tuned.end())
             return it->second;
     }
-    const CgLaunchTable &tab = cg_table(prec);
+    const CgLaunchTable &tab = cg_table(prec, f->rows);
     KernelCfg best;
     best.lps = prec == 0 ? 2 : 1;
     best.block = 256;

@@ -49,15 +49,17 @@ template <int LPS, typename T> __device__ __forceinline__ T lane_sum(T v)
 // input colour vector of right-hand side r at neighbour site n.  LEAN keeps
 // the direction loop rolled (one direction's loads in flight at a time), for
 // rarely taken paths that must not raise the register budget of the kernel
-// they live in.
-template <class P, int LPS, int R, class Load, bool LEAN = false>
+// they live in.  ROWS = 3: all 9 link entries are stored; ROWS = 2: rows 0
+// and 1 are stored and row 2 is rebuilt in registers.
+template <class P, int LPS, int R, class Load, bool LEAN = false, int ROWS = 3>
 __device__ __forceinline__ void hop_accumulate(const Geom &g, const typename P::link_t *__restrict__ links,
                                                const int32_t *__restrict__ nbr, int p_out, int s, int sub,
                                                const bool *act, cplx<typename P::real> (*acc)[3], Load load)
 {
     using real = typename P::real;
+    static_assert(ROWS == 2 || ROWS == 3, "links are stored with 2 or 3 rows");
     SiteCoord c;
-    if (!nbr)
+    if (!nbr || ROWS == 2)
         c = decode_site(g, p_out, s);
     auto one_direction = [&](int j) {
         const int d = sub + j * LPS;
@@ -65,8 +67,10 @@ __device__ __forceinline__ void hop_accumulate(const Geom &g, const typename P::
         cplx<real> U[9];
         const typename P::link_t *lp = links + link_offset(g.Vh, d, 0, s);
 #pragma unroll
-        for (int k = 0; k < 9; ++k)
+        for (int k = 0; k < 3 * ROWS; ++k)
             U[k] = P::load_link(lp + (int64_t)k * 8 * g.Vh);
+        if constexpr (ROWS == 2)
+            third_row(U, folded_negative(g, c, d) ? real(-2) : real(2));
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (!act[r])
@@ -115,7 +119,8 @@ template <int CTRL> __device__ __forceinline__ double dpp_move(double v)
 __device__ __forceinline__ double read_lane(double v, int lane)
 {
     const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, lane), hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), lane);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), lane);
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 

@@ -71,7 +71,8 @@ struct GaugeField {
     int32_t dims[4] = {0, 0, 0, 0};
     int32_t tap = 1;
     Geom g{};
-    void *links[3] = {nullptr, nullptr, nullptr};  // per precision id: [2][8][9][Vh]
+    int32_t rows = 3;                                // link rows stored (2: third row rebuilt)
+    void *links[3] = {nullptr, nullptr, nullptr};  // per precision id: [2 parities][3 * rows][Vh / 8][8][8]
     int32_t *nbr = nullptr;                          // [2][8][Vh]
     std::atomic<int> users{0};                       // serving requests queued / running
     std::map<uint64_t, KernelCfg> tuned;             // key: (prec, nrhs)
@@ -79,7 +80,7 @@ struct GaugeField {
 
     const void *links_for(int prec, int out_parity) const
     {
-        size_t per_parity = (size_t)8 * 9 * g.Vh * link_entry_bytes_of(prec);
+        const size_t per_parity = (size_t)link_parity_entries(rows, g.Vh) * link_entry_bytes_of(prec);
         return (const char *)links[prec] + (size_t)out_parity * per_parity;
     }
     const int32_t *nbr_for(int out_parity) const { return nbr + (size_t)out_parity * 8 * g.Vh; }
@@ -127,7 +128,16 @@ struct DeviceGuard {
 
 // ---- functions implemented in the .hip files -------------------------------
 
-int gauge_prepare(Ctx *ctx, GaugeField *f, const double *links_dev, hipStream_t s);
+// Largest deviation (absolute, on entries of magnitude <= 1/2) between the
+// given third row of a folded link and the row rebuilt from the other two for
+// which a field is stored in two-row form; it bounds the change of D to about
+// twice this, relative.
+constexpr double kTwoRowTolerance = 1e-14;
+// Check the lexicographic links on the device: ENONFINITE for NaN/Inf;
+// two_rows = whether every folded link admits the two-row form.
+int gauge_check(Ctx *ctx, const Geom &g, const double *links_dev, hipStream_t s, bool &two_rows);
+// Fill f->links (f->rows rows, every precision) and f->nbr from the links.
+int gauge_prepare(GaugeField *f, const double *links_dev, hipStream_t s);
 int launch_pack(const Geom &g, const double *lex, double *eo, int to_eo, hipStream_t s);
 int dslash_f64(Ctx *ctx, GaugeField *f, int out_parity, int64_t offset, int64_t count,
                const double *in, double *out, int accumulate, hipStream_t s);

@@ -13,6 +13,10 @@
 //           signs.  With these, (D chi)(x) = sum_d L_d(x) chi(n_d(x)),
 //           n_d = x+mu (d < 4) or x-mu (d >= 4).  Vh is a multiple of 8
 //           because every extent is even.
+//           Two-row form (fields whose links are special unitary): only
+//           entries 0..5 (rows 0 and 1) are stored.  Every stored matrix is
+//           c V with V in SU(3) and c = +-1/2, so row 2 = conj(row0 x row1) / c,
+//           with the sign of c recomputed from the site's coordinates.
 //   spinors FP64 / FP32: [colour 3][Vh] of complex; FP16: one 16-byte record
 //           per site (3 half2 colours scaled by 1/norm, and the FP32 norm =
 //           largest |component| of the site).
@@ -43,6 +47,7 @@ struct Geom {
     int32_t sy;   // checkerboard stride of one step in y: Lxh
     int32_t sz;   // ... in z: Lxh * Ly
     int32_t st;   // ... in t: Lxh * Ly * Lz
+    int32_t tap;  // 1: antiperiodic in t (the sign is folded into the links)
 };
 
 inline Geom make_geom(const int32_t d[4])
@@ -55,7 +60,14 @@ inline Geom make_geom(const int32_t d[4])
     g.sy = g.Lxh;
     g.sz = g.Lxh * d[1];
     g.st = g.Lxh * d[1] * d[2];
+    g.tap = 0;
     return g;
+}
+
+// Link entries per output parity: 8 directions x (3 x rows) complex per site.
+__host__ __device__ __forceinline__ int64_t link_parity_entries(int rows, int Vh)
+{
+    return (int64_t)24 * rows * Vh;
 }
 
 // Offset of link entry k of direction d at checkerboard site s, within one parity.
@@ -82,6 +94,22 @@ __device__ __forceinline__ SiteCoord decode_site(const Geom &g, int p, int s)
     c.x = 2 * xh + ((p + c.y + c.z + c.t) & 1);
     c.base = s - xh;
     return c;
+}
+
+// True when the real factor folded into link d of the site with coordinates
+// c is negative: eta_mu(x), the minus of a backward link and the sign of a hop
+// across the t boundary of an antiperiodic field (the rule the gauge
+// preparation applies).
+__device__ __forceinline__ bool folded_negative(const Geom &g, const SiteCoord &c, int d)
+{
+    const int mu = d & 3;
+    const int esum = (mu > 0 ? c.x : 0) + (mu > 1 ? c.y : 0) + (mu > 2 ? c.z : 0);
+    bool neg = (esum & 1) != 0;
+    if (d >= 4)
+        neg = !neg;
+    if (g.tap && mu == 3 && (d >= 4 ? c.t == 0 : c.t == g.L[3] - 1))
+        neg = !neg;
+    return neg;
 }
 
 // Checkerboard index (in the other parity) of neighbour d of site s:
@@ -119,6 +147,23 @@ __device__ __forceinline__ void cmac(cplx<T> &acc, const cplx<T> &a, const cplx<
     acc.re = fma(-a.im, b.im, acc.re);
     acc.im = fma(a.re, b.im, acc.im);
     acc.im = fma(a.im, b.re, acc.im);
+}
+
+// Row 2 of W = c V (V special unitary, c real) from rows 0 and 1 (entries
+// U[0..5], row-major): W_2 = conj(W_0 x W_1) / c; inv_c = 1 / c.
+template <typename T> __device__ __forceinline__ void third_row(cplx<T> (&U)[9], T inv_c)
+{
+    // z = a_i b_j - a_j b_i for rows a = U[0..2], b = U[3..5]
+    auto cross = [&](int i, int j) {
+        cplx<T> z;
+        z.re = U[i].re * U[3 + j].re - U[i].im * U[3 + j].im - (U[j].re * U[3 + i].re - U[j].im * U[3 + i].im);
+        z.im = U[i].re * U[3 + j].im + U[i].im * U[3 + j].re - (U[j].re * U[3 + i].im + U[j].im * U[3 + i].re);
+        return z;
+    };
+    const cplx<T> z0 = cross(1, 2), z1 = cross(2, 0), z2 = cross(0, 1);
+    U[6] = {z0.re * inv_c, -z0.im * inv_c};
+    U[7] = {z1.re * inv_c, -z1.im * inv_c};
+    U[8] = {z2.re * inv_c, -z2.im * inv_c};
 }
 
 // ---- precision traits --------------------------------------------------------

@@ -112,18 +112,33 @@ def test_serving_alone_equals_in_the_mix(gpu_ctx):
 
 
 def test_serving_admission_by_memory():
-    # Two 8^4 fields (8 MiB each with all precisions and tables) in an arena
-    # with 1.5 MiB to spare: the first field's two-slot FP32 batch (about
-    # 1.2 MB) fits, the second field's does not, so its requests wait until
-    # the first batch drains and its workspace is released, then run.
+    # Two 8^4 fields in an arena with room for both plus 1.25 workspaces of a
+    # two-slot FP32 batch: the first field's batch fits, the second field's
+    # does not (nor does a one-slot batch, about half a workspace), so its
+    # requests wait until the first batch drains and its workspace is
+    # released, then run.  Sizes are measured, not assumed.
     dims = (8, 8, 8, 8)
     U = inputs.smooth_su3(dims, 0.5, 151)
     Ud = torch.from_numpy(U).cuda()
-    with binding.Context(device=0, arena_bytes=(16 << 20) + (3 << 19)) as ctx:
+    with binding.Context(device=0, arena_bytes=256 << 20) as ctx:
+        ctx.serve_config(slots_per_field=2, epoch_iters=8)
+        used0 = ctx.arena_usage()[0]
+        f = ctx.set_gauge(dims, Ud)
+        field_bytes = ctx.arena_usage()[0] - used0
+        b = ctx.pack(f, inputs.gaussian_source(dims, 159))
+        x = ctx.new_fermion(f)
+        torch.cuda.synchronize()
+        used1 = ctx.arena_usage()[0]
+        info = ctx.wait(ctx.submit(f, b, x, mass=0.05, precision=binding.FP32_RU))
+        assert info["status"] == 0
+        ws_bytes = ctx.arena_usage()[0] - used1  # the lane's cached workspace
+    assert field_bytes > 0 and ws_bytes > 0
+    with binding.Context(device=0, arena_bytes=2 * field_bytes + ws_bytes + ws_bytes // 4) as ctx:
         ctx.serve_config(slots_per_field=2, epoch_iters=8)
         f1 = ctx.set_gauge(dims, Ud)
         f2 = ctx.set_gauge(dims, Ud)
         srcs = [inputs.gaussian_source(dims, 160 + i) for i in range(4)]
+        # sources and solutions live outside the arena (torch tensors)
         bs = [ctx.pack(f1, s) for s in srcs]
         xs = [ctx.new_fermion(f1) for _ in srcs]
         torch.cuda.synchronize()
@@ -139,7 +154,7 @@ def test_serving_admission_by_memory():
         first_done = max(infos[0]["seconds"], infos[1]["seconds"])
         assert min(infos[2]["queue_seconds"], infos[3]["queue_seconds"]) >= first_done - 5e-3
     # an arena with room for the field but for no workspace: ENOMEM
-    with binding.Context(device=0, arena_bytes=(8 << 20) + (320 << 10)) as ctx:
+    with binding.Context(device=0, arena_bytes=field_bytes + ws_bytes // 4) as ctx:
         f = ctx.set_gauge(dims, Ud)
         b = ctx.pack(f, inputs.gaussian_source(dims, 170))
         x = ctx.new_fermion(f)

@@ -75,6 +75,37 @@ def test_single_parity_and_second_half(gpu_ctx, par):
         gpu_ctx.free_gauge(f)
 
 
+@pytest.mark.parametrize("case", ["three_rows_forced", "not_special_unitary"])
+def test_fp64_both_link_formats(gpu_ctx, case):
+    # the CG kernels with all three link rows stored: forced on a special
+    # unitary field, and chosen by the library for links that are not
+    # special unitary (Haar x 0.9); both match the oracle, and so does FP32
+    import os
+
+    dims, m, tol = (4, 4, 4, 6), 0.1, 1e-10
+    U = inputs.haar_su3(dims, 141)
+    if case == "not_special_unitary":
+        U = 0.9 * U
+    b = inputs.gaussian_source(dims, 142)
+    if case == "three_rows_forced":
+        os.environ["STAG_LINK_ROWS"] = "3"
+    try:
+        f = gpu_ctx.set_gauge(dims, U)
+    finally:
+        os.environ.pop("STAG_LINK_ROWS", None)
+    try:
+        assert gpu_ctx.link_rows(f) == 3
+        x, _, info = solve(gpu_ctx, f, b, mass=m, tol=tol)
+        xr, _, oi = oracle.cg_solve(dims, U, m, b, tol=tol)
+        assert info["status"] == 0 and abs(info["iters"] - oi["iters"]) <= 1
+        assert rel(x, xr) <= 1e-10
+        x32, _, i32 = solve(gpu_ctx, f, b, mass=m, tol=tol, precision=binding.FP32_RU)
+        assert i32["status"] == 0
+        assert oracle.true_residual(dims, U, m, b, x32) <= tol
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
 def test_free_field_closed_form(gpu_ctx):
     dims, m = (8, 8, 8, 8), 0.05
     b = inputs.gaussian_source(dims, 81)

@@ -100,22 +100,76 @@ def test_site_range_and_accumulate(gpu_ctx, par):
         gpu_ctx.free_gauge(f)
 
 
+@pytest.mark.parametrize("rows", [2, 3])
 @pytest.mark.parametrize("cfg", ["1,64,1,0,0", "2,128,1,1,1", "4,256,1,0,1", "8,64,1,1,0", "8,256,1,0,1"])
-def test_every_kernel_shape(cfg):
+def test_every_kernel_shape(cfg, rows):
     # the tuner may pick any lanes-per-site / block / table / XCD-order
-    # combination: each must give the same operator
+    # combination, for either link format: each must give the same operator
     dims = (6, 4, 4, 10)
     U = inputs.haar_su3(dims, 41)
     chi = inputs.gaussian_source(dims, 42)
     ref = oracle.dslash(dims, U, chi)
     os.environ["STAG_KERNEL_CFG"] = cfg
+    if rows == 3:
+        os.environ["STAG_LINK_ROWS"] = "3"
     try:
         with binding.Context(device=0, arena_bytes=64 << 20) as ctx:
             f = ctx.set_gauge(dims, U)
+            assert ctx.link_rows(f) == rows
             assert ctx.tune_info(f)["lanes_per_site"] == int(cfg.split(",")[0])
             assert site_err(apply(ctx, f, chi), ref) <= TOL
     finally:
         del os.environ["STAG_KERNEL_CFG"]
+        os.environ.pop("STAG_LINK_ROWS", None)
+
+
+def not_special_unitary(dims, seed):
+    """Links that are not special unitary: Haar links scaled by 0.9 (so
+    row 2 != conj(row 0 x row 1)), which still make D anti-Hermitian."""
+    return 0.9 * inputs.haar_su3(dims, seed)
+
+
+def test_link_format_selection(gpu_ctx):
+    # special unitary fields are stored with two rows; anything else (also a
+    # single link perturbed by 1e-10) keeps all three, and D is exact either way
+    dims = (4, 4, 4, 6)
+    chi = inputs.gaussian_source(dims, 72)
+    cases = [("haar", inputs.haar_su3(dims, 71), 2), ("smooth", inputs.smooth_su3(dims, 0.5, 73), 2),
+             ("unit", inputs.unit_links(dims), 2), ("scaled", not_special_unitary(dims, 74), 3)]
+    nudged = inputs.haar_su3(dims, 75)
+    nudged[123, 2, 1, 0] += 1e-10
+    cases.append(("nudged", nudged, 3))
+    for name, U, rows in cases:
+        f = gpu_ctx.set_gauge(dims, U)
+        try:
+            assert gpu_ctx.link_rows(f) == rows, name
+            assert site_err(apply(gpu_ctx, f, chi), oracle.dslash(dims, U, chi)) <= TOL, name
+        finally:
+            gpu_ctx.free_gauge(f)
+
+
+@pytest.mark.parametrize("tap", [True, False])
+def test_three_rows_forced_equals_two_rows(gpu_ctx, tap):
+    # the same special unitary field stored both ways gives the same operator
+    # (to rounding), with either t boundary condition
+    dims = (4, 6, 4, 8)
+    U = inputs.haar_su3(dims, 81)
+    chi = inputs.gaussian_source(dims, 82)
+    ref = oracle.dslash(dims, U, chi, antiperiodic_t=tap)
+    f2 = gpu_ctx.set_gauge(dims, U, antiperiodic_t=tap)
+    os.environ["STAG_LINK_ROWS"] = "3"
+    try:
+        f3 = gpu_ctx.set_gauge(dims, U, antiperiodic_t=tap)
+    finally:
+        del os.environ["STAG_LINK_ROWS"]
+    try:
+        assert gpu_ctx.link_rows(f2) == 2 and gpu_ctx.link_rows(f3) == 3
+        g2, g3 = apply(gpu_ctx, f2, chi), apply(gpu_ctx, f3, chi)
+        assert site_err(g2, ref) <= TOL and site_err(g3, ref) <= TOL
+        assert site_err(g2, g3) <= TOL
+    finally:
+        gpu_ctx.free_gauge(f2)
+        gpu_ctx.free_gauge(f3)
 
 
 def test_anti_hermitian_on_gpu(gpu_ctx):
@@ -201,8 +255,11 @@ def test_links_from_device_and_arena_accounting(gpu_ctx):
     used0, total = gpu_ctx.arena_usage()
     f = gpu_ctx.set_gauge(dims, torch.from_numpy(U).cuda())
     used1, _ = gpu_ctx.arena_usage()
-    # FP64 + FP32 + FP16 links with back-links (1152 + 576 + 288 B/site) + tables (32 B/site)
-    assert used1 - used0 >= 2048 * int(np.prod(dims))
+    # FP64 + FP32 + FP16 links with back-links (1152 + 576 + 288 B/site with
+    # three rows, 2/3 of that with two) + tables (32 B/site)
+    rows = gpu_ctx.link_rows(f)
+    assert rows == 2
+    assert used1 - used0 >= (2016 * rows // 3 + 32) * int(np.prod(dims))
     assert site_err(apply(gpu_ctx, f, chi), oracle.dslash(dims, U, chi)) <= TOL
     gpu_ctx.free_gauge(f)
     assert gpu_ctx.arena_usage()[0] == used0
