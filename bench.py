@@ -78,7 +78,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--suite", default="default", choices=["default", "mixed32", "batch24", "serve", "copy"])
+    ap.add_argument("--suite", default="default",
+                    choices=["default", "mixed32", "batch24", "serve", "copy", "cpu_baseline"])
+    ap.add_argument("--oracle-threads-one", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--dslash-reps", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
@@ -481,7 +483,73 @@ def run_serve(args):
            "fields": [list(d) for d, _ in specs], "points": points})
 
 
-SUITES = {"mixed32": run_mixed32, "batch24": run_batch24, "serve": run_serve}
+def _host_cpu():
+    import subprocess
+
+    info = {"nproc": os.cpu_count()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)"):
+                info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+def run_cpu_baseline(args):
+    """The CPU oracle timed on the host cores (the baseline beside the GPU
+    numbers, never a target): FP64 D_slash GB/s (1248 B per site, the
+    oracle stores full links) and FP64 CG solves/s on the four workloads --
+    4^4 Haar, 16^4 eps 0.3, 32^4 eps 0.5, 24^4 eps 0.5 (one of its twelve
+    sources, the lightest mass) -- with all OpenMP threads, and the 4^4 and
+    16^4 ones again with one thread (a child process); plus a STREAM-style
+    triad as the host's own bandwidth roofline.  No GPU is used."""
+    import subprocess
+
+    import oracle
+    from paper_1311_2719_amd import inputs
+
+    if args.oracle_threads_one:
+        os.environ["OMP_NUM_THREADS"] = "1"
+    work = [("4^4 Haar m=0.1", (4, 4, 4, 4), lambda d: inputs.haar_su3(d, 101), 201, 0.1),
+            ("16^4 eps=0.3 m=0.05", (16, 16, 16, 16), lambda d: inputs.smooth_su3(d, 0.3, 102), 202, 0.05)]
+    if not args.oracle_threads_one:
+        work += [("32^4 eps=0.5 m=0.01", (32, 32, 32, 32), lambda d: inputs.smooth_su3(d, 0.5, 103), 203, 0.01),
+                 ("24^4 eps=0.5 m=0.01 (source 2040)", (24, 24, 24, 24), lambda d: inputs.smooth_su3(d, 0.5, 104),
+                  2040, 0.01)]
+    results = []
+    for name, dims, links, seed, m in work:
+        print("bench cpu_baseline: %s" % name, file=sys.stderr, flush=True)
+        U = links(dims)
+        b = inputs.gaussian_source(dims, seed)
+        V = int(np.prod(dims))
+        oracle.dslash(dims, U, b)
+        reps, t0 = 0, time.perf_counter()
+        while reps < 3 or (time.perf_counter() - t0 < 1.0 and reps < 50):
+            oracle.dslash(dims, U, b)
+            reps += 1
+        td = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        _, _, info = oracle.cg_solve(dims, U, m, b, tol=1e-10)
+        tc = time.perf_counter() - t0
+        results.append({"workload": name, "dslash_us": td * 1e6, "dslash_gbs": 1248 * V / td / 1e9,
+                        "cg_seconds": tc, "cg_solves_per_s": 1.0 / tc, "cg_iters": info["iters"],
+                        "true_rel_resid": info["true_rel"]})
+        del U, b
+    line = {"suite": "cpu_baseline", "kind": "oracle", "threads": oracle.max_threads(),
+            "triad_gbs": oracle.stream_triad(1 << 26) / 1e9, "host": _host_cpu(), "results": results}
+    if not args.oracle_threads_one:
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--suite", "cpu_baseline",
+                            "--oracle-threads-one"], capture_output=True, text=True,
+                           env=dict(os.environ, OMP_NUM_THREADS="1"))
+        one = [json.loads(x) for x in r.stdout.splitlines() if x.startswith("{")]
+        line["one_thread"] = one[0] if one else {"error": r.stderr[-500:]}
+    print(json.dumps(line), flush=True)
+
+
+SUITES = {"mixed32": run_mixed32, "batch24": run_batch24, "serve": run_serve, "cpu_baseline": run_cpu_baseline}
 
 
 def main():

@@ -41,6 +41,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -566,4 +567,31 @@ int orc_max_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ---- host bandwidth reference (no part of the method) ------------------ */
+
+/* STREAM-style triad a = b + s c over n doubles, reps times, with the
+ * OpenMP threads of the oracle; returns the wall seconds of the best rep.
+ * The CPU's own bandwidth roofline for the oracle timings. */
+static double wall_seconds(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+double orc_stream_triad(int64_t n, double *a, const double *b, const double *c, double s, int reps)
+{
+    double best = 1e30;
+    for (int r = 0; r < reps; ++r) {
+        const double t0 = wall_seconds();
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i)
+            a[i] = b[i] + s * c[i];
+        const double t = wall_seconds() - t0;
+        if (t < best)
+            best = t;
+    }
+    return best;
 }

@@ -585,10 +585,17 @@ static int estimate_remaining(const Batch &B, std::vector<ConvergenceTrack> &tra
             const int di = st.iters - t.iters;
             if (di >= 8 && t.rr > st.rr && st.rr > 0)
                 rate = std::max(rate, std::log(t.rr / st.rr) / di);
-            if (rate > 0 && st.stop2 > 0)
-                worst = std::max(worst, std::log(std::max(st.rr / st.stop2, 1.0)) / rate);
-            else
+            if (rate > 0 && st.stop2 > 0) {
+                // CG iterations to the stopping test, plus the residual
+                // recomputations on the way (one per factor 1/delta^2 of <r,r>)
+                const double decades = std::log(std::max(st.rr / st.stop2, 1.0));
+                double steps = decades / rate;
+                if (st.delta2 > 0 && st.delta2 < 1)
+                    steps += decades / -std::log(st.delta2);
+                worst = std::max(worst, steps);
+            } else {
                 known = false;
+            }
         }
         if (!running || st.iters - t.iters >= 8) {
             t.iters = st.iters;
@@ -667,13 +674,21 @@ int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs, con
             // stopping test plus the final FP64 check), less the epoch in
             // flight; the next epoch covers about half of them (an epoch too
             // short costs a look at the state, which overlaps the epoch in
-            // flight; one too long costs idle steps).  The shortest epoch is
+            // flight unless the epochs are very short; one too long costs
+            // idle steps of a few microseconds each).  The shortest epoch is
             // 2 steps; 16 while the rate of convergence is not known yet.
             const int rem = estimate_remaining(B, track);
             const int ahead = rem == kUnknownRemaining ? 32 : rem + 1 - inflight;
             E = 2;
-            while (E * 2 <= std::min(Emax, ahead / 2))
-                E *= 2;
+            if (ahead <= 16) {
+                // the end is near: one epoch for all of it (a few idle steps
+                // cost less than another look at the state)
+                while (E < ahead)
+                    E *= 2;
+            } else {
+                while (E * 2 <= std::min(Emax, ahead / 2))
+                    E *= 2;
+            }
             if (fixed_epoch)
                 E = Emax;
             if (epoch_log)

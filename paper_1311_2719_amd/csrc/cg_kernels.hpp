@@ -334,6 +334,11 @@ __device__ __forceinline__ void advance(SysState &s, const double (&t)[3])
     }
 }
 
+// Directions per iteration of the rolled FP64 hop of a residual
+// recomputation: two keeps the register budget of the single-site CG kernels
+// while overlapping the loads of two directions.
+constexpr int kRecomputeUnroll = 2;
+
 // First site index handled by this thread in grid-stride round `it`.
 __device__ __forceinline__ int64_t round_base(int it, int remap)
 {
@@ -510,8 +515,8 @@ __global__ void __launch_bounds__(256) k_cg_step1(CgArgs a, int ver)
                         chi[c] = {v.x, v.y};
                     }
                 };
-                hop_accumulate<PrecF64, LPS, 1, decltype(load), true, ROWS>(a.g, a.links64[pout], a.nbr[pout], pout,
-                                                                            s, sub, one, acc, load);
+                hop_accumulate<PrecF64, LPS, 1, decltype(load), true, ROWS, kRecomputeUnroll>(
+                    a.g, a.links64[pout], a.nbr[pout], pout, s, sub, one, acc, load);
                 dbl2 *t = a.tmp + (size_t)j * 3 * Vh;
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
@@ -668,8 +673,8 @@ __global__ void __launch_bounds__(256) k_cg_step2(CgArgs a, int ver)
                 const bool one[1] = {true};
                 cplx<double> acc[1][3] = {{czero<double>(), czero<double>(), czero<double>()}};
                 auto load = [&](int, int n, cplx<double> *chi) { PrecF64::load_spinor(t, Vh, n, chi); };
-                hop_accumulate<PrecF64, LPS, 1, decltype(load), true, ROWS>(a.g, a.links64[par], a.nbr[par], par, s,
-                                                                            sub, one, acc, load);
+                hop_accumulate<PrecF64, LPS, 1, decltype(load), true, ROWS, kRecomputeUnroll>(
+                    a.g, a.links64[par], a.nbr[par], par, s, sub, one, acc, load);
                 const double m2d = uniform(sst[r].mass2);
                 dbl2 *x = a.xhi[j];
                 const dbl2 *b = a.b[j];

@@ -47,11 +47,11 @@ template <int LPS, typename T> __device__ __forceinline__ T lane_sum(T v)
 // acc[r][a] += sum over this lane's directions of L_d(s)[a][b] in_r(n_d(s))[b],
 // then summed over the LPS lanes of the site.  load(r, n, chi) fetches the
 // input colour vector of right-hand side r at neighbour site n.  LEAN keeps
-// the direction loop rolled (one direction's loads in flight at a time), for
-// rarely taken paths that must not raise the register budget of the kernel
-// they live in.  ROWS = 3: all 9 link entries are stored; ROWS = 2: rows 0
-// and 1 are stored and row 2 is rebuilt in registers.
-template <class P, int LPS, int R, class Load, bool LEAN = false, int ROWS = 3>
+// the direction loop rolled (LEAN_UNROLL directions' loads in flight at a
+// time), for rarely taken paths that must not raise the register budget of
+// the kernel they live in.  ROWS = 3: all 9 link entries are stored; ROWS = 2:
+// rows 0 and 1 are stored and row 2 is rebuilt in registers.
+template <class P, int LPS, int R, class Load, bool LEAN = false, int ROWS = 3, int LEAN_UNROLL = 1>
 __device__ __forceinline__ void hop_accumulate(const Geom &g, const typename P::link_t *__restrict__ links,
                                                const int32_t *__restrict__ nbr, int p_out, int s, int sub,
                                                const bool *act, cplx<typename P::real> (*acc)[3], Load load)
@@ -85,7 +85,7 @@ __device__ __forceinline__ void hop_accumulate(const Geom &g, const typename P::
         }
     };
     if constexpr (LEAN) {
-#pragma unroll 1
+#pragma unroll LEAN_UNROLL
         for (int j = 0; j < 8 / LPS; ++j)
             one_direction(j);
     } else {
