@@ -24,6 +24,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "stag_oracle.c")
+_SRC_WILSON = os.path.join(_HERE, "wilson_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
@@ -48,10 +49,11 @@ class CGResult(ctypes.Structure):
 
 def build(force: bool = False) -> str:
     """Compile stag_oracle.c with gcc into liboracle.so (OpenMP on)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_WILSON))
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-               "-Wall", "-o", tmp, _SRC, "-lm"]
+               "-Wall", "-o", tmp, _SRC, _SRC_WILSON, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -81,6 +83,16 @@ def _load():
             lib.orc_cg_full.restype = ctypes.c_int
             lib.orc_max_threads.argtypes = []
             lib.orc_max_threads.restype = ctypes.c_int
+            lib.orc_stream_triad.argtypes = [I64, P, P, P, D, ctypes.c_int]
+            lib.orc_stream_triad.restype = D
+            lib.orc_wilson_hop.argtypes = [P, I32, P, P, P, I32]
+            lib.orc_wilson_hop.restype = ctypes.c_int
+            lib.orc_wilson_apply.argtypes = [P, I32, P, D, P, P]
+            lib.orc_wilson_apply.restype = ctypes.c_int
+            lib.orc_wilson_gamma.argtypes = [I32, P]
+            lib.orc_wilson_gamma.restype = ctypes.c_int
+            lib.orc_wilson_cg.argtypes = [P, I32, P, D, D, I32, P, P, P]
+            lib.orc_wilson_cg.restype = ctypes.c_int
             _lib = lib
     return _lib
 
@@ -105,6 +117,19 @@ def _ptr(a):
 
 def max_threads() -> int:
     return int(_load().orc_max_threads())
+
+
+def stream_triad(n_doubles: int, reps: int = 5) -> float:
+    """Host memory bandwidth (bytes/s) of a = b + s*c over n_doubles with the
+    oracle's OpenMP threads (24 bytes per element), best of reps.  A
+    reference for the oracle timings, not part of the method."""
+    lib = _load()
+    a = np.zeros(n_doubles)
+    b = np.ones(n_doubles)
+    c = np.full(n_doubles, 2.0)
+    sec = lib.orc_stream_triad(ctypes.c_int64(n_doubles), _ptr(a), _ptr(b), _ptr(c), ctypes.c_double(3.0),
+                               ctypes.c_int(reps))
+    return 24.0 * n_doubles / sec
 
 
 def dslash(dims, U, chi, out_parity=ALL, antiperiodic_t=True, out=None):
@@ -216,4 +241,72 @@ def cg_full(dims, U, m, b, tol=1e-13, maxiter=100000, max_restarts=20,
                          int(maxiter), int(max_restarts), _ptr(b), _ptr(x), ctypes.byref(res))
     if rc < 0:
         raise ValueError("orc_cg_full rejected its arguments")
+    return x, res.as_dict()
+
+
+# ---- Wilson fermions (textbook readings; see wilson_oracle.c) ---------------------------------
+
+class WilsonResult(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("iters", ctypes.c_int32),
+        ("rr", ctypes.c_double),
+        ("bb", ctypes.c_double),
+        ("true_rel", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def wilson_gamma(mu: int) -> np.ndarray:
+    """gamma_mu (4x4 complex) of the oracle's chiral basis, mu = 0..3 = x, y, z, t."""
+    out = np.zeros((4, 4), np.complex128)
+    if _load().orc_wilson_gamma(mu, _ptr(out)) != 0:
+        raise ValueError("mu must be 0..3")
+    return out
+
+
+def wilson_hop(dims, U, psi, out_parity=ALL, antiperiodic_t=True, out=None):
+    """(H psi)(x) = sum_mu [(1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^dagger psi(x-mu)]
+    on the sites of out_parity (others of `out` untouched; zero when `out` is not given).
+    psi: complex128 [V, 4, 3] (spin, colour)."""
+    L = _dims(dims)
+    V = int(np.prod(dims))
+    U = _c128(U, (V, 4, 3, 3))
+    psi = _c128(psi, (V, 4, 3))
+    if out is None:
+        out = np.zeros((V, 4, 3), np.complex128)
+    rc = _load().orc_wilson_hop(_ptr(L), int(antiperiodic_t), _ptr(U), _ptr(psi), _ptr(out), out_parity)
+    if rc != 0:
+        raise ValueError("orc_wilson_hop failed (%d)" % rc)
+    return out
+
+
+def wilson_apply(dims, U, kappa, psi, antiperiodic_t=True):
+    """M psi = psi - kappa H psi on every site."""
+    L = _dims(dims)
+    V = int(np.prod(dims))
+    U = _c128(U, (V, 4, 3, 3))
+    psi = _c128(psi, (V, 4, 3))
+    out = np.zeros((V, 4, 3), np.complex128)
+    rc = _load().orc_wilson_apply(_ptr(L), int(antiperiodic_t), _ptr(U), float(kappa), _ptr(psi), _ptr(out))
+    if rc != 0:
+        raise ValueError("orc_wilson_apply failed (%d)" % rc)
+    return out
+
+
+def wilson_cg(dims, U, kappa, b, tol=1e-10, maxiter=20000, antiperiodic_t=True):
+    """Solve M x = b by CG on the even-odd normal equations
+    Mhat^dagger Mhat x_e = Mhat^dagger (b_e + kappa D_eo b_o), x_o = b_o + kappa D_oe x_e."""
+    L = _dims(dims)
+    V = int(np.prod(dims))
+    U = _c128(U, (V, 4, 3, 3))
+    b = _c128(b, (V, 4, 3))
+    x = np.zeros((V, 4, 3), np.complex128)
+    res = WilsonResult()
+    rc = _load().orc_wilson_cg(_ptr(L), int(antiperiodic_t), _ptr(U), float(kappa), float(tol), int(maxiter),
+                               _ptr(b), _ptr(x), ctypes.byref(res))
+    if rc != 0:
+        raise ValueError("orc_wilson_cg failed (%d)" % rc)
     return x, res.as_dict()

@@ -104,3 +104,70 @@ def lu_solve(dims, U, m, b, antiperiodic_t=True) -> np.ndarray:
     D = dense_normal(dense_dslash(dims, U, antiperiodic_t), m)
     x = np.linalg.solve(D, np.asarray(b, dtype=np.complex128).reshape(-1))
     return x.reshape(-1, 3)
+
+
+# ---- Wilson fermions -----------------------------------------------------------------------------
+#
+# (H psi)(x) = sum_mu [(1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^dagger psi(x-mu)],
+# M = 1 - kappa H, spinor index 12*site + 3*spin + colour.  The gamma matrices of the chiral basis are
+# typed here a second time, independently of wilson_oracle.c (a test checks the two agree and obey the
+# Clifford algebra).
+
+WILSON_GAMMA = (
+    np.array([[0, 0, 0, 1j], [0, 0, 1j, 0], [0, -1j, 0, 0], [-1j, 0, 0, 0]]),
+    np.array([[0, 0, 0, -1], [0, 0, 1, 0], [0, 1, 0, 0], [-1, 0, 0, 0]], dtype=np.complex128),
+    np.array([[0, 0, 1j, 0], [0, 0, 0, -1j], [-1j, 0, 0, 0], [0, 1j, 0, 0]]),
+    np.array([[0, 0, 1, 0], [0, 0, 0, 1], [1, 0, 0, 0], [0, 1, 0, 0]], dtype=np.complex128),
+)
+
+WILSON_MUTATIONS = (
+    "projector_sign",      # (1 + gamma) on the forward hop and (1 - gamma) on the backward one
+    "no_dagger",           # U instead of U^dagger on the backward hop
+    "periodic_t",          # forget the antiperiodic sign
+    "drop_direction",      # leave out the y hops
+    "gamma_transpose",     # gamma^T instead of gamma
+    "wrong_backward_link", # U_mu(x)^dagger instead of U_mu(x-mu)^dagger
+)
+
+
+def dense_wilson_hop(dims, U, antiperiodic_t=True, mutation=None) -> np.ndarray:
+    """The Wilson hopping term H as a dense (12V x 12V) complex matrix."""
+    if mutation is not None and mutation not in WILSON_MUTATIONS:
+        raise ValueError("unknown mutation %r" % mutation)
+    L = np.asarray(dims, dtype=np.int64)
+    V = int(np.prod(L))
+    U = np.asarray(U).reshape(V, 4, 3, 3)
+    H = np.zeros((12 * V, 12 * V), dtype=np.complex128)
+    one = np.eye(4)
+    for s in range(V):
+        c = _coords(s, L)
+        for mu in range(4):
+            if mutation == "drop_direction" and mu == 1:
+                continue
+            g = WILSON_GAMMA[mu].T if mutation == "gamma_transpose" else WILSON_GAMMA[mu]
+            pf, pb = (one + g, one - g) if mutation == "projector_sign" else (one - g, one + g)
+            cf = c.copy()
+            cf[mu] = (c[mu] + 1) % L[mu]
+            sf = _lex(cf, L)
+            sgn_f = -1.0 if (antiperiodic_t and mutation != "periodic_t" and mu == 3 and c[3] == L[3] - 1) else 1.0
+            H[12 * s:12 * s + 12, 12 * sf:12 * sf + 12] += sgn_f * np.kron(pf, U[s, mu])
+            cb = c.copy()
+            cb[mu] = (c[mu] - 1) % L[mu]
+            sb = _lex(cb, L)
+            sgn_b = -1.0 if (antiperiodic_t and mutation != "periodic_t" and mu == 3 and c[3] == 0) else 1.0
+            if mutation == "wrong_backward_link":
+                Ub = U[s, mu].conj().T
+            elif mutation == "no_dagger":
+                Ub = U[sb, mu]
+            else:
+                Ub = U[sb, mu].conj().T
+            H[12 * s:12 * s + 12, 12 * sb:12 * sb + 12] += sgn_b * np.kron(pb, Ub)
+    return H
+
+
+def wilson_parity_of_rows(dims) -> np.ndarray:
+    """Parity (0 even, 1 odd) of each row/column index of the dense Wilson matrices."""
+    L = np.asarray(dims, dtype=np.int64)
+    V = int(np.prod(L))
+    par = np.array([int(np.sum(_coords(s, L))) & 1 for s in range(V)])
+    return np.repeat(par, 12)
