@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--suite", default="default",
-                    choices=["default", "mixed32", "batch24", "serve", "copy", "cpu_baseline"])
+                    choices=["default", "mixed32", "batch24", "serve", "copy", "cpu_baseline", "wilson"])
     ap.add_argument("--oracle-threads-one", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--dslash-reps", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -483,6 +483,88 @@ def run_serve(args):
            "fields": [list(d) for d, _ in specs], "points": points})
 
 
+def wilson_bytes_per_site(rows: int) -> int:
+    """Wilson hop algorithmic bytes per output site (FP64): 8 links of
+    3 x rows complex entries, one gathered and one written spin-colour vector."""
+    return 8 * 3 * rows * 16 + 192 + 192
+
+
+def run_wilson(args):
+    """Wilson fermions (the paper's second workload): FP64 solves of M x = b,
+    M = 1 - kappa H, by CG on the even-odd normal equations, 16^4 lattice
+    (links proj_SU3(exp(0.3 i H)) seed 102, Gaussian spin-colour source seed
+    202, kappa = 0.12, true residual reported); the hop H timed alone at 16^4
+    and 32^4 (unit links); the oracle's solve of the same system on the host."""
+    import torch
+
+    import oracle
+    from paper_1311_2719_amd import binding, inputs
+
+    dims, kappa, tol = (16, 16, 16, 16), 0.12, 1e-10
+    V = int(np.prod(dims))
+    U = inputs.smooth_su3(dims, 0.3, seed=102)
+    b_lex = inputs.gaussian_spinor(dims, seed=202)
+    ctx = binding.Context(device=0, arena_bytes=8 << 30)
+    f = ctx.set_gauge_wilson(dims, U)
+    b = ctx.pack_spinor(f, b_lex)
+    x = ctx.new_spinor(f)
+    torch.cuda.synchronize()
+    for _ in range(max(1, args.warmup)):
+        ctx.wilson_solve(f, b, x, kappa, tol=tol)
+    torch.cuda.synchronize()
+    steps = max(1, args.steps)
+    t0 = time.perf_counter()
+    infos = [ctx.wilson_solve(f, b, x, kappa, tol=tol) for _ in range(steps)]
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+
+    def hop_mean(field, inp, reps):
+        out = ctx.new_spinor(field)
+        for _ in range(5):
+            ctx.wilson_dslash(field, inp, out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(reps):
+            ctx.wilson_dslash(field, inp, out)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    rows = ctx.link_rows(f)
+    h16 = hop_mean(f, b, 100)
+    dims32 = (32, 32, 32, 32)
+    f32 = ctx.set_gauge_wilson(dims32, inputs.unit_links(dims32))
+    b32 = ctx.pack_spinor(f32, inputs.gaussian_spinor(dims32, seed=203))
+    h32 = hop_mean(f32, b32, 30)
+    V32 = int(np.prod(dims32))
+    rows32 = ctx.link_rows(f32)
+    ctx.free_gauge(f32)
+    del b32
+    cpu = None
+    if not args.no_cpu:
+        t1 = time.perf_counter()
+        _, oi = oracle.wilson_cg(dims, U, kappa, b_lex, tol=tol)
+        tc = time.perf_counter() - t1
+        cpu = {"value": 1.0 / tc, "unit": "solves/s", "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": "1 complete FP64 solve of the same 16x16x16x16 system (oracle iterations %d)" % oi["iters"]}
+    info = infos[-1]
+    ctx.close()
+    _emit({"suite": "wilson", "metric": "Wilson CG solves/s to 1e-10 (FP64, even-odd)",
+           "workload": "Wilson M = 1 - kappa H, 16^4, proj_SU3(exp(0.3iH)) links seed 102, Gaussian spin-colour "
+                       "source seed 202, kappa = 0.12, CG on the even-odd normal equations to 1e-10",
+           "value": steps / secs, "unit": "solves/s", "ms_per_solve": secs / steps * 1e3,
+           "iters": info["iters"], "true_rel_resid": info["true_rel_resid"],
+           "ok": all(i["status"] == 0 for i in infos),
+           "hop_16": {"mean_us": h16 * 1e6, "link_rows": rows, "bytes_per_site": wilson_bytes_per_site(rows),
+                      "gbs": wilson_bytes_per_site(rows) * V / h16 / 1e9,
+                      "frac": wilson_bytes_per_site(rows) * V / h16 / 1e9 / HBM_PEAK_GBS},
+           "hop_32": {"mean_us": h32 * 1e6, "link_rows": rows32,
+                      "gbs": wilson_bytes_per_site(rows32) * V32 / h32 / 1e9,
+                      "frac": wilson_bytes_per_site(rows32) * V32 / h32 / 1e9 / HBM_PEAK_GBS},
+           "cpu_baseline": cpu})
+
+
 def _host_cpu():
     import subprocess
 
@@ -549,7 +631,8 @@ def run_cpu_baseline(args):
     print(json.dumps(line), flush=True)
 
 
-SUITES = {"mixed32": run_mixed32, "batch24": run_batch24, "serve": run_serve, "cpu_baseline": run_cpu_baseline}
+SUITES = {"mixed32": run_mixed32, "batch24": run_batch24, "serve": run_serve, "cpu_baseline": run_cpu_baseline,
+          "wilson": run_wilson}
 
 
 def main():

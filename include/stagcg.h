@@ -267,6 +267,62 @@ int stag_tune_info(stag_ctx *ctx, int32_t gauge_id, int32_t precision,
                    int32_t *rhs_tile, int32_t *use_tables);
 
 /* Library version string. */
+/* ---- Wilson fermions (the paper's second workload, Sec. 5) ------------
+ *
+ * The paper runs an N_f = 2 Wilson-fermion program without writing the
+ * operator out; the library takes the textbook form
+ *   M = 1 - kappa H,
+ *   (H psi)(x) = sum_mu [(1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                        + (1 + gamma_mu) U_mu(x-mu)^dagger psi(x-mu)],
+ * with the same sites, links and boundary conditions as the staggered
+ * operator, and gamma matrices of a chiral basis, gamma_5 = diag(1,1,-1,-1):
+ *   gamma_x = [[0,0,0,i],[0,0,i,0],[0,-i,0,0],[-i,0,0,0]],
+ *   gamma_y = [[0,0,0,-1],[0,0,1,0],[0,1,0,0],[-1,0,0,0]],
+ *   gamma_z = [[0,0,i,0],[0,0,0,-i],[-i,0,0,0],[0,i,0,0]],
+ *   gamma_t = [[0,0,1,0],[0,0,0,1],[1,0,0,0],[0,1,0,0]].
+ * Spin-colour vectors: lexicographic complex128 [V][4 spin][3 colour]
+ * (host side, for stag_pack_spinor), and the library's even-odd layout
+ * complex128 [2 parity][4 spin][3 colour][V/2] on the device.  All FP64.
+ */
+
+/* Register links for the Wilson operator (same input layout and ownership as
+ * stag_set_gauge).  The t-boundary sign is folded in, the backward links
+ * U(x-mu)^dagger are stored at the site that uses them, and special unitary
+ * fields keep two rows (as for stag_set_gauge; STAG_LINK_ROWS=3 keeps three).
+ * The id is usable only with the stag_wilson_* calls (the staggered calls
+ * return EINVAL for it, and the Wilson calls for a staggered id).
+ * Errors: EINVAL, ENOMEM, ENONFINITE.  Synchronous. */
+int stag_set_gauge_wilson(stag_ctx *ctx, const int32_t dims[4], const double *links,
+                          int32_t links_on_device, int32_t t_antiperiodic,
+                          int32_t *gauge_id);
+
+/* Lexicographic [V][4][3] <-> even-odd [2][4][3][V/2] spin-colour vectors
+ * (device pointers, not overlapping).  Stream-ordered on `stream`. */
+int stag_pack_spinor(stag_ctx *ctx, const int32_t dims[4], const double *lex,
+                     double *eo, void *stream);
+int stag_unpack_spinor(stag_ctx *ctx, const int32_t dims[4], const double *eo,
+                       double *lex, void *stream);
+
+/* out = H in on the sites of out_parity (STAG_EVEN / STAG_ODD: the other
+ * parity of `out` is not written; STAG_ALL: every site).  in, out: device
+ * even-odd spin-colour vectors, not overlapping.  Errors: EINVAL, ENOENT.
+ * Asynchronous on `stream`. */
+int stag_wilson_dslash(stag_ctx *ctx, int32_t gauge_id, int32_t out_parity,
+                       const double *in, double *out, void *stream);
+
+/* Solve M x = b (full lattice) by CG on the even-odd normal equations:
+ * Mhat = 1 - kappa^2 D_eo D_oe on the even sites, Mhat^dagger Mhat x_e =
+ * Mhat^dagger (b_e + kappa D_eo b_o) (Mhat^dagger = gamma_5 Mhat gamma_5),
+ * stopping when <r,r> < tol^2 <Mhat^dagger bhat, Mhat^dagger bhat>, then
+ * x_o = b_o + kappa D_oe x_e.  Scalars and the stopping test stay on the
+ * device.  info->true_rel_resid is ||b - M x|| / ||b|| in FP64.
+ * b, x: device even-odd vectors (x is overwritten).  Errors: EINVAL (kappa
+ * <= 0, tol outside (0,1), maxiter < 0, overlap), ENOENT, ENOMEM, ENOCONV,
+ * EBREAKDOWN, ENONFINITE.  Returns when the solve is complete. */
+int stag_wilson_solve(stag_ctx *ctx, int32_t gauge_id, double kappa, double tol,
+                      int32_t maxiter, const double *b, double *x, void *stream,
+                      stag_cg_info *info);
+
 const char *stag_version(void);
 
 #ifdef __cplusplus

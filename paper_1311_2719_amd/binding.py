@@ -102,6 +102,12 @@ def load():
             "stag_tune_info": ([P, I32, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32),
                                 ctypes.POINTER(I32)], ctypes.c_int),
             "stag_version": ([], ctypes.c_char_p),
+            "stag_set_gauge_wilson": ([P, P, P, I32, I32, ctypes.POINTER(I32)], ctypes.c_int),
+            "stag_pack_spinor": ([P, P, P, P, P], ctypes.c_int),
+            "stag_unpack_spinor": ([P, P, P, P, P], ctypes.c_int),
+            "stag_wilson_dslash": ([P, I32, I32, P, P, P], ctypes.c_int),
+            "stag_wilson_solve": ([P, I32, ctypes.c_double, ctypes.c_double, I32, P, P, P, ctypes.POINTER(CGInfo)],
+                                  ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -118,6 +124,8 @@ def exported_symbols():
         "stag_free_gauge", "stag_gauge_dims", "stag_gauge_link_rows", "stag_pack_fermion", "stag_unpack_fermion", "stag_dslash",
         "stag_cg_solve", "stag_cg_solve_batch", "stag_submit", "stag_poll", "stag_wait",
         "stag_release_ticket", "stag_serve_config", "stag_tune_info", "stag_version",
+        "stag_set_gauge_wilson", "stag_pack_spinor", "stag_unpack_spinor", "stag_wilson_dslash",
+        "stag_wilson_solve",
     ]
 
 
@@ -195,6 +203,13 @@ class Context:
     # -- gauge fields --------------------------------------------------------
     def set_gauge(self, dims, links, antiperiodic_t=True) -> Field:
         """links: complex128 [V,4,3,3], numpy (host) or a torch CUDA tensor."""
+        return self._register(self.lib.stag_set_gauge, "stag_set_gauge", dims, links, antiperiodic_t)
+
+    def set_gauge_wilson(self, dims, links, antiperiodic_t=True) -> Field:
+        """The same links registered for the Wilson-fermion operator."""
+        return self._register(self.lib.stag_set_gauge_wilson, "stag_set_gauge_wilson", dims, links, antiperiodic_t)
+
+    def _register(self, fn, name, dims, links, antiperiodic_t):
         torch = _torch()
         d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32))
         gid = ctypes.c_int32()
@@ -207,10 +222,10 @@ class Context:
             keep = np.ascontiguousarray(links, dtype=np.complex128)
             ptr, on_dev = keep.ctypes.data, 0
         V = int(np.prod(d))
-        if keep.shape != (V, 4, 3, 3):
+        if tuple(keep.shape) != (V, 4, 3, 3):
             raise ValueError("links must have shape (V,4,3,3)")
-        _check(self.lib.stag_set_gauge(self.h, d.ctypes.data, ctypes.c_void_p(ptr), on_dev,
-                                       int(bool(antiperiodic_t)), ctypes.byref(gid)), "stag_set_gauge")
+        _check(fn(self.h, d.ctypes.data, ctypes.c_void_p(ptr), on_dev, int(bool(antiperiodic_t)), ctypes.byref(gid)),
+               name)
         f = Field(gid.value, tuple(int(v) for v in d))
         self.fields[gid.value] = f
         return f
@@ -259,6 +274,63 @@ class Context:
         if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()
                 and tuple(t.shape) == (2, 3, field.volume // 2)):
             raise ValueError("expected a contiguous complex128 CUDA tensor of shape (2,3,V/2)")
+
+    # -- Wilson spin-colour vectors ---------------------------------------------------
+    def new_spinor(self, field: Field):
+        torch = _torch()
+        return torch.zeros((2, 12, field.volume // 2), dtype=torch.complex128, device=self.torch_device)
+
+    def _check_spinor(self, field, t):
+        torch = _torch()
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()
+                and tuple(t.shape) == (2, 12, field.volume // 2)):
+            raise ValueError("expected a contiguous complex128 CUDA tensor of shape (2,12,V/2)")
+
+    def pack_spinor(self, field: Field, lex):
+        """(V,4,3) complex128 (numpy or torch) -> device even-odd tensor (2,12,V/2)."""
+        torch = _torch()
+        if not isinstance(lex, torch.Tensor):
+            lex = torch.from_numpy(np.ascontiguousarray(lex, dtype=np.complex128))
+        lex = lex.to(self.torch_device).contiguous()
+        if tuple(lex.shape) != (field.volume, 4, 3) or lex.dtype != torch.complex128:
+            raise ValueError("expected complex128 (V,4,3)")
+        eo = self.new_spinor(field)
+        d = np.asarray(field.dims, dtype=np.int32)
+        _check(self.lib.stag_pack_spinor(self.h, d.ctypes.data, ctypes.c_void_p(lex.data_ptr()),
+                                         ctypes.c_void_p(eo.data_ptr()), None), "stag_pack_spinor")
+        return eo
+
+    def unpack_spinor(self, field: Field, eo):
+        """device even-odd (2,12,V/2) -> device lexicographic (V,4,3)."""
+        torch = _torch()
+        self._check_spinor(field, eo)
+        lex = torch.empty((field.volume, 4, 3), dtype=torch.complex128, device=self.torch_device)
+        d = np.asarray(field.dims, dtype=np.int32)
+        _check(self.lib.stag_unpack_spinor(self.h, d.ctypes.data, ctypes.c_void_p(eo.data_ptr()),
+                                           ctypes.c_void_p(lex.data_ptr()), None), "stag_unpack_spinor")
+        return lex
+
+    def wilson_dslash(self, field: Field, inp, out, out_parity=ALL):
+        """out = H inp on the sites of out_parity (Wilson hopping term)."""
+        self._check_spinor(field, inp)
+        self._check_spinor(field, out)
+        _check(self.lib.stag_wilson_dslash(self.h, field.gauge_id, int(out_parity), ctypes.c_void_p(inp.data_ptr()),
+                                           ctypes.c_void_p(out.data_ptr()), None), "stag_wilson_dslash")
+        return out
+
+    def wilson_solve(self, field: Field, b, x, kappa, tol=1e-10, maxiter=20000, check=True):
+        """M x = b, M = 1 - kappa H, by CG on the even-odd normal equations."""
+        self._check_spinor(field, b)
+        self._check_spinor(field, x)
+        info = CGInfo()
+        rc = self.lib.stag_wilson_solve(self.h, field.gauge_id, float(kappa), float(tol), int(maxiter),
+                                        ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), None,
+                                        ctypes.byref(info))
+        if check:
+            _check(rc, "stag_wilson_solve")
+        d = info.as_dict()
+        d["rc"] = rc
+        return d
 
     # -- operator and solves ------------------------------------------------------
     def dslash(self, field: Field, inp, out, out_parity=ALL, offset=0, count=-1, accumulate=False, stream=None):

@@ -229,6 +229,137 @@ int stag_gauge_link_rows(stag_ctx *ctx, int32_t gauge_id, int32_t *rows)
     return STAG_OK;
 }
 
+// ---- Wilson fermions -----------------------------------------------------------------
+
+int stag_set_gauge_wilson(stag_ctx *ctx, const int32_t dims[4], const double *links, int32_t links_on_device,
+                          int32_t t_antiperiodic, int32_t *gauge_id)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx || !links || !gauge_id)
+        return set_error(STAG_EINVAL, "stag_set_gauge_wilson: NULL argument");
+    if (!dims_ok(dims))
+        return set_error(STAG_EINVAL, "stag_set_gauge_wilson: every extent must be even and >= 2");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    DeviceGuard dg(c->device);
+    auto f = std::make_shared<GaugeField>();
+    f->kind = FIELD_WILSON;
+    memcpy(f->dims, dims, sizeof(f->dims));
+    f->tap = t_antiperiodic ? 1 : 0;
+    f->g = make_geom(dims);
+    f->g.tap = f->tap;
+    const size_t Vh = f->g.Vh;
+    hipStream_t s = c->stream;
+    const size_t in_bytes = 2 * Vh * 4 * 9 * 16;
+    const double *src = links;
+    void *staging = nullptr;
+    if (!links_on_device) {
+        staging = c->arena.alloc(in_bytes);
+        if (!staging)
+            return set_error(STAG_ENOMEM, "stag_set_gauge_wilson: arena exhausted (staging %zu bytes)", in_bytes);
+        hipError_t e = hipMemcpyAsync(staging, links, in_bytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) {
+            c->arena.release(staging);
+            return set_error(STAG_EHIP, "stag_set_gauge_wilson: copy failed: %s", hipGetErrorString(e));
+        }
+        src = (const double *)staging;
+    }
+    const int rc = wilson_prepare(c, f.get(), src, s);
+    c->arena.release(staging);
+    if (rc != STAG_OK)
+        return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    f->id = c->next_id++;
+    c->fields[f->id] = f;
+    *gauge_id = f->id;
+    return STAG_OK;
+    STAG_GUARD_END
+}
+
+int stag_pack_spinor(stag_ctx *ctx, const int32_t dims[4], const double *lex, double *eo, void *stream)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx || !lex || !eo)
+        return set_error(STAG_EINVAL, "stag_pack_spinor: NULL argument");
+    if (!dims_ok(dims))
+        return set_error(STAG_EINVAL, "stag_pack_spinor: every extent must be even and >= 2");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    DeviceGuard dg(c->device);
+    return launch_pack_spinor(make_geom(dims), lex, eo, 1, pick_stream(ctx, stream));
+    STAG_GUARD_END
+}
+
+int stag_unpack_spinor(stag_ctx *ctx, const int32_t dims[4], const double *eo, double *lex, void *stream)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx || !lex || !eo)
+        return set_error(STAG_EINVAL, "stag_unpack_spinor: NULL argument");
+    if (!dims_ok(dims))
+        return set_error(STAG_EINVAL, "stag_unpack_spinor: every extent must be even and >= 2");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    DeviceGuard dg(c->device);
+    return launch_pack_spinor(make_geom(dims), lex, const_cast<double *>(eo), 0, pick_stream(ctx, stream));
+    STAG_GUARD_END
+}
+
+static int wilson_field(stag_ctx *ctx, int32_t gauge_id, std::shared_ptr<GaugeField> &f)
+{
+    f = reinterpret_cast<Ctx *>(ctx)->field(gauge_id);
+    if (!f)
+        return set_error(STAG_ENOENT, "unknown gauge id %d", gauge_id);
+    if (f->kind != FIELD_WILSON)
+        return set_error(STAG_EINVAL, "gauge id %d holds staggered links", gauge_id);
+    return STAG_OK;
+}
+
+int stag_wilson_dslash(stag_ctx *ctx, int32_t gauge_id, int32_t out_parity, const double *in, double *out,
+                       void *stream)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx || !in || !out)
+        return set_error(STAG_EINVAL, "stag_wilson_dslash: NULL argument");
+    std::shared_ptr<GaugeField> f;
+    int rc = wilson_field(ctx, gauge_id, f);
+    if (rc != STAG_OK)
+        return rc;
+    if (out_parity < STAG_EVEN || out_parity > STAG_ALL)
+        return set_error(STAG_EINVAL, "stag_wilson_dslash: bad parity %d", out_parity);
+    const char *a0 = (const char *)in, *b0 = (const char *)out;
+    const size_t fb = (size_t)2 * 12 * f->g.Vh * 16;
+    if (a0 < b0 + fb && b0 < a0 + fb)
+        return set_error(STAG_EINVAL, "stag_wilson_dslash: in and out must not overlap");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    DeviceGuard dg(c->device);
+    return wilson_dslash(f.get(), out_parity, in, out, pick_stream(ctx, stream));
+    STAG_GUARD_END
+}
+
+int stag_wilson_solve(stag_ctx *ctx, int32_t gauge_id, double kappa, double tol, int32_t maxiter, const double *b,
+                      double *x, void *stream, stag_cg_info *info)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx || !b || !x)
+        return set_error(STAG_EINVAL, "stag_wilson_solve: NULL argument");
+    std::shared_ptr<GaugeField> f;
+    int rc = wilson_field(ctx, gauge_id, f);
+    if (rc != STAG_OK)
+        return rc;
+    if (!(kappa > 0 && kappa < INFINITY) || !(tol > 0 && tol < 1) || maxiter < 0)
+        return set_error(STAG_EINVAL, "stag_wilson_solve: kappa > 0, 0 < tol < 1 and maxiter >= 0 are required");
+    const char *a0 = (const char *)b, *b0 = (const char *)x;
+    const size_t fb = (size_t)2 * 12 * f->g.Vh * 16;
+    if (a0 < b0 + fb && b0 < a0 + fb)
+        return set_error(STAG_EINVAL, "stag_wilson_solve: b and x must not overlap");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    DeviceGuard dg(c->device);
+    return wilson_cg_solve(c, f.get(), kappa, tol, maxiter, b, x, pick_stream(ctx, stream), info);
+    STAG_GUARD_END
+}
+
 int stag_pack_fermion(stag_ctx *ctx, const int32_t dims[4], const double *lex, double *eo, void *stream)
 {
     STAG_GUARD_BEGIN
@@ -270,6 +401,8 @@ int stag_dslash(stag_ctx *ctx, int32_t gauge_id, int32_t out_parity, int64_t off
     auto f = c->field(gauge_id);
     if (!f)
         return set_error(STAG_ENOENT, "unknown gauge id %d", gauge_id);
+    if (f->kind != FIELD_STAGGERED)
+        return set_error(STAG_EINVAL, "gauge id %d holds Wilson-fermion links", gauge_id);
     const int64_t Vh = f->g.Vh;
     if (out_parity < STAG_EVEN || out_parity > STAG_ALL)
         return set_error(STAG_EINVAL, "stag_dslash: bad parity %d", out_parity);
@@ -302,6 +435,8 @@ int stag_cg_solve(stag_ctx *ctx, int32_t gauge_id, const stag_cg_params *params,
     auto f = c->field(gauge_id);
     if (!f)
         return set_error(STAG_ENOENT, "unknown gauge id %d", gauge_id);
+    if (f->kind != FIELD_STAGGERED)
+        return set_error(STAG_EINVAL, "gauge id %d holds Wilson-fermion links", gauge_id);
     int rc = validate_cg_params(*params);
     if (rc != STAG_OK)
         return rc;
@@ -324,6 +459,8 @@ int stag_cg_solve_batch(stag_ctx *ctx, int32_t gauge_id, int32_t nrhs, const sta
     auto f = c->field(gauge_id);
     if (!f)
         return set_error(STAG_ENOENT, "unknown gauge id %d", gauge_id);
+    if (f->kind != FIELD_STAGGERED)
+        return set_error(STAG_EINVAL, "gauge id %d holds Wilson-fermion links", gauge_id);
     for (int i = 0; i < nrhs; ++i) {
         int rc = validate_cg_params(params[i]);
         if (rc != STAG_OK)
@@ -345,6 +482,8 @@ int stag_tune_info(stag_ctx *ctx, int32_t gauge_id, int32_t precision, int32_t n
     auto f = c->field(gauge_id);
     if (!f)
         return set_error(STAG_ENOENT, "unknown gauge id %d", gauge_id);
+    if (f->kind != FIELD_STAGGERED)
+        return set_error(STAG_EINVAL, "gauge id %d holds Wilson-fermion links", gauge_id);
     DeviceGuard dg(c->device);
     KernelCfg k = tune_config(c, f.get(), precision, nrhs, c->stream);
     if (lanes_per_site)
@@ -399,6 +538,8 @@ int stag_submit(stag_ctx *ctx, int32_t gauge_id, const stag_cg_params *params, c
     auto f = c->field(gauge_id);
     if (!f)
         return set_error(STAG_ENOENT, "unknown gauge id %d", gauge_id);
+    if (f->kind != FIELD_STAGGERED)
+        return set_error(STAG_EINVAL, "gauge id %d holds Wilson-fermion links", gauge_id);
     return server_of(c)->submit(f, *params, b_dev, x_dev, ticket);
     STAG_GUARD_END
 }

@@ -66,8 +66,11 @@ struct KernelCfg {
 
 // ---- gauge field -------------------------------------------------------------
 
+enum FieldKind : int32_t { FIELD_STAGGERED = 0, FIELD_WILSON = 1 };
+
 struct GaugeField {
     int32_t id = 0;
+    int32_t kind = FIELD_STAGGERED;  // which operator the links were prepared for
     int32_t dims[4] = {0, 0, 0, 0};
     int32_t tap = 1;
     Geom g{};
@@ -138,6 +141,17 @@ constexpr double kTwoRowTolerance = 1e-14;
 int gauge_check(Ctx *ctx, const Geom &g, const double *links_dev, hipStream_t s, bool &two_rows);
 // Fill f->links (f->rows rows, every precision) and f->nbr from the links.
 int gauge_prepare(GaugeField *f, const double *links_dev, hipStream_t s);
+
+// Wilson fermions: check the links, choose the stored rows, allocate and fill
+// f->links[0] (FP64; t-boundary sign folded, backward links daggered).
+int wilson_prepare(Ctx *ctx, GaugeField *f, const double *links_dev, hipStream_t s);
+// lexicographic [V][4][3] <-> even-odd [2][12][Vh] complex128
+int launch_pack_spinor(const Geom &g, const double *lex, double *eo, int to_eo, hipStream_t s);
+// out_p = (H in)_p on one parity or both (STAG_ALL)
+int wilson_dslash(GaugeField *f, int out_parity, const double *in, double *out, hipStream_t s);
+// M x = b by CG on the even-odd normal equations
+int wilson_cg_solve(Ctx *ctx, GaugeField *f, double kappa, double tol, int maxiter, const double *b, double *x,
+                    hipStream_t s, stag_cg_info *info);
 int launch_pack(const Geom &g, const double *lex, double *eo, int to_eo, hipStream_t s);
 int dslash_f64(Ctx *ctx, GaugeField *f, int out_parity, int64_t offset, int64_t count,
                const double *in, double *out, int accumulate, hipStream_t s);

@@ -1,0 +1,356 @@
+// Wilson fermions (the paper's second workload, Sec. 5): gauge preparation,
+// spin-colour vector layout, the standalone hop and the even-odd CG driver.
+// The operator and the kernels are described in wilson_kernels.hpp.
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "runtime.hpp"
+#include "wilson_kernels.hpp"
+
+namespace stag {
+
+namespace {
+
+// The link of direction d at checkerboard site s of output parity p for the
+// Wilson operator: W_mu(x) = s_fwd U_mu(x) (d < 4), B_mu(x) = s_bwd
+// U_mu(x - mu)^dagger (d >= 4), s_* the t-boundary signs.  False if an entry is
+// not finite.
+__device__ bool wilson_link(const Geom &g, const double *__restrict__ U, int p, int d, int s, dbl2 (&w)[9])
+{
+    const SiteCoord c = decode_site(g, p, s);
+    const int mu = d & 3;
+    int src[4] = {c.x, c.y, c.z, c.t};
+    const bool back = d >= 4;
+    double fac = wil::wilson_link_negative(g, c, d) ? -1.0 : 1.0;
+    if (back)
+        src[mu] = src[mu] == 0 ? g.L[mu] - 1 : src[mu] - 1;
+    const int64_t lex = src[0] + (int64_t)g.L[0] * (src[1] + (int64_t)g.L[1] * (src[2] + (int64_t)g.L[2] * src[3]));
+    const double *u = U + (lex * 4 + mu) * 18;
+    bool finite = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const int k = back ? (b * 3 + a) : (a * 3 + b);
+            const double re = u[2 * k], im = back ? -u[2 * k + 1] : u[2 * k + 1];
+            w[a * 3 + b] = dbl2{re * fac, im * fac};
+            finite = finite && isfinite(re) && isfinite(im);
+        }
+    return finite;
+}
+
+// flags |= 1: an entry is not finite; |= 2: some link is not special unitary
+// in the sense the two-row form relies on (row 2 = conj(row 0 x row 1) / c)
+__global__ void __launch_bounds__(256) k_wcheck_links(Geom g, const double *__restrict__ U, double tol, int *flags)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)2 * 8 * g.Vh)
+        return;
+    const int s = (int)(gid % g.Vh), d = (int)((gid / g.Vh) % 8), p = (int)(gid / ((int64_t)8 * g.Vh));
+    dbl2 w[9];
+    int f = 0;
+    if (!wilson_link(g, U, p, d, s, w)) {
+        f = 1;
+    } else {
+        cplx<double> W[9];
+        for (int k = 0; k < 9; ++k)
+            W[k] = {w[k].x, w[k].y};
+        const cplx<double> given[3] = {W[6], W[7], W[8]};
+        third_row(W, wil::wilson_link_negative(g, decode_site(g, p, s), d) ? -1.0 : 1.0);
+        double dev = 0.0;
+        for (int k = 0; k < 3; ++k)
+            dev = fmax(dev, fmax(fabs(W[6 + k].re - given[k].re), fabs(W[6 + k].im - given[k].im)));
+        if (!(dev <= tol))
+            f = 2;
+    }
+    if (f)
+        atomicOr(flags, f);
+}
+
+template <int ROWS>
+__global__ void __launch_bounds__(256) k_wprepare_links(Geom g, const double *__restrict__ U, dbl2 *__restrict__ l64)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)2 * 8 * g.Vh)
+        return;
+    const int s = (int)(gid % g.Vh), d = (int)((gid / g.Vh) % 8), p = (int)(gid / ((int64_t)8 * g.Vh));
+    dbl2 w[9];
+    (void)wilson_link(g, U, p, d, s, w);
+    const int64_t base = link_parity_entries(ROWS, g.Vh) * p;
+#pragma unroll
+    for (int k = 0; k < 3 * ROWS; ++k)
+        l64[base + link_offset(g.Vh, d, k, s)] = w[k];
+}
+
+// lexicographic [V][4][3] <-> even-odd [2][12][Vh]
+__global__ void __launch_bounds__(256) k_pack_spinor(Geom g, dbl2 *__restrict__ lex, dbl2 *__restrict__ eo, int to_eo)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)2 * g.Vh)
+        return;
+    const int p = (int)(gid / g.Vh), s = (int)(gid % g.Vh);
+    const SiteCoord c = decode_site(g, p, s);
+    const int64_t l = c.x + (int64_t)g.L[0] * (c.y + (int64_t)g.L[1] * (c.z + (int64_t)g.L[2] * c.t));
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        const int64_t e = ((int64_t)p * 12 + k) * g.Vh + s;
+        if (to_eo)
+            eo[e] = lex[l * 12 + k];
+        else
+            lex[l * 12 + k] = eo[e];
+    }
+}
+
+// per-block partial sums of |v|^2 over n complex entries
+__global__ void __launch_bounds__(256) k_norm2_partials(const dbl2 *__restrict__ v, int64_t n, double *out)
+{
+    __shared__ double lds[4];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const dbl2 t = v[i];
+        acc += t.x * t.x + t.y * t.y;
+    }
+    double arr[1] = {acc};
+    double tot;
+    block_sum_multi<1>(arr, lds, tot);
+    if (threadIdx.x == 0)
+        out[blockIdx.x] = tot;
+}
+
+constexpr int kWBlock = 128;
+
+}  // namespace
+
+int wilson_prepare(Ctx *ctx, GaugeField *f, const double *links_dev, hipStream_t s)
+{
+    const Geom &g = f->g;
+    const int64_t n = (int64_t)2 * 8 * g.Vh;
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    int *flags = (int *)ctx->arena.alloc(256);
+    if (!flags)
+        return set_error(STAG_ENOMEM, "arena exhausted (gauge check flags)");
+    int hflags = 0;
+    hipError_t e = hipMemsetAsync(flags, 0, sizeof(int), s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_wcheck_links, grid, block, 0, s, g, links_dev, kTwoRowTolerance, flags);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    ctx->arena.release(flags);
+    if (e != hipSuccess)
+        return set_error(STAG_EHIP, "gauge check failed: %s", hipGetErrorString(e));
+    if (hflags & 1)
+        return set_error(STAG_ENONFINITE, "gauge field holds NaN or Inf");
+    const char *rows_env = getenv("STAG_LINK_ROWS");
+    f->rows = (hflags & 2) == 0 && !(rows_env && atoi(rows_env) == 3) ? 2 : 3;
+    const size_t lb = (size_t)2 * link_parity_entries(f->rows, g.Vh) * 16;
+    f->links[0] = ctx->arena.alloc(lb);
+    if (!f->links[0])
+        return set_error(STAG_ENOMEM, "arena exhausted (%zu bytes of Wilson links)", lb);
+    f->bytes = lb;
+    if (f->rows == 2)
+        hipLaunchKernelGGL((k_wprepare_links<2>), grid, block, 0, s, g, links_dev, (dbl2 *)f->links[0]);
+    else
+        hipLaunchKernelGGL((k_wprepare_links<3>), grid, block, 0, s, g, links_dev, (dbl2 *)f->links[0]);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        ctx->arena.release(f->links[0]);
+        f->links[0] = nullptr;
+        return set_error(STAG_EHIP, "Wilson gauge preparation failed: %s", hipGetErrorString(e));
+    }
+    return STAG_OK;
+}
+
+int launch_pack_spinor(const Geom &g, const double *lex, double *eo, int to_eo, hipStream_t s)
+{
+    const int64_t n = (int64_t)2 * g.Vh;
+    hipLaunchKernelGGL(k_pack_spinor, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g,
+                       (dbl2 *)const_cast<double *>(lex), (dbl2 *)eo, to_eo);
+    STAG_HIP_CHECK(hipGetLastError());
+    return STAG_OK;
+}
+
+int wilson_dslash(GaugeField *f, int out_parity, const double *in, double *out, hipStream_t s)
+{
+    const Geom &g = f->g;
+    const dim3 grid((unsigned)((g.Vh + kWBlock - 1) / kWBlock), out_parity == STAG_ALL ? 2u : 1u);
+    const int pf = out_parity == STAG_ALL ? -1 : out_parity;
+    if (f->rows == 2)
+        hipLaunchKernelGGL((wil::k_wilson_dslash<2>), grid, dim3(kWBlock), 0, s, g, (const dbl2 *)f->links[0],
+                           (const dbl2 *)in, (dbl2 *)out, pf);
+    else
+        hipLaunchKernelGGL((wil::k_wilson_dslash<3>), grid, dim3(kWBlock), 0, s, g, (const dbl2 *)f->links[0],
+                           (const dbl2 *)in, (dbl2 *)out, pf);
+    STAG_HIP_CHECK(hipGetLastError());
+    return STAG_OK;
+}
+
+namespace {
+
+// The launches of one solve, for one link format.
+template <int ROWS> struct WLaunch {
+    static void init(const wil::WArgs &a, dim3 grid, hipStream_t s)
+    {
+        hipLaunchKernelGGL((wil::k_wil_bhat<ROWS>), grid, dim3(kWBlock), 0, s, a);
+        hipLaunchKernelGGL((wil::k_wil_odd_g5<ROWS>), grid, dim3(kWBlock), 0, s, a, (const dbl2 *)a.bh, 0, 0);
+        hipLaunchKernelGGL((wil::k_wil_init<ROWS>), grid, dim3(kWBlock), 0, s, a);
+    }
+    static void step(const wil::WArgs &a, dim3 grid, hipStream_t s, int ver)
+    {
+        hipLaunchKernelGGL((wil::k_wil_step1<ROWS>), grid, dim3(kWBlock), 0, s, a, ver);
+        hipLaunchKernelGGL((wil::k_wil_step2<ROWS>), grid, dim3(kWBlock), 0, s, a, ver);
+        hipLaunchKernelGGL((wil::k_wil_odd_g5<ROWS>), grid, dim3(kWBlock), 0, s, a, (const dbl2 *)a.ap, ver, 1);
+        hipLaunchKernelGGL((wil::k_wil_step4<ROWS>), grid, dim3(kWBlock), 0, s, a, ver);
+    }
+    static void finish(const wil::WArgs &a, dim3 grid, hipStream_t s)
+    {
+        hipLaunchKernelGGL((wil::k_wil_xodd<ROWS>), grid, dim3(kWBlock), 0, s, a);
+        hipLaunchKernelGGL((wil::k_wil_resid<ROWS>), grid, dim3(kWBlock), 0, s, a, 0);
+        hipLaunchKernelGGL((wil::k_wil_resid<ROWS>), grid, dim3(kWBlock), 0, s, a, 1);
+    }
+};
+
+}  // namespace
+
+int wilson_cg_solve(Ctx *ctx, GaugeField *f, double kappa, double tol, int maxiter, const double *b, double *x,
+                    hipStream_t s, stag_cg_info *info)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const Geom &g = f->g;
+    const int Vh = g.Vh;
+    const int nblk = (Vh + kWBlock - 1) / kWBlock;
+    const int pstride = (nblk + 63) & ~63;
+    const size_t vec = (size_t)12 * Vh * sizeof(dbl2);
+    const size_t bytes = 6 * vec + 256 + (size_t)4 * pstride * sizeof(double);
+    char *mem = (char *)ctx->arena.alloc(bytes);
+    if (!mem)
+        return set_error(STAG_ENOMEM, "arena exhausted: Wilson CG workspace needs %zu bytes", bytes);
+    struct Release {
+        Arena &arena;
+        void *p;
+        hipStream_t s;
+        ~Release()
+        {
+            (void)hipStreamSynchronize(s);
+            arena.release(p);
+        }
+    } release{ctx->arena, mem, s};
+    wil::WArgs a;
+    memset(&a, 0, sizeof(a));
+    a.g = g;
+    a.links[0] = (const dbl2 *)f->links[0];
+    a.links[1] = (const dbl2 *)f->links[0] + link_parity_entries(f->rows, Vh);
+    a.kappa = kappa;
+    a.b = (const dbl2 *)b;
+    a.x = (dbl2 *)x;
+    a.bh = (dbl2 *)mem;
+    a.r = (dbl2 *)(mem + vec);
+    a.p[0] = (dbl2 *)(mem + 2 * vec);
+    a.p[1] = (dbl2 *)(mem + 3 * vec);
+    a.ap = (dbl2 *)(mem + 4 * vec);
+    a.t = (dbl2 *)(mem + 5 * vec);
+    a.st[0] = (wil::WState *)(mem + 6 * vec);
+    a.st[1] = a.st[0] + 1;
+    a.partials = (double *)(mem + 6 * vec + 256);
+    a.pstride = pstride;
+
+    wil::WState *host = nullptr;
+    STAG_HIP_CHECK(hipHostMalloc((void **)&host, 4 * sizeof(wil::WState), hipHostMallocDefault));
+    std::vector<double> hpart(2 * (size_t)nblk);
+    hipEvent_t ev = nullptr;
+    struct HostRelease {
+        wil::WState *h;
+        hipEvent_t *e;
+        ~HostRelease()
+        {
+            if (*e)
+                (void)hipEventDestroy(*e);
+            (void)hipHostFree(h);
+        }
+    } host_release{host, &ev};
+    STAG_HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    memset(host, 0, 4 * sizeof(wil::WState));
+    host[0].mode = wil::W_INIT;
+    host[0].tol2 = tol * tol;
+    host[0].maxiter = maxiter;
+    host[1] = host[0];
+    STAG_HIP_CHECK(hipMemcpyAsync(a.st[0], host, 2 * sizeof(wil::WState), hipMemcpyHostToDevice, s));
+
+    const dim3 grid((unsigned)nblk);
+    auto init = f->rows == 2 ? WLaunch<2>::init : WLaunch<3>::init;
+    auto step = f->rows == 2 ? WLaunch<2>::step : WLaunch<3>::step;
+    auto finish = f->rows == 2 ? WLaunch<2>::finish : WLaunch<3>::finish;
+    init(a, grid, s);
+    STAG_HIP_CHECK(hipGetLastError());
+    // epochs of E iterations; the state after epoch n is read while epoch n+1 runs
+    const int E = 16;
+    int64_t it = 0;
+    auto epoch = [&]() {
+        for (int k = 0; k < E; ++k, ++it)
+            step(a, grid, s, (int)(it & 1));
+    };
+    auto snapshot = [&]() -> hipError_t {
+        hipError_t e = hipMemcpyAsync(host + 2, a.st[0], 2 * sizeof(wil::WState), hipMemcpyDeviceToHost, s);
+        return e == hipSuccess ? hipEventRecord(ev, s) : e;
+    };
+    epoch();
+    STAG_HIP_CHECK(snapshot());
+    const int64_t budget = (int64_t)maxiter + 2 * E + 1;
+    wil::WState last{};
+    bool done = false;
+    while (!done) {
+        if (it < budget)
+            epoch();
+        STAG_HIP_CHECK(hipGetLastError());
+        STAG_HIP_CHECK(hipEventSynchronize(ev));
+        last = host[3].step > host[2].step ? host[3] : host[2];
+        done = last.mode == wil::W_DONE || it >= budget;
+        if (!done)
+            STAG_HIP_CHECK(snapshot());
+    }
+    STAG_HIP_CHECK(hipMemcpyAsync(host + 2, a.st[0], 2 * sizeof(wil::WState), hipMemcpyDeviceToHost, s));
+    finish(a, grid, s);
+    STAG_HIP_CHECK(hipGetLastError());
+    // |b - M x|^2 (slots 0 and 1 of buffer 0), then |b|^2 into buffer 1
+    STAG_HIP_CHECK(hipMemcpyAsync(hpart.data(), a.partials, nblk * sizeof(double), hipMemcpyDeviceToHost, s));
+    STAG_HIP_CHECK(hipMemcpyAsync(hpart.data() + nblk, a.partials + pstride, nblk * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+    STAG_HIP_CHECK(hipStreamSynchronize(s));
+    double res2 = 0.0;
+    for (int i = 0; i < 2 * nblk; ++i)
+        res2 += hpart[i];
+    const int nb2 = 256;
+    double *bpart = a.partials + (size_t)2 * pstride;
+    hipLaunchKernelGGL(k_norm2_partials, dim3(nb2 < 2 * pstride ? nb2 : 2 * pstride), dim3(256), 0, s,
+                       (const dbl2 *)b, (int64_t)24 * Vh, bpart);
+    STAG_HIP_CHECK(hipGetLastError());
+    const int nb2u = nb2 < 2 * pstride ? nb2 : 2 * pstride;
+    std::vector<double> hb(nb2u);
+    STAG_HIP_CHECK(hipMemcpyAsync(hb.data(), bpart, nb2u * sizeof(double), hipMemcpyDeviceToHost, s));
+    STAG_HIP_CHECK(hipStreamSynchronize(s));
+    double bb = 0.0;
+    for (double v : hb)
+        bb += v;
+    last = host[3].step > host[2].step ? host[3] : host[2];
+    stag_cg_info inf;
+    memset(&inf, 0, sizeof(inf));
+    inf.status = last.mode == wil::W_DONE ? last.status : STAG_ENOCONV;
+    inf.iters = last.iters;
+    inf.true_rel_resid = bb > 0 ? std::sqrt(res2 / bb) : 0.0;
+    inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info)
+        *info = inf;
+    if (inf.status != STAG_OK)
+        return set_error(inf.status, "Wilson CG did not converge (status %d)", inf.status);
+    return STAG_OK;
+}
+
+}  // namespace stag

@@ -28,6 +28,7 @@ __all__ = [
     "smooth_su3",
     "unit_links",
     "gaussian_source",
+    "gaussian_spinor",
     "proj_su3",
     "masses_uniform",
 ]
@@ -114,6 +115,14 @@ def gaussian_source(dims, seed: int) -> np.ndarray:
     V = volume(dims)
     rng = np.random.default_rng(seed)
     g = rng.standard_normal((V, 3, 2))
+    return np.ascontiguousarray(g[..., 0] + 1j * g[..., 1], dtype=np.complex128)
+
+
+def gaussian_spinor(dims, seed: int) -> np.ndarray:
+    """Spin-colour source [V, 4, 3] (Wilson fermions) with Re, Im ~ N(0,1)."""
+    V = volume(dims)
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((V, 4, 3, 2))
     return np.ascontiguousarray(g[..., 0] + 1j * g[..., 1], dtype=np.complex128)
 
 
