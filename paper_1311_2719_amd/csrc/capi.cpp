@@ -333,7 +333,7 @@ int stag_wilson_dslash(stag_ctx *ctx, int32_t gauge_id, int32_t out_parity, cons
         return set_error(STAG_EINVAL, "stag_wilson_dslash: in and out must not overlap");
     Ctx *c = reinterpret_cast<Ctx *>(ctx);
     DeviceGuard dg(c->device);
-    return wilson_dslash(f.get(), out_parity, in, out, pick_stream(ctx, stream));
+    return wilson_dslash(c, f.get(), out_parity, in, out, pick_stream(ctx, stream));
     STAG_GUARD_END
 }
 

@@ -148,7 +148,7 @@ int wilson_prepare(Ctx *ctx, GaugeField *f, const double *links_dev, hipStream_t
 // lexicographic [V][4][3] <-> even-odd [2][12][Vh] complex128
 int launch_pack_spinor(const Geom &g, const double *lex, double *eo, int to_eo, hipStream_t s);
 // out_p = (H in)_p on one parity or both (STAG_ALL)
-int wilson_dslash(GaugeField *f, int out_parity, const double *in, double *out, hipStream_t s);
+int wilson_dslash(Ctx *ctx, GaugeField *f, int out_parity, const double *in, double *out, hipStream_t s);
 // M x = b by CG on the even-odd normal equations
 int wilson_cg_solve(Ctx *ctx, GaugeField *f, double kappa, double tol, int maxiter, const double *b, double *x,
                     hipStream_t s, stag_cg_info *info);

@@ -3,8 +3,10 @@
 // The operator and the kernels are described in wilson_kernels.hpp.
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "runtime.hpp"
@@ -178,47 +180,120 @@ int launch_pack_spinor(const Geom &g, const double *lex, double *eo, int to_eo, 
     return STAG_OK;
 }
 
-int wilson_dslash(GaugeField *f, int out_parity, const double *in, double *out, hipStream_t s)
-{
-    const Geom &g = f->g;
-    const dim3 grid((unsigned)((g.Vh + kWBlock - 1) / kWBlock), out_parity == STAG_ALL ? 2u : 1u);
-    const int pf = out_parity == STAG_ALL ? -1 : out_parity;
-    if (f->rows == 2)
-        hipLaunchKernelGGL((wil::k_wilson_dslash<2>), grid, dim3(kWBlock), 0, s, g, (const dbl2 *)f->links[0],
-                           (const dbl2 *)in, (dbl2 *)out, pf);
-    else
-        hipLaunchKernelGGL((wil::k_wilson_dslash<3>), grid, dim3(kWBlock), 0, s, g, (const dbl2 *)f->links[0],
-                           (const dbl2 *)in, (dbl2 *)out, pf);
-    STAG_HIP_CHECK(hipGetLastError());
-    return STAG_OK;
-}
-
 namespace {
 
-// The launches of one solve, for one link format.
-template <int ROWS> struct WLaunch {
-    static void init(const wil::WArgs &a, dim3 grid, hipStream_t s)
+// The launches of the hop and of one solve, for one link format and one
+// number of lanes per site.
+template <int ROWS, int LPS> struct WLaunch {
+    static dim3 grid(int Vh, int ny = 1) { return dim3((unsigned)(((int64_t)Vh * LPS + kWBlock - 1) / kWBlock), ny); }
+    static void hop(const GaugeField *f, int pf, const double *in, double *out, hipStream_t s)
     {
-        hipLaunchKernelGGL((wil::k_wil_bhat<ROWS>), grid, dim3(kWBlock), 0, s, a);
-        hipLaunchKernelGGL((wil::k_wil_odd_g5<ROWS>), grid, dim3(kWBlock), 0, s, a, (const dbl2 *)a.bh, 0, 0);
-        hipLaunchKernelGGL((wil::k_wil_init<ROWS>), grid, dim3(kWBlock), 0, s, a);
+        hipLaunchKernelGGL((wil::k_wilson_dslash<ROWS, LPS>), grid(f->g.Vh, pf < 0 ? 2 : 1), dim3(kWBlock), 0, s, f->g,
+                           (const dbl2 *)f->links[0], (const dbl2 *)in, (dbl2 *)out, pf);
     }
-    static void step(const wil::WArgs &a, dim3 grid, hipStream_t s, int ver)
+    static void init(const wil::WArgs &a, hipStream_t s)
     {
-        hipLaunchKernelGGL((wil::k_wil_step1<ROWS>), grid, dim3(kWBlock), 0, s, a, ver);
-        hipLaunchKernelGGL((wil::k_wil_step2<ROWS>), grid, dim3(kWBlock), 0, s, a, ver);
-        hipLaunchKernelGGL((wil::k_wil_odd_g5<ROWS>), grid, dim3(kWBlock), 0, s, a, (const dbl2 *)a.ap, ver, 1);
-        hipLaunchKernelGGL((wil::k_wil_step4<ROWS>), grid, dim3(kWBlock), 0, s, a, ver);
+        const dim3 g = grid(a.g.Vh);
+        hipLaunchKernelGGL((wil::k_wil_bhat<ROWS, LPS>), g, dim3(kWBlock), 0, s, a);
+        hipLaunchKernelGGL((wil::k_wil_odd_g5<ROWS, LPS>), g, dim3(kWBlock), 0, s, a, (const dbl2 *)a.bh, 0, 0);
+        hipLaunchKernelGGL((wil::k_wil_init<ROWS, LPS>), g, dim3(kWBlock), 0, s, a);
     }
-    static void finish(const wil::WArgs &a, dim3 grid, hipStream_t s)
+    static void step(const wil::WArgs &a, hipStream_t s, int ver)
     {
-        hipLaunchKernelGGL((wil::k_wil_xodd<ROWS>), grid, dim3(kWBlock), 0, s, a);
-        hipLaunchKernelGGL((wil::k_wil_resid<ROWS>), grid, dim3(kWBlock), 0, s, a, 0);
-        hipLaunchKernelGGL((wil::k_wil_resid<ROWS>), grid, dim3(kWBlock), 0, s, a, 1);
+        const dim3 g = grid(a.g.Vh);
+        hipLaunchKernelGGL((wil::k_wil_step1<ROWS, LPS>), g, dim3(kWBlock), 0, s, a, ver);
+        hipLaunchKernelGGL((wil::k_wil_step2<ROWS, LPS>), g, dim3(kWBlock), 0, s, a, ver);
+        hipLaunchKernelGGL((wil::k_wil_odd_g5<ROWS, LPS>), g, dim3(kWBlock), 0, s, a, (const dbl2 *)a.ap, ver, 1);
+        hipLaunchKernelGGL((wil::k_wil_step4<ROWS, LPS>), g, dim3(kWBlock), 0, s, a, ver);
+    }
+    static void finish(const wil::WArgs &a, hipStream_t s)
+    {
+        const dim3 g = grid(a.g.Vh);
+        hipLaunchKernelGGL((wil::k_wil_xodd<ROWS, LPS>), g, dim3(kWBlock), 0, s, a);
+        hipLaunchKernelGGL((wil::k_wil_resid<ROWS, LPS>), g, dim3(kWBlock), 0, s, a, 0);
+        hipLaunchKernelGGL((wil::k_wil_resid<ROWS, LPS>), g, dim3(kWBlock), 0, s, a, 1);
     }
 };
 
+struct WTable {
+    void (*hop)(const GaugeField *, int, const double *, double *, hipStream_t);
+    void (*init)(const wil::WArgs &, hipStream_t);
+    void (*step)(const wil::WArgs &, hipStream_t, int);
+    void (*finish)(const wil::WArgs &, hipStream_t);
+};
+
+template <int ROWS, int LPS> constexpr WTable wtable()
+{
+    return {WLaunch<ROWS, LPS>::hop, WLaunch<ROWS, LPS>::init, WLaunch<ROWS, LPS>::step, WLaunch<ROWS, LPS>::finish};
+}
+
+constexpr int kWLps[3] = {1, 2, 4};
+
+const WTable &wilson_table(int rows, int lps)
+{
+    static const WTable t[2][3] = {{wtable<2, 1>(), wtable<2, 2>(), wtable<2, 4>()},
+                                   {wtable<3, 1>(), wtable<3, 2>(), wtable<3, 4>()}};
+    return t[rows == 2 ? 0 : 1][lps == 1 ? 0 : lps == 2 ? 1 : 2];
+}
+
+// Lanes per site for the Wilson kernels of a field: STAG_WILSON_LPS, else the
+// fastest hop on two full-field vectors of scratch (`in`, `out`, each
+// [2][12][Vh]), timed once per field; 4 when no scratch is given.
+int wilson_lps(Ctx *ctx, GaugeField *f, const double *in, double *out, hipStream_t s)
+{
+    const uint64_t key = (uint64_t)3 << 40;
+    if (const char *e = getenv("STAG_WILSON_LPS")) {
+        const int v = atoi(e);
+        if (v == 1 || v == 2 || v == 4)
+            return v;
+    }
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = f->tuned.find(key);
+        if (it != f->tuned.end())
+            return it->second.lps;
+    }
+    if (!in || !out)
+        return 4;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return 4;
+    int best = 4;
+    float best_ms = 1e30f;
+    for (int L : kWLps) {
+        const WTable &t = wilson_table(f->rows, L);
+        t.hop(f, -1, in, out, s);
+        (void)hipEventRecord(e0, s);
+        for (int i = 0; i < 3; ++i)
+            t.hop(f, -1, in, out, s);
+        (void)hipEventRecord(e1, s);
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
+            ms < best_ms * 0.97f) {
+            best_ms = ms;
+            best = L;
+        }
+        if (getenv("STAG_TUNE_VERBOSE"))
+            fprintf(stderr, "[stag tune wilson] V=%d lps=%d: %.2f us\n", 2 * f->g.Vh, L, ms * 1e3 / 3);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    KernelCfg c;
+    c.lps = best;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    f->tuned[key] = c;
+    return best;
+}
+
 }  // namespace
+
+int wilson_dslash(Ctx *ctx, GaugeField *f, int out_parity, const double *in, double *out, hipStream_t s)
+{
+    const int lps = wilson_lps(ctx, f, nullptr, nullptr, s);
+    wilson_table(f->rows, lps).hop(f, out_parity == STAG_ALL ? -1 : out_parity, in, out, s);
+    STAG_HIP_CHECK(hipGetLastError());
+    return STAG_OK;
+}
 
 int wilson_cg_solve(Ctx *ctx, GaugeField *f, double kappa, double tol, int maxiter, const double *b, double *x,
                     hipStream_t s, stag_cg_info *info)
@@ -226,8 +301,9 @@ int wilson_cg_solve(Ctx *ctx, GaugeField *f, double kappa, double tol, int maxit
     const auto t0 = std::chrono::steady_clock::now();
     const Geom &g = f->g;
     const int Vh = g.Vh;
-    const int nblk = (Vh + kWBlock - 1) / kWBlock;
-    const int pstride = (nblk + 63) & ~63;
+    // partial sums sized for the most lanes per site (the most blocks)
+    const int nblk_max = (int)(((int64_t)Vh * 4 + kWBlock - 1) / kWBlock);
+    const int pstride = (nblk_max + 63) & ~63;
     const size_t vec = (size_t)12 * Vh * sizeof(dbl2);
     const size_t bytes = 6 * vec + 256 + (size_t)4 * pstride * sizeof(double);
     char *mem = (char *)ctx->arena.alloc(bytes);
@@ -264,7 +340,7 @@ int wilson_cg_solve(Ctx *ctx, GaugeField *f, double kappa, double tol, int maxit
 
     wil::WState *host = nullptr;
     STAG_HIP_CHECK(hipHostMalloc((void **)&host, 4 * sizeof(wil::WState), hipHostMallocDefault));
-    std::vector<double> hpart(2 * (size_t)nblk);
+    std::vector<double> hpart(2 * (size_t)nblk_max);
     hipEvent_t ev = nullptr;
     struct HostRelease {
         wil::WState *h;
@@ -284,18 +360,19 @@ int wilson_cg_solve(Ctx *ctx, GaugeField *f, double kappa, double tol, int maxit
     host[1] = host[0];
     STAG_HIP_CHECK(hipMemcpyAsync(a.st[0], host, 2 * sizeof(wil::WState), hipMemcpyHostToDevice, s));
 
-    const dim3 grid((unsigned)nblk);
-    auto init = f->rows == 2 ? WLaunch<2>::init : WLaunch<3>::init;
-    auto step = f->rows == 2 ? WLaunch<2>::step : WLaunch<3>::step;
-    auto finish = f->rows == 2 ? WLaunch<2>::finish : WLaunch<3>::finish;
-    init(a, grid, s);
+    // lanes per site: tuned on this workspace (bh|r and p[0]|p[1] are two
+    // adjacent full-field vectors) before the solve uses it
+    const int lps = wilson_lps(ctx, f, (const double *)a.bh, (double *)a.p[0], s);
+    const WTable &tab = wilson_table(f->rows, lps);
+    const int nblk = (int)(((int64_t)Vh * lps + kWBlock - 1) / kWBlock);
+    tab.init(a, s);
     STAG_HIP_CHECK(hipGetLastError());
     // epochs of E iterations; the state after epoch n is read while epoch n+1 runs
     const int E = 16;
     int64_t it = 0;
     auto epoch = [&]() {
         for (int k = 0; k < E; ++k, ++it)
-            step(a, grid, s, (int)(it & 1));
+            tab.step(a, s, (int)(it & 1));
     };
     auto snapshot = [&]() -> hipError_t {
         hipError_t e = hipMemcpyAsync(host + 2, a.st[0], 2 * sizeof(wil::WState), hipMemcpyDeviceToHost, s);
@@ -317,7 +394,7 @@ int wilson_cg_solve(Ctx *ctx, GaugeField *f, double kappa, double tol, int maxit
             STAG_HIP_CHECK(snapshot());
     }
     STAG_HIP_CHECK(hipMemcpyAsync(host + 2, a.st[0], 2 * sizeof(wil::WState), hipMemcpyDeviceToHost, s));
-    finish(a, grid, s);
+    tab.finish(a, s);
     STAG_HIP_CHECK(hipGetLastError());
     // |b - M x|^2 (slots 0 and 1 of buffer 0), then |b|^2 into buffer 1
     STAG_HIP_CHECK(hipMemcpyAsync(hpart.data(), a.partials, nblk * sizeof(double), hipMemcpyDeviceToHost, s));

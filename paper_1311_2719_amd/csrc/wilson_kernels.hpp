@@ -53,14 +53,14 @@ template <int C> __device__ __forceinline__ cplx<double> times(const cplx<double
         return {z.im, -z.re};
 }
 
+// z times the coefficient coded c, without branches (c may be a runtime value:
+// the coefficient is formed by selects, so the gathers around it are not split
+// into separate basic blocks that each wait for their loads)
 __device__ __forceinline__ cplx<double> times(int c, const cplx<double> &z)
 {
-    switch (c) {
-    case 0: return z;
-    case 1: return {-z.re, -z.im};
-    case 2: return {-z.im, z.re};
-    default: return {z.im, -z.re};
-    }
+    const double cr = c == 0 ? 1.0 : (c == 1 ? -1.0 : 0.0);
+    const double ci = c == 2 ? 1.0 : (c == 3 ? -1.0 : 0.0);
+    return {z.re * cr - z.im * ci, z.re * ci + z.im * cr};
 }
 
 // True when the t-boundary sign folded into Wilson link d of the site with
@@ -70,17 +70,22 @@ __device__ __forceinline__ bool wilson_link_negative(const Geom &g, const SiteCo
     return g.tap && (d & 3) == 3 && (d >= 4 ? c.t == 0 : c.t == g.L[3] - 1);
 }
 
-// acc[spin][colour] += (H psi)(s) for output site s of parity p_out.
+// acc[spin][colour] = (H psi)(s) for output site s of parity p_out, computed
+// by LPS lanes (sub = 0 .. LPS-1; lane sub takes directions sub, sub + LPS,
+// ...) and summed over them, so every lane of the site ends with the total.
 // load(n, sp, col) returns component (sp, col) of the input at site n of the
 // other parity (with gamma_5 or any fused combination applied by the caller).
-template <int ROWS, class Load>
-__device__ __forceinline__ void wilson_hop(const Geom &g, const dbl2 *__restrict__ links, int p_out, int s,
+template <int ROWS, int LPS, class Load>
+__device__ __forceinline__ void wilson_hop(const Geom &g, const dbl2 *__restrict__ links, int p_out, int s, int sub,
                                            cplx<double> (&acc)[4][3], Load load)
 {
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            acc[sp][a] = czero<double>();
     const SiteCoord c = decode_site(g, p_out, s);
-    // two directions per iteration: enough loads in flight without spilling
-#pragma unroll 2
-    for (int d = 0; d < 8; ++d) {
+    auto one_direction = [&](int d) {
         const Proj q = kProj[d];
         const int n = neighbour(g, c, s, d);
         cplx<double> U[9];
@@ -124,7 +129,30 @@ __device__ __forceinline__ void wilson_hop(const Geom &g, const dbl2 *__restrict
             acc[3][a].re += r3.re;
             acc[3][a].im += r3.im;
         }
+    };
+    if constexpr (LPS == 1) {
+        // two directions per iteration: enough loads in flight without spilling
+#pragma unroll 2
+        for (int d = 0; d < 8; ++d)
+            one_direction(d);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8 / LPS; ++j)
+            one_direction(sub + j * LPS);
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                acc[sp][a].re = lane_sum<LPS>(acc[sp][a].re);
+                acc[sp][a].im = lane_sum<LPS>(acc[sp][a].im);
+            }
     }
+}
+
+// Component k = 3 * spin + colour of the site is handled by lane k mod LPS.
+template <int LPS> __device__ __forceinline__ bool owns_component(int sub, int sp, int col)
+{
+    return ((sp * 3 + col) % LPS) == sub;
 }
 
 // Component (spin, colour) of a 12-plane parity vector at site n.
@@ -139,33 +167,37 @@ __device__ __forceinline__ void put(dbl2 *v, int Vh, int n, int sp, int col, con
     v[(int64_t)(sp * 3 + col) * Vh + n] = dbl2{z.re, z.im};
 }
 
+// Site and lane-within-site of this thread (LPS lanes per site, sub-major
+// within a wavefront), false for threads past the last site.
+template <int LPS> __device__ __forceinline__ bool wsite(int Vh, int &s, int &sub)
+{
+    site_of_thread<LPS>((int)(blockIdx.x * blockDim.x + threadIdx.x), s, sub);
+    return s < Vh;
+}
+
 // ---- the standalone hop: out_p = H_p in (one parity, or both with blockIdx.y) -------
 
-template <int ROWS>
+template <int ROWS, int LPS>
 __global__ void __launch_bounds__(128)
 k_wilson_dslash(Geom g, const dbl2 *__restrict__ links, const dbl2 *__restrict__ in, dbl2 *__restrict__ out,
                 int par_fixed)
 {
     const int p = par_fixed >= 0 ? par_fixed : (int)blockIdx.y;
     const int Vh = g.Vh;
-    const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (s >= Vh)
+    int s, sub;
+    if (!wsite<LPS>(Vh, s, sub))
         return;
     const dbl2 *src = in + (size_t)(1 - p) * 12 * Vh;
     cplx<double> acc[4][3];
-#pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-            acc[sp][a] = czero<double>();
-    wilson_hop<ROWS>(g, links + link_parity_entries(ROWS, Vh) * p, p, s, acc,
-                     [&](int n, int sp, int col) { return comp(src, Vh, n, sp, col); });
+    wilson_hop<ROWS, LPS>(g, links + link_parity_entries(ROWS, Vh) * p, p, s, sub, acc,
+                          [&](int n, int sp, int col) { return comp(src, Vh, n, sp, col); });
     dbl2 *o = out + (size_t)p * 12 * Vh;
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
         for (int a = 0; a < 3; ++a)
-            put(o, Vh, s, sp, a, acc[sp][a]);
+            if (owns_component<LPS>(sub, sp, a))
+                put(o, Vh, s, sp, a, acc[sp][a]);
 }
 
 // ---- even-odd CG ------------------------------------------------------------------
@@ -274,47 +306,39 @@ __device__ __forceinline__ double wuniform(double v)
 }
 
 // init 1 (even outputs): bh = b_e + kappa (H b)_e
-template <int ROWS> __global__ void __launch_bounds__(128) k_wil_bhat(WArgs a)
+template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_bhat(WArgs a)
 {
     const int Vh = a.g.Vh;
-    const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (s >= Vh)
+    int s, sub;
+    if (!wsite<LPS>(Vh, s, sub))
         return;
     const dbl2 *bo = a.b + (size_t)12 * Vh;
     cplx<double> acc[4][3];
+    wilson_hop<ROWS, LPS>(a.g, a.links[0], 0, s, sub, acc,
+                          [&](int n, int sp, int col) { return comp(bo, Vh, n, sp, col); });
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            acc[sp][c] = czero<double>();
-    wilson_hop<ROWS>(a.g, a.links[0], 0, s, acc, [&](int n, int sp, int col) { return comp(bo, Vh, n, sp, col); });
-#pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const cplx<double> be = comp(a.b, Vh, s, sp, c);
-            put(a.bh, Vh, s, sp, c, {be.re + a.kappa * acc[sp][c].re, be.im + a.kappa * acc[sp][c].im});
-        }
+            if (owns_component<LPS>(sub, sp, c)) {
+                const cplx<double> be = comp(a.b, Vh, s, sp, c);
+                put(a.bh, Vh, s, sp, c, {be.re + a.kappa * acc[sp][c].re, be.im + a.kappa * acc[sp][c].im});
+            }
 }
 
 // odd outputs: t = H_oe (gamma_5 src).  With a state (K3 of a step) it runs
 // only while the system iterates; without one (initialisation) always.
-template <int ROWS>
+template <int ROWS, int LPS>
 __global__ void __launch_bounds__(128) k_wil_odd_g5(WArgs a, const dbl2 *__restrict__ src, int ver, int check)
 {
     if (check && a.st[ver ^ 1]->mode != W_CG)
         return;
     const int Vh = a.g.Vh;
-    const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (s >= Vh)
+    int s, sub;
+    if (!wsite<LPS>(Vh, s, sub))
         return;
     cplx<double> acc[4][3];
-#pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            acc[sp][c] = czero<double>();
-    wilson_hop<ROWS>(a.g, a.links[1], 1, s, acc, [&](int n, int sp, int col) {
+    wilson_hop<ROWS, LPS>(a.g, a.links[1], 1, s, sub, acc, [&](int n, int sp, int col) {
         const cplx<double> z = comp(src, Vh, n, sp, col);
         return sp < 2 ? z : cplx<double>{-z.re, -z.im};
     });
@@ -322,30 +346,29 @@ __global__ void __launch_bounds__(128) k_wil_odd_g5(WArgs a, const dbl2 *__restr
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            put(a.t, Vh, s, sp, c, acc[sp][c]);
+            if (owns_component<LPS>(sub, sp, c))
+                put(a.t, Vh, s, sp, c, acc[sp][c]);
 }
 
 // init 3 (even outputs): r = bh - kappa^2 gamma_5 (H t)_e = Mhat^dagger bh;
 // p[0] = r; x_e = 0; <r,r> into slot 1 of buffer 0
-template <int ROWS> __global__ void __launch_bounds__(128) k_wil_init(WArgs a)
+template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_init(WArgs a)
 {
     __shared__ double lds[4];
     const int Vh = a.g.Vh;
-    const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    int s, sub;
     double nrm = 0.0;
-    if (s < Vh) {
+    if (wsite<LPS>(Vh, s, sub)) {
         cplx<double> acc[4][3];
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                acc[sp][c] = czero<double>();
-        wilson_hop<ROWS>(a.g, a.links[0], 0, s, acc, [&](int n, int sp, int col) { return comp(a.t, Vh, n, sp, col); });
+        wilson_hop<ROWS, LPS>(a.g, a.links[0], 0, s, sub, acc,
+                              [&](int n, int sp, int col) { return comp(a.t, Vh, n, sp, col); });
         const double k2 = a.kappa * a.kappa;
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
+                if (!owns_component<LPS>(sub, sp, c))
+                    continue;
                 const double g5 = sp < 2 ? k2 : -k2;
                 const cplx<double> bh = comp(a.bh, Vh, s, sp, c);
                 const cplx<double> r = {bh.re - g5 * acc[sp][c].re, bh.im - g5 * acc[sp][c].im};
@@ -361,7 +384,7 @@ template <int ROWS> __global__ void __launch_bounds__(128) k_wil_init(WArgs a)
 // K1 (odd outputs): advance the state over the previous step, then
 // t = H_oe p' with p' = r + beta p formed at every gathered neighbour; p' is
 // also stored at the partner site (same index, even parity).
-template <int ROWS> __global__ void __launch_bounds__(128) k_wil_step1(WArgs a, int ver)
+template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_step1(WArgs a, int ver)
 {
     __shared__ double lds[8];
     __shared__ __align__(16) WState sst;
@@ -427,16 +450,11 @@ template <int ROWS> __global__ void __launch_bounds__(128) k_wil_step1(WArgs a, 
     const int pn = wuniform(sst.pcur);
     const dbl2 *pold = a.p[pn ^ 1];
     dbl2 *pnew = a.p[pn];
-    const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (s >= Vh)
+    int s, sub;
+    if (!wsite<LPS>(Vh, s, sub))
         return;
     cplx<double> acc[4][3];
-#pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            acc[sp][c] = czero<double>();
-    wilson_hop<ROWS>(a.g, a.links[1], 1, s, acc, [&](int n, int sp, int col) {
+    wilson_hop<ROWS, LPS>(a.g, a.links[1], 1, s, sub, acc, [&](int n, int sp, int col) {
         const cplx<double> r = comp(a.r, Vh, n, sp, col), p = comp(pold, Vh, n, sp, col);
         return cplx<double>{fma(beta, p.re, r.re), fma(beta, p.im, r.im)};
     });
@@ -444,6 +462,8 @@ template <int ROWS> __global__ void __launch_bounds__(128) k_wil_step1(WArgs a, 
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
+            if (!owns_component<LPS>(sub, sp, c))
+                continue;
             put(a.t, Vh, s, sp, c, acc[sp][c]);
             const cplx<double> r = comp(a.r, Vh, s, sp, c), p = comp(pold, Vh, s, sp, c);
             put(pnew, Vh, s, sp, c, {fma(beta, p.re, r.re), fma(beta, p.im, r.im)});
@@ -452,7 +472,7 @@ template <int ROWS> __global__ void __launch_bounds__(128) k_wil_step1(WArgs a, 
 
 // K2 (even outputs): ap = p' - kappa^2 (H t)_e = Mhat p'; <ap,ap> into slot 0
 // of buffer ver^1
-template <int ROWS> __global__ void __launch_bounds__(128) k_wil_step2(WArgs a, int ver)
+template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_step2(WArgs a, int ver)
 {
     __shared__ double lds[4];
     const WState *st = a.st[ver ^ 1];
@@ -460,21 +480,19 @@ template <int ROWS> __global__ void __launch_bounds__(128) k_wil_step2(WArgs a, 
         return;
     const dbl2 *pn = a.p[wuniform(st->pcur)];
     const int Vh = a.g.Vh;
-    const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    int s, sub;
     double nrm = 0.0;
-    if (s < Vh) {
+    if (wsite<LPS>(Vh, s, sub)) {
         cplx<double> acc[4][3];
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                acc[sp][c] = czero<double>();
-        wilson_hop<ROWS>(a.g, a.links[0], 0, s, acc, [&](int n, int sp, int col) { return comp(a.t, Vh, n, sp, col); });
+        wilson_hop<ROWS, LPS>(a.g, a.links[0], 0, s, sub, acc,
+                              [&](int n, int sp, int col) { return comp(a.t, Vh, n, sp, col); });
         const double k2 = a.kappa * a.kappa;
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
+                if (!owns_component<LPS>(sub, sp, c))
+                    continue;
                 const cplx<double> p = comp(pn, Vh, s, sp, c);
                 const cplx<double> v = {p.re - k2 * acc[sp][c].re, p.im - k2 * acc[sp][c].im};
                 put(a.ap, Vh, s, sp, c, v);
@@ -487,7 +505,7 @@ template <int ROWS> __global__ void __launch_bounds__(128) k_wil_step2(WArgs a, 
 // K4 (even outputs): alpha = rr / <ap,ap>; atap = ap - kappa^2 gamma_5 (H t)_e
 // (= Mhat^dagger Mhat p'); x += alpha p'; r -= alpha atap; <r,r> into slot 1 of
 // buffer ver^1
-template <int ROWS> __global__ void __launch_bounds__(128) k_wil_step4(WArgs a, int ver)
+template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_step4(WArgs a, int ver)
 {
     __shared__ double lds[8];
     const WState *st = a.st[ver ^ 1];
@@ -500,21 +518,19 @@ template <int ROWS> __global__ void __launch_bounds__(128) k_wil_step4(WArgs a, 
     wtotals<1>(a, cur, gridDim.x, lds, tot);
     const double alpha = wfinite_pos(tot[0]) ? rr / tot[0] : 0.0;
     const int Vh = a.g.Vh;
-    const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    int s, sub;
     double nrm = 0.0;
-    if (s < Vh) {
+    if (wsite<LPS>(Vh, s, sub)) {
         cplx<double> acc[4][3];
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                acc[sp][c] = czero<double>();
-        wilson_hop<ROWS>(a.g, a.links[0], 0, s, acc, [&](int n, int sp, int col) { return comp(a.t, Vh, n, sp, col); });
+        wilson_hop<ROWS, LPS>(a.g, a.links[0], 0, s, sub, acc,
+                              [&](int n, int sp, int col) { return comp(a.t, Vh, n, sp, col); });
         const double k2 = a.kappa * a.kappa;
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
+                if (!owns_component<LPS>(sub, sp, c))
+                    continue;
                 const double g5 = sp < 2 ? k2 : -k2;
                 const cplx<double> ap = comp(a.ap, Vh, s, sp, c);
                 const cplx<double> atap = {ap.re - g5 * acc[sp][c].re, ap.im - g5 * acc[sp][c].im};
@@ -531,54 +547,48 @@ template <int ROWS> __global__ void __launch_bounds__(128) k_wil_step4(WArgs a, 
 }
 
 // x_o = b_o + kappa (H x_e)_o
-template <int ROWS> __global__ void __launch_bounds__(128) k_wil_xodd(WArgs a)
+template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_xodd(WArgs a)
 {
     const int Vh = a.g.Vh;
-    const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (s >= Vh)
+    int s, sub;
+    if (!wsite<LPS>(Vh, s, sub))
         return;
     cplx<double> acc[4][3];
-#pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            acc[sp][c] = czero<double>();
-    wilson_hop<ROWS>(a.g, a.links[1], 1, s, acc, [&](int n, int sp, int col) { return comp(a.x, Vh, n, sp, col); });
+    wilson_hop<ROWS, LPS>(a.g, a.links[1], 1, s, sub, acc,
+                          [&](int n, int sp, int col) { return comp(a.x, Vh, n, sp, col); });
     const dbl2 *bo = a.b + (size_t)12 * Vh;
     dbl2 *xo = a.x + (size_t)12 * Vh;
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const cplx<double> b = comp(bo, Vh, s, sp, c);
-            put(xo, Vh, s, sp, c, {b.re + a.kappa * acc[sp][c].re, b.im + a.kappa * acc[sp][c].im});
-        }
+        for (int c = 0; c < 3; ++c)
+            if (owns_component<LPS>(sub, sp, c)) {
+                const cplx<double> b = comp(bo, Vh, s, sp, c);
+                put(xo, Vh, s, sp, c, {b.re + a.kappa * acc[sp][c].re, b.im + a.kappa * acc[sp][c].im});
+            }
 }
 
 // |b - M x|^2 on the sites of parity `par`, per block into slot `par` of
 // buffer 0 (the solve is over when this runs)
-template <int ROWS> __global__ void __launch_bounds__(128) k_wil_resid(WArgs a, int par)
+template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_resid(WArgs a, int par)
 {
     __shared__ double lds[4];
     const int Vh = a.g.Vh;
-    const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    int s, sub;
     double nrm = 0.0;
-    if (s < Vh) {
+    if (wsite<LPS>(Vh, s, sub)) {
         const dbl2 *xin = a.x + (size_t)(1 - par) * 12 * Vh;
         cplx<double> acc[4][3];
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                acc[sp][c] = czero<double>();
-        wilson_hop<ROWS>(a.g, a.links[par], par, s, acc,
-                         [&](int n, int sp, int col) { return comp(xin, Vh, n, sp, col); });
+        wilson_hop<ROWS, LPS>(a.g, a.links[par], par, s, sub, acc,
+                              [&](int n, int sp, int col) { return comp(xin, Vh, n, sp, col); });
         const dbl2 *bp = a.b + (size_t)par * 12 * Vh;
         const dbl2 *xp = a.x + (size_t)par * 12 * Vh;
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
+                if (!owns_component<LPS>(sub, sp, c))
+                    continue;
                 const cplx<double> b = comp(bp, Vh, s, sp, c), x = comp(xp, Vh, s, sp, c);
                 const double re = b.re - x.re + a.kappa * acc[sp][c].re;
                 const double im = b.im - x.im + a.kappa * acc[sp][c].im;

@@ -198,3 +198,23 @@ def test_solve_edge_cases_and_errors(gpu_ctx):
     finally:
         gpu_ctx.free_gauge(f)
         gpu_ctx.free_gauge(fs)
+
+
+@pytest.mark.parametrize("lps", ["1", "2", "4"])
+def test_every_lanes_per_site(lps):
+    # the tuner may pick 1, 2 or 4 lanes per site for the Wilson kernels: each
+    # must give the same hop and the same solve
+    dims = (6, 4, 2, 10)
+    U = inputs.haar_su3(dims, 61)
+    psi = inputs.gaussian_spinor(dims, 62)
+    os.environ["STAG_WILSON_LPS"] = lps
+    try:
+        with binding.Context(device=0, arena_bytes=64 << 20) as ctx:
+            f = ctx.set_gauge_wilson(dims, U)
+            assert site_err(hop(ctx, f, psi), oracle.wilson_hop(dims, U, psi)) <= TOL
+            x, info = solve(ctx, f, psi, 0.11, tol=1e-10)
+            xr, oi = oracle.wilson_cg(dims, U, 0.11, psi, tol=1e-10)
+            assert info["status"] == 0 and abs(info["iters"] - oi["iters"]) <= 1
+            assert rel(x, xr) <= 1e-10
+    finally:
+        del os.environ["STAG_WILSON_LPS"]
