@@ -406,6 +406,13 @@ __global__ void __launch_bounds__(256) k_cg_step1(CgArgs a, int ver)
     for (int r = 0; r < 2 * R; ++r)
         nrm[r] = 0.0;
     const int64_t nthreads = (int64_t)Vh * LPS;
+    // systems the CG hop works for; with one system per tile it is the one
+    // system whenever the CG loop runs, known at compile time, so the hop's
+    // direction loop carries no per-system branch
+    bool act[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        act[r] = R == 1 ? true : cg[r];
     if (anycg) {
         for (int it = 0;; ++it) {
             const int64_t gt = round_base(it, a.remap);
@@ -434,7 +441,7 @@ __global__ void __launch_bounds__(256) k_cg_step1(CgArgs a, int ver)
                 }
             };
             hop_accumulate<P, LPS, R, decltype(load), false, ROWS>(a.g, (const typename P::link_t *)a.links[pout],
-                                                                   a.nbr[pout], pout, s, sub, cg, acc, load);
+                                                                   a.nbr[pout], pout, s, sub, act, acc, load);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 if (!cg[r])
@@ -601,6 +608,13 @@ __global__ void __launch_bounds__(256) k_cg_step2(CgArgs a, int ver)
     for (int r = 0; r < R; ++r)
         nrm[r] = 0.0;
     const int64_t nthreads = (int64_t)Vh * LPS;
+    // systems the CG hop works for; with one system per tile it is the one
+    // system whenever the CG loop runs, known at compile time, so the hop's
+    // direction loop carries no per-system branch
+    bool act[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        act[r] = R == 1 ? true : cg[r];
     if (anycg) {
         for (int it = 0;; ++it) {
             const int64_t gt = round_base(it, a.remap);
@@ -620,7 +634,7 @@ __global__ void __launch_bounds__(256) k_cg_step2(CgArgs a, int ver)
                 P::load_spinor(spin_at<P>(a.ap, js[r], Vh), Vh, n, chi);
             };
             hop_accumulate<P, LPS, R, decltype(load), false, ROWS>(a.g, (const typename P::link_t *)a.links[par],
-                                                                   a.nbr[par], par, s, sub, cg, acc, load);
+                                                                   a.nbr[par], par, s, sub, act, acc, load);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 if (!cg[r])

@@ -51,19 +51,23 @@ template <int LPS, typename T> __device__ __forceinline__ T lane_sum(T v)
 // time), for rarely taken paths that must not raise the register budget of
 // the kernel they live in.  ROWS = 3: all 9 link entries are stored; ROWS = 2:
 // rows 0 and 1 are stored and row 2 is rebuilt in registers.
-template <class P, int LPS, int R, class Load, bool LEAN = false, int ROWS = 3, int LEAN_UNROLL = 1>
-__device__ __forceinline__ void hop_accumulate(const Geom &g, const typename P::link_t *__restrict__ links,
-                                               const int32_t *__restrict__ nbr, int p_out, int s, int sub,
-                                               const bool *act, cplx<typename P::real> (*acc)[3], Load load)
+template <class P, int LPS, int R, class Load, bool LEAN, int ROWS, int LEAN_UNROLL, bool TABLES>
+__device__ __forceinline__ void hop_accumulate_impl(const Geom &g, const typename P::link_t *__restrict__ links,
+                                                    const int32_t *__restrict__ nbr, int p_out, int s, int sub,
+                                                    const bool *act, cplx<typename P::real> (*acc)[3], Load load)
 {
     using real = typename P::real;
     static_assert(ROWS == 2 || ROWS == 3, "links are stored with 2 or 3 rows");
     SiteCoord c;
-    if (!nbr || ROWS == 2)
+    if constexpr (!TABLES || ROWS == 2)
         c = decode_site(g, p_out, s);
     auto one_direction = [&](int j) {
         const int d = sub + j * LPS;
-        const int n = nbr ? nbr[(int64_t)d * g.Vh + s] : neighbour(g, c, s, d);
+        int n;
+        if constexpr (TABLES)
+            n = nbr[(int64_t)d * g.Vh + s];
+        else
+            n = neighbour(g, c, s, d);
         cplx<real> U[9];
         const typename P::link_t *lp = links + link_offset(g.Vh, d, 0, s);
 #pragma unroll
@@ -100,6 +104,23 @@ __device__ __forceinline__ void hop_accumulate(const Geom &g, const typename P::
             acc[r][a].re = lane_sum<LPS>(acc[r][a].re);
             acc[r][a].im = lane_sum<LPS>(acc[r][a].im);
         }
+}
+
+// The hop with the neighbour source (tables or coordinates) decided once,
+// outside the direction loop: a choice inside it would merge the table load
+// and the computed index into one register, and the wait for that load would
+// drain every load in flight at each direction.
+template <class P, int LPS, int R, class Load, bool LEAN = false, int ROWS = 3, int LEAN_UNROLL = 1>
+__device__ __forceinline__ void hop_accumulate(const Geom &g, const typename P::link_t *__restrict__ links,
+                                               const int32_t *__restrict__ nbr, int p_out, int s, int sub,
+                                               const bool *act, cplx<typename P::real> (*acc)[3], Load load)
+{
+    if (nbr)
+        hop_accumulate_impl<P, LPS, R, Load, LEAN, ROWS, LEAN_UNROLL, true>(g, links, nbr, p_out, s, sub, act, acc,
+                                                                             load);
+    else
+        hop_accumulate_impl<P, LPS, R, Load, LEAN, ROWS, LEAN_UNROLL, false>(g, links, nbr, p_out, s, sub, act, acc,
+                                                                              load);
 }
 
 // Colour c of an output site is written / reduced by lane (c mod LPS).
