@@ -180,10 +180,15 @@ __device__ __forceinline__ void load_prologue(const CgArgs &a, int pbuf, const S
         double buf[U][NS * R];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
+            // every load is in bounds (index 0 past the end): the guard is a
+            // select after the load, not a branch around it
             const int i = i0 + u * blockDim.x;
+            const bool in = i < nblk;
 #pragma unroll
-            for (int k = 0; k < NS * R; ++k)
-                buf[u][k] = (i < nblk && valid[k / NS]) ? base[k][i] : 0.0;
+            for (int k = 0; k < NS * R; ++k) {
+                const double v = base[k][in ? i : 0];
+                buf[u][k] = (in && valid[k / NS]) ? v : 0.0;
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)

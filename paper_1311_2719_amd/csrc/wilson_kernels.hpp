@@ -256,9 +256,12 @@ __device__ __forceinline__ void wtotals(const WArgs &a, int buf, int nblk, doubl
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int i = i0 + u * blockDim.x;
+            const bool in = i < nblk;
 #pragma unroll
-            for (int k = 0; k < NS; ++k)
-                q[u][k] = i < nblk ? wslot(a, buf, k)[i] : 0.0;
+            for (int k = 0; k < NS; ++k) {
+                const double v = wslot(a, buf, k)[in ? i : 0];  // in bounds; the guard selects
+                q[u][k] = in ? v : 0.0;
+            }
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
