@@ -102,33 +102,34 @@ __device__ __forceinline__ SiteCoord decode_site(const Geom &g, int p, int s)
 // preparation applies).
 __device__ __forceinline__ bool folded_negative(const Geom &g, const SiteCoord &c, int d)
 {
+    // every field is read before any choice is made, so the choices below
+    // select between values and never become a per-lane indexed memory access
+    const int cx = c.x, cy = c.y, cz = c.z, ct = c.t, tap = g.tap, Lt = g.L[3];
     const int mu = d & 3;
-    const int esum = (mu > 0 ? c.x : 0) + (mu > 1 ? c.y : 0) + (mu > 2 ? c.z : 0);
-    bool neg = (esum & 1) != 0;
-    if (d >= 4)
-        neg = !neg;
-    if (g.tap && mu == 3 && (d >= 4 ? c.t == 0 : c.t == g.L[3] - 1))
-        neg = !neg;
-    return neg;
+    const int esum = (mu > 0 ? cx : 0) + (mu > 1 ? cy : 0) + (mu > 2 ? cz : 0);
+    const bool back = d >= 4;
+    const bool wrap = tap && mu == 3 && (back ? ct == 0 : ct == Lt - 1);
+    return ((esum & 1) != 0) != (back != wrap);
 }
 
 // Checkerboard index (in the other parity) of neighbour d of site s:
-// d = 0..3 forward in x,y,z,t; d = 4..7 backward.  Written with selects only,
-// so lanes of one wavefront that take different directions do not diverge.
+// d = 0..3 forward in x,y,z,t; d = 4..7 backward.  Written with selects on
+// values only, so lanes of one wavefront that take different directions
+// neither diverge nor index memory by lane.
 __device__ __forceinline__ int neighbour(const Geom &g, const SiteCoord &c, int s, int d)
 {
+    const int cx = c.x, cy = c.y, cz = c.z, ct = c.t, base = c.base;
+    const int L0 = g.L[0], L1 = g.L[1], L2 = g.L[2], L3 = g.L[3], sy = g.sy, sz = g.sz, st_t = g.st;
     const int mu = d & 3;
     const bool fwd = d < 4;
-    if (mu == 0) {
-        const int xn = fwd ? (c.x + 1 == g.L[0] ? 0 : c.x + 1) : (c.x == 0 ? g.L[0] - 1 : c.x - 1);
-        return c.base + (xn >> 1);
-    }
-    const int co = mu == 1 ? c.y : (mu == 2 ? c.z : c.t);
-    const int L = mu == 1 ? g.L[1] : (mu == 2 ? g.L[2] : g.L[3]);
-    const int st = mu == 1 ? g.sy : (mu == 2 ? g.sz : g.st);
-    if (fwd)
-        return co + 1 == L ? s - (L - 1) * st : s + st;
-    return co == 0 ? s + (L - 1) * st : s - st;
+    const int xn = fwd ? (cx + 1 == L0 ? 0 : cx + 1) : (cx == 0 ? L0 - 1 : cx - 1);
+    const int nx = base + (xn >> 1);
+    const int co = mu == 1 ? cy : (mu == 2 ? cz : ct);
+    const int L = mu == 1 ? L1 : (mu == 2 ? L2 : L3);
+    const int st = mu == 1 ? sy : (mu == 2 ? sz : st_t);
+    const int nf = co + 1 == L ? s - (L - 1) * st : s + st;
+    const int nb = co == 0 ? s + (L - 1) * st : s - st;
+    return mu == 0 ? nx : (fwd ? nf : nb);
 }
 
 // ---- complex arithmetic in the compute type --------------------------------
