@@ -54,8 +54,9 @@ template <int C> __device__ __forceinline__ cplx<double> times(const cplx<double
 }
 
 // z times the coefficient coded c, without branches (c may be a runtime value:
-// the coefficient is formed by selects, so the gathers around it are not split
-// into separate basic blocks that each wait for their loads)
+// the coefficient is formed by selects of constants, and the product by
+// multiplications, so the gathers around it are not split into separate
+// basic blocks that each wait for their loads)
 __device__ __forceinline__ cplx<double> times(int c, const cplx<double> &z)
 {
     const double cr = c == 0 ? 1.0 : (c == 1 ? -1.0 : 0.0);
@@ -63,11 +64,40 @@ __device__ __forceinline__ cplx<double> times(int c, const cplx<double> &z)
     return {z.re * cr - z.im * ci, z.re * ci + z.im * cr};
 }
 
+// The projector of direction d, 4 bits per field, so that a lane-dependent
+// choice between directions is one select of a constant word.
+__host__ __device__ constexpr uint32_t pack_proj(const Proj &q)
+{
+    return (uint32_t)q.k0 | (uint32_t)q.a0 << 4 | (uint32_t)q.k1 << 8 | (uint32_t)q.a1 << 12 | (uint32_t)q.j2 << 16 |
+           (uint32_t)q.b2 << 20 | (uint32_t)q.j3 << 24 | (uint32_t)q.b3 << 28;
+}
+
+__device__ __forceinline__ Proj unpack_proj(uint32_t w)
+{
+    return {(int)(w & 15), (int)(w >> 4 & 15), (int)(w >> 8 & 15), (int)(w >> 12 & 15),
+            (int)(w >> 16 & 15), (int)(w >> 20 & 15), (int)(w >> 24 & 15), (int)(w >> 28)};
+}
+
+// Projector of direction j * LPS + sub.  The table is never read from memory:
+// with j known at compile time (unrolled loop) the word is chosen among the
+// LPS candidates of the lanes; with a runtime j (rolled loop, LPS = 1, the
+// same in every lane) among all eight.
+template <int LPS> __device__ __forceinline__ Proj proj_of(int j, int sub)
+{
+    const int d = j * LPS + sub;
+    uint32_t w = pack_proj(kProj[0]);
+#pragma unroll
+    for (int t = 1; t < 8; ++t)
+        w = d == t ? pack_proj(kProj[t]) : w;
+    return unpack_proj(w);
+}
+
 // True when the t-boundary sign folded into Wilson link d of the site with
 // coordinates c is negative.
 __device__ __forceinline__ bool wilson_link_negative(const Geom &g, const SiteCoord &c, int d)
 {
-    return g.tap && (d & 3) == 3 && (d >= 4 ? c.t == 0 : c.t == g.L[3] - 1);
+    const int ct = c.t, Lt = g.L[3], tap = g.tap;  // values first: the choice below is a select
+    return tap && (d & 3) == 3 && (d >= 4 ? ct == 0 : ct == Lt - 1);
 }
 
 // acc[spin][colour] = (H psi)(s) for output site s of parity p_out, computed
@@ -85,8 +115,9 @@ __device__ __forceinline__ void wilson_hop(const Geom &g, const dbl2 *__restrict
         for (int a = 0; a < 3; ++a)
             acc[sp][a] = czero<double>();
     const SiteCoord c = decode_site(g, p_out, s);
-    auto one_direction = [&](int d) {
-        const Proj q = kProj[d];
+    auto one_direction = [&](int j) {
+        const int d = sub + j * LPS;
+        const Proj q = proj_of<LPS>(j, sub);
         const int n = neighbour(g, c, s, d);
         cplx<double> U[9];
         const dbl2 *lp = links + link_offset(g.Vh, d, 0, s);
@@ -133,12 +164,12 @@ __device__ __forceinline__ void wilson_hop(const Geom &g, const dbl2 *__restrict
     if constexpr (LPS == 1) {
         // two directions per iteration: enough loads in flight without spilling
 #pragma unroll 2
-        for (int d = 0; d < 8; ++d)
-            one_direction(d);
+        for (int j = 0; j < 8; ++j)
+            one_direction(j);
     } else {
 #pragma unroll
         for (int j = 0; j < 8 / LPS; ++j)
-            one_direction(sub + j * LPS);
+            one_direction(j);
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
