@@ -350,6 +350,121 @@ __device__ __forceinline__ int64_t round_base(int it, int remap)
     return ((int64_t)it * gridDim.x + logical_block(blockIdx.x, gridDim.x, remap)) * blockDim.x + threadIdx.x;
 }
 
+// ---- own-site values of a step ------------------------------------------------------
+// The values a step kernel reads at its own site (not gathered) are loaded
+// before the hop when the tile holds at most two systems, so that their
+// latency overlaps the gathers instead of following them; with larger tiles
+// they are read where they are used (registers go to the gathers).  The
+// accessors return the value for system r and colour c either way.
+template <class P, int R, int LPS> struct OwnSite {
+    using real = typename P::real;
+    using v2 = typename vec2_of<real>::type;
+    using xv_t = typename std::conditional<P::id == 0, dbl2, flt2>::type;
+    static constexpr bool kPre = R <= 2;
+    static constexpr int N = kPre ? R : 1;
+    v2 pr_[N][3], rr_[N][3];
+    cplx<real> ps_[N][3];
+    xv_t xx_[N][3];
+
+    // K1: p (current buffer) and r at the partner site
+    template <class Args>
+    __device__ __forceinline__ void load_k1(const Args &a, const int *js, const bool *cg, const int *pc, int s, int sub)
+    {
+        if constexpr (kPre) {
+            const int Vh = a.g.Vh;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (!cg[r])
+                    continue;
+                const v2 *rv = (const v2 *)a.r + (size_t)js[r] * 3 * Vh;
+                const void *pold = spin_at<P>(a.p[pc[r]], js[r], Vh);
+                if constexpr (P::id == 2)
+                    P::load_spinor(pold, Vh, s, ps_[r]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if (P::id != 2 && !owns_colour<LPS>(sub, c))
+                        continue;
+                    rr_[r][c] = rv[(int64_t)c * Vh + s];
+                    if constexpr (P::id != 2)
+                        pr_[r][c] = ((const v2 *)pold)[(int64_t)c * Vh + s];
+                }
+            }
+        }
+    }
+    // K2: p' (new buffer), x and r at the own site
+    template <class Args>
+    __device__ __forceinline__ void load_k2(const Args &a, const int *js, const bool *cg, const int *pn, int s, int sub)
+    {
+        if constexpr (kPre) {
+            const int Vh = a.g.Vh;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (!cg[r])
+                    continue;
+                const int j = js[r];
+                const void *pb = spin_at<P>(a.p[pn[r]], j, Vh);
+                const v2 *rv = (const v2 *)a.r + (size_t)j * 3 * Vh;
+                if constexpr (P::id == 2)
+                    P::load_spinor(pb, Vh, s, ps_[r]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if (!owns_colour<LPS>(sub, c))
+                        continue;
+                    const int64_t o = (int64_t)c * Vh + s;
+                    if constexpr (P::id != 2)
+                        ps_[r][c] = load_colour<P>(pb, Vh, s, c);
+                    if constexpr (P::id == 0)
+                        xx_[r][c] = a.xhi[j][o];
+                    else
+                        xx_[r][c] = a.xlo[(size_t)j * 3 * Vh + o];
+                    rr_[r][c] = rv[o];
+                }
+            }
+        }
+    }
+    __device__ __forceinline__ v2 p(int r, int c, const v2 *pold, int Vh, int s) const
+    {
+        if constexpr (kPre)
+            return pr_[r][c];
+        else
+            return pold[(int64_t)c * Vh + s];
+    }
+    __device__ __forceinline__ v2 r(int r, int c, const v2 *rv, int Vh, int s) const
+    {
+        if constexpr (kPre)
+            return rr_[r][c];
+        else
+            return rv[(int64_t)c * Vh + s];
+    }
+    __device__ __forceinline__ void p_site(int r, const void *pold, int Vh, int s, cplx<real> (&out)[3]) const
+    {
+        if constexpr (kPre) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                out[c] = ps_[r][c];
+        } else {
+            P::load_spinor(pold, Vh, s, out);
+        }
+    }
+    __device__ __forceinline__ cplx<real> pc(int r, int c, const void *pb, int Vh, int s) const
+    {
+        if constexpr (kPre)
+            return ps_[r][c];
+        else
+            return load_colour<P>(pb, Vh, s, c);
+    }
+    template <class Args>
+    __device__ __forceinline__ xv_t x(int r, int c, const Args &a, int j, int Vh, int s) const
+    {
+        if constexpr (kPre)
+            return xx_[r][c];
+        else if constexpr (P::id == 0)
+            return a.xhi[j][(int64_t)c * Vh + s];
+        else
+            return a.xlo[(size_t)j * 3 * Vh + (int64_t)c * Vh + s];
+    }
+};
+
 // ---- K1 -----------------------------------------------------------------------------
 
 template <class P, int LPS, int R, int ROWS>
@@ -445,6 +560,10 @@ __global__ void __launch_bounds__(256) k_cg_step1(CgArgs a, int ver)
                     chi[c].im = fma(beta[r], pv[c].im, t.y);
                 }
             };
+            // the partner site's p and r (same index, parity par), loaded
+            // before the gathers so that their latency overlaps the hop
+            OwnSite<P, R, LPS> own;
+            own.load_k1(a, js, cg, pc, s, sub);
             hop_accumulate<P, LPS, R, decltype(load), false, ROWS>(a.g, (const typename P::link_t *)a.links[pout],
                                                                    a.nbr[pout], pout, s, sub, act, acc, load);
 #pragma unroll
@@ -461,10 +580,10 @@ __global__ void __launch_bounds__(256) k_cg_step1(CgArgs a, int ver)
                         P::store_spinor(out, Vh, s, acc[r]);
                         // the new direction at the partner site (same index, parity par)
                         cplx<real> pv[3];
-                        P::load_spinor(pold, Vh, s, pv);
+                        own.p_site(r, pold, Vh, s, pv);
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
-                            const v2 t = rv[(int64_t)c * Vh + s];
+                            const v2 t = own.r(r, c, rv, Vh, s);
                             pv[c].re = fma(beta[r], pv[c].re, t.x);
                             pv[c].im = fma(beta[r], pv[c].im, t.y);
                         }
@@ -481,8 +600,8 @@ __global__ void __launch_bounds__(256) k_cg_step1(CgArgs a, int ver)
                             continue;
                         const int64_t o = (int64_t)c * Vh + s;
                         ((v2 *)out)[o] = v2{acc[r][c].re, acc[r][c].im};
-                        const v2 po = ((const v2 *)pold)[o];
-                        const v2 t = rv[o];
+                        const v2 po = own.p(r, c, (const v2 *)pold, Vh, s);
+                        const v2 t = own.r(r, c, rv, Vh, s);
                         const v2 pn = v2{fma(beta[r], po.x, t.x), fma(beta[r], po.y, t.y)};
                         ((v2 *)pnew)[o] = pn;
                         nrm[R + r] += (double)pn.x * pn.x + (double)pn.y * pn.y;
@@ -638,6 +757,9 @@ __global__ void __launch_bounds__(256) k_cg_step2(CgArgs a, int ver)
             auto load = [&](int r, int n, cplx<real> *chi) {
                 P::load_spinor(spin_at<P>(a.ap, js[r], Vh), Vh, n, chi);
             };
+            // this site's p', x and r, loaded before the gathers
+            OwnSite<P, R, LPS> own;
+            own.load_k2(a, js, cg, pnew, s, sub);
             hop_accumulate<P, LPS, R, decltype(load), false, ROWS>(a.g, (const typename P::link_t *)a.links[par],
                                                                    a.nbr[par], par, s, sub, act, acc, load);
 #pragma unroll
@@ -651,20 +773,20 @@ __global__ void __launch_bounds__(256) k_cg_step2(CgArgs a, int ver)
                 for (int c = 0; c < 3; ++c) {
                     if (!owns_colour<LPS>(sub, c))
                         continue;
-                    const cplx<real> pv = load_colour<P>(pb, Vh, s, c);
+                    const cplx<real> pv = own.pc(r, c, pb, Vh, s);
                     const int64_t o = (int64_t)c * Vh + s;
                     if constexpr (P::id == 0) {
                         dbl2 *x = a.xhi[j];
-                        const dbl2 xv = x[o];
+                        const dbl2 xv = own.x(r, c, a, j, Vh, s);
                         x[o] = dbl2{fma(alpha[r], pv.re, xv.x), fma(alpha[r], pv.im, xv.y)};
                     } else {
                         flt2 *xl = a.xlo + (size_t)j * 3 * Vh;
-                        const flt2 xv = xl[o];
+                        const flt2 xv = own.x(r, c, a, j, Vh, s);
                         xl[o] = flt2{fmaf(alpha[r], pv.re, xv.x), fmaf(alpha[r], pv.im, xv.y)};
                     }
                     const real apr = m2[r] * pv.re - acc[r][c].re;
                     const real api = m2[r] * pv.im - acc[r][c].im;
-                    v2 rr = rv[o];
+                    v2 rr = own.r(r, c, rv, Vh, s);
                     rr.x = fma(-alpha[r], apr, rr.x);
                     rr.y = fma(-alpha[r], api, rr.y);
                     rv[o] = rr;
