@@ -352,116 +352,78 @@ __device__ __forceinline__ int64_t round_base(int it, int remap)
 
 // ---- own-site values of a step ------------------------------------------------------
 // The values a step kernel reads at its own site (not gathered) are loaded
-// before the hop when the tile holds at most two systems, so that their
-// latency overlaps the gathers instead of following them; with larger tiles
-// they are read where they are used (registers go to the gathers).  The
-// accessors return the value for system r and colour c either way.
+// in groups of G = 2 systems, all loads of a group before any use, so that a
+// group costs one memory round trip instead of one per system (a store of
+// one system cannot be passed by the next system's loads, which the compiler
+// must assume may alias it).  With at most two systems per tile the single
+// group is loaded before the hop, so its latency overlaps the gathers; larger
+// tiles load each group after the hop, when the gathers' registers are free.
+// Larger groups measured slower (the registers they hold lower occupancy).
 template <class P, int R, int LPS> struct OwnSite {
     using real = typename P::real;
     using v2 = typename vec2_of<real>::type;
     using xv_t = typename std::conditional<P::id == 0, dbl2, flt2>::type;
-    static constexpr bool kPre = R <= 2;
-    static constexpr int N = kPre ? R : 1;
-    v2 pr_[N][3], rr_[N][3];
-    cplx<real> ps_[N][3];
-    xv_t xx_[N][3];
+    static constexpr bool kBeforeHop = R <= 2;
+    static constexpr int G = R < 2 ? R : 2;  // systems per group
+    v2 pr_[G][3], rr_[G][3];
+    cplx<real> ps_[G][3];
+    xv_t xx_[G][3];
 
-    // K1: p (current buffer) and r at the partner site
+    // K1: p (current buffer) and r of systems r0 .. r0 + G - 1 at the partner site
     template <class Args>
-    __device__ __forceinline__ void load_k1(const Args &a, const int *js, const bool *cg, const int *pc, int s, int sub)
+    __device__ __forceinline__ void load_k1(const Args &a, const int *js, const bool *cg, const int *pc, int s,
+                                            int sub, int r0)
     {
-        if constexpr (kPre) {
-            const int Vh = a.g.Vh;
+        const int Vh = a.g.Vh;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (!cg[r])
+        for (int q = 0; q < G; ++q) {
+            const int r = r0 + q;
+            if (r >= R || !cg[r])
+                continue;
+            const v2 *rv = (const v2 *)a.r + (size_t)js[r] * 3 * Vh;
+            const void *pold = spin_at<P>(a.p[pc[r]], js[r], Vh);
+            if constexpr (P::id == 2)
+                P::load_spinor(pold, Vh, s, ps_[q]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (P::id != 2 && !owns_colour<LPS>(sub, c))
                     continue;
-                const v2 *rv = (const v2 *)a.r + (size_t)js[r] * 3 * Vh;
-                const void *pold = spin_at<P>(a.p[pc[r]], js[r], Vh);
-                if constexpr (P::id == 2)
-                    P::load_spinor(pold, Vh, s, ps_[r]);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    if (P::id != 2 && !owns_colour<LPS>(sub, c))
-                        continue;
-                    rr_[r][c] = rv[(int64_t)c * Vh + s];
-                    if constexpr (P::id != 2)
-                        pr_[r][c] = ((const v2 *)pold)[(int64_t)c * Vh + s];
-                }
+                rr_[q][c] = rv[(int64_t)c * Vh + s];
+                if constexpr (P::id != 2)
+                    pr_[q][c] = ((const v2 *)pold)[(int64_t)c * Vh + s];
             }
         }
     }
-    // K2: p' (new buffer), x and r at the own site
+    // K2: p' (new buffer), x and r of systems r0 .. r0 + G - 1 at the own site
     template <class Args>
-    __device__ __forceinline__ void load_k2(const Args &a, const int *js, const bool *cg, const int *pn, int s, int sub)
+    __device__ __forceinline__ void load_k2(const Args &a, const int *js, const bool *cg, const int *pn, int s,
+                                            int sub, int r0)
     {
-        if constexpr (kPre) {
-            const int Vh = a.g.Vh;
+        const int Vh = a.g.Vh;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (!cg[r])
+        for (int q = 0; q < G; ++q) {
+            const int r = r0 + q;
+            if (r >= R || !cg[r])
+                continue;
+            const int j = js[r];
+            const void *pb = spin_at<P>(a.p[pn[r]], j, Vh);
+            const v2 *rv = (const v2 *)a.r + (size_t)j * 3 * Vh;
+            if constexpr (P::id == 2)
+                P::load_spinor(pb, Vh, s, ps_[q]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (!owns_colour<LPS>(sub, c))
                     continue;
-                const int j = js[r];
-                const void *pb = spin_at<P>(a.p[pn[r]], j, Vh);
-                const v2 *rv = (const v2 *)a.r + (size_t)j * 3 * Vh;
-                if constexpr (P::id == 2)
-                    P::load_spinor(pb, Vh, s, ps_[r]);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    if (!owns_colour<LPS>(sub, c))
-                        continue;
-                    const int64_t o = (int64_t)c * Vh + s;
-                    if constexpr (P::id != 2)
-                        ps_[r][c] = load_colour<P>(pb, Vh, s, c);
-                    if constexpr (P::id == 0)
-                        xx_[r][c] = a.xhi[j][o];
-                    else
-                        xx_[r][c] = a.xlo[(size_t)j * 3 * Vh + o];
-                    rr_[r][c] = rv[o];
-                }
+                const int64_t o = (int64_t)c * Vh + s;
+                if constexpr (P::id != 2)
+                    ps_[q][c] = load_colour<P>(pb, Vh, s, c);
+                if constexpr (P::id == 0)
+                    xx_[q][c] = a.xhi[j][o];
+                else
+                    xx_[q][c] = a.xlo[(size_t)j * 3 * Vh + o];
+                rr_[q][c] = rv[o];
             }
         }
-    }
-    __device__ __forceinline__ v2 p(int r, int c, const v2 *pold, int Vh, int s) const
-    {
-        if constexpr (kPre)
-            return pr_[r][c];
-        else
-            return pold[(int64_t)c * Vh + s];
-    }
-    __device__ __forceinline__ v2 r(int r, int c, const v2 *rv, int Vh, int s) const
-    {
-        if constexpr (kPre)
-            return rr_[r][c];
-        else
-            return rv[(int64_t)c * Vh + s];
-    }
-    __device__ __forceinline__ void p_site(int r, const void *pold, int Vh, int s, cplx<real> (&out)[3]) const
-    {
-        if constexpr (kPre) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                out[c] = ps_[r][c];
-        } else {
-            P::load_spinor(pold, Vh, s, out);
-        }
-    }
-    __device__ __forceinline__ cplx<real> pc(int r, int c, const void *pb, int Vh, int s) const
-    {
-        if constexpr (kPre)
-            return ps_[r][c];
-        else
-            return load_colour<P>(pb, Vh, s, c);
-    }
-    template <class Args>
-    __device__ __forceinline__ xv_t x(int r, int c, const Args &a, int j, int Vh, int s) const
-    {
-        if constexpr (kPre)
-            return xx_[r][c];
-        else if constexpr (P::id == 0)
-            return a.xhi[j][(int64_t)c * Vh + s];
-        else
-            return a.xlo[(size_t)j * 3 * Vh + (int64_t)c * Vh + s];
     }
 };
 
@@ -526,13 +488,6 @@ __global__ void __launch_bounds__(256) k_cg_step1(CgArgs a, int ver)
     for (int r = 0; r < 2 * R; ++r)
         nrm[r] = 0.0;
     const int64_t nthreads = (int64_t)Vh * LPS;
-    // systems the CG hop works for; with one system per tile it is the one
-    // system whenever the CG loop runs, known at compile time, so the hop's
-    // direction loop carries no per-system branch
-    bool act[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-        act[r] = R == 1 ? true : cg[r];
     if (anycg) {
         for (int it = 0;; ++it) {
             const int64_t gt = round_base(it, a.remap);
@@ -560,57 +515,59 @@ __global__ void __launch_bounds__(256) k_cg_step1(CgArgs a, int ver)
                     chi[c].im = fma(beta[r], pv[c].im, t.y);
                 }
             };
-            // the partner site's p and r (same index, parity par), loaded
-            // before the gathers so that their latency overlaps the hop
-            OwnSite<P, R, LPS> own;
-            own.load_k1(a, js, cg, pc, s, sub);
+            // the partner site's p and r (same index, parity par)
+            using Own = OwnSite<P, R, LPS>;
+            Own own;
+            if constexpr (Own::kBeforeHop)
+                own.load_k1(a, js, cg, pc, s, sub, 0);
             hop_accumulate<P, LPS, R, decltype(load), false, ROWS>(a.g, (const typename P::link_t *)a.links[pout],
-                                                                   a.nbr[pout], pout, s, sub, act, acc, load);
+                                                                   a.nbr[pout], pout, s, sub, acc, load);
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (!cg[r])
-                    continue;
-                const int j = js[r];
-                void *out = spin_at<P>(a.ap, j, Vh);
-                const v2 *rv = (const v2 *)a.r + (size_t)j * 3 * Vh;
-                const void *pold = spin_at<P>(a.p[pc[r]], j, Vh);
-                void *pnew = spin_at<P>(a.p[pc[r] ^ 1], j, Vh);
-                if constexpr (P::id == 2) {
-                    if (sub == 0) {
-                        P::store_spinor(out, Vh, s, acc[r]);
-                        // the new direction at the partner site (same index, parity par)
-                        cplx<real> pv[3];
-                        own.p_site(r, pold, Vh, s, pv);
+            for (int g = 0; g < R; g += Own::G) {
+                if constexpr (!Own::kBeforeHop)
+                    own.load_k1(a, js, cg, pc, s, sub, g);
+#pragma unroll
+                for (int q = 0; q < Own::G; ++q) {
+                    const int r = g + q;
+                    if (r >= R || !cg[r])
+                        continue;
+                    const int j = js[r];
+                    void *out = spin_at<P>(a.ap, j, Vh);
+                    void *pnew = spin_at<P>(a.p[pc[r] ^ 1], j, Vh);
+                    if constexpr (P::id == 2) {
+                        if (sub == 0) {
+                            P::store_spinor(out, Vh, s, acc[r]);
+                            // the new direction at the partner site (same index, parity par)
+                            cplx<real> pv[3];
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) {
+                                const v2 t = own.rr_[q][c];
+                                pv[c].re = fma(beta[r], own.ps_[q][c].re, t.x);
+                                pv[c].im = fma(beta[r], own.ps_[q][c].im, t.y);
+                            }
+                            P::store_spinor_read_back(pnew, Vh, s, pv);  // pv: the value D will read
+#pragma unroll
+                            for (int c = 0; c < 3; ++c)
+                                nrm[R + r] += (double)pv[c].re * pv[c].re + (double)pv[c].im * pv[c].im;
+                        }
+                    } else {
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
-                            const v2 t = own.r(r, c, rv, Vh, s);
-                            pv[c].re = fma(beta[r], pv[c].re, t.x);
-                            pv[c].im = fma(beta[r], pv[c].im, t.y);
+                            if (!owns_colour<LPS>(sub, c))
+                                continue;
+                            const int64_t o = (int64_t)c * Vh + s;
+                            ((v2 *)out)[o] = v2{acc[r][c].re, acc[r][c].im};
+                            const v2 po = own.pr_[q][c], t = own.rr_[q][c];
+                            const v2 pn = v2{fma(beta[r], po.x, t.x), fma(beta[r], po.y, t.y)};
+                            ((v2 *)pnew)[o] = pn;
+                            nrm[R + r] += (double)pn.x * pn.x + (double)pn.y * pn.y;
                         }
-                        P::store_spinor(pnew, Vh, s, pv);
-                        P::load_spinor(pnew, Vh, s, pv);  // the norm of the value D will read
+                    }
+                    if (sub == 0) {
 #pragma unroll
                         for (int c = 0; c < 3; ++c)
-                            nrm[R + r] += (double)pv[c].re * pv[c].re + (double)pv[c].im * pv[c].im;
+                            nrm[r] += (double)acc[r][c].re * acc[r][c].re + (double)acc[r][c].im * acc[r][c].im;
                     }
-                } else {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        if (!owns_colour<LPS>(sub, c))
-                            continue;
-                        const int64_t o = (int64_t)c * Vh + s;
-                        ((v2 *)out)[o] = v2{acc[r][c].re, acc[r][c].im};
-                        const v2 po = own.p(r, c, (const v2 *)pold, Vh, s);
-                        const v2 t = own.r(r, c, rv, Vh, s);
-                        const v2 pn = v2{fma(beta[r], po.x, t.x), fma(beta[r], po.y, t.y)};
-                        ((v2 *)pnew)[o] = pn;
-                        nrm[R + r] += (double)pn.x * pn.x + (double)pn.y * pn.y;
-                    }
-                }
-                if (sub == 0) {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        nrm[r] += (double)acc[r][c].re * acc[r][c].re + (double)acc[r][c].im * acc[r][c].im;
                 }
             }
         }
@@ -632,7 +589,6 @@ __global__ void __launch_bounds__(256) k_cg_step1(CgArgs a, int ver)
                 const int j = js[r];
                 const dbl2 *xh = a.xhi[j];
                 const flt2 *xl = a.xlo ? a.xlo + (size_t)j * 3 * Vh : nullptr;
-                const bool one[1] = {true};
                 cplx<double> acc[1][3] = {{czero<double>(), czero<double>(), czero<double>()}};
                 auto load = [&](int, int n, cplx<double> *chi) {
 #pragma unroll
@@ -647,7 +603,7 @@ __global__ void __launch_bounds__(256) k_cg_step1(CgArgs a, int ver)
                     }
                 };
                 hop_accumulate<PrecF64, LPS, 1, decltype(load), true, ROWS, kRecomputeUnroll>(
-                    a.g, a.links64[pout], a.nbr[pout], pout, s, sub, one, acc, load);
+                    a.g, a.links64[pout], a.nbr[pout], pout, s, sub, acc, load);
                 dbl2 *t = a.tmp + (size_t)j * 3 * Vh;
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
@@ -732,13 +688,6 @@ __global__ void __launch_bounds__(256) k_cg_step2(CgArgs a, int ver)
     for (int r = 0; r < R; ++r)
         nrm[r] = 0.0;
     const int64_t nthreads = (int64_t)Vh * LPS;
-    // systems the CG hop works for; with one system per tile it is the one
-    // system whenever the CG loop runs, known at compile time, so the hop's
-    // direction loop carries no per-system branch
-    bool act[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-        act[r] = R == 1 ? true : cg[r];
     if (anycg) {
         for (int it = 0;; ++it) {
             const int64_t gt = round_base(it, a.remap);
@@ -757,40 +706,45 @@ __global__ void __launch_bounds__(256) k_cg_step2(CgArgs a, int ver)
             auto load = [&](int r, int n, cplx<real> *chi) {
                 P::load_spinor(spin_at<P>(a.ap, js[r], Vh), Vh, n, chi);
             };
-            // this site's p', x and r, loaded before the gathers
-            OwnSite<P, R, LPS> own;
-            own.load_k2(a, js, cg, pnew, s, sub);
+            // this site's p', x and r
+            using Own = OwnSite<P, R, LPS>;
+            Own own;
+            if constexpr (Own::kBeforeHop)
+                own.load_k2(a, js, cg, pnew, s, sub, 0);
             hop_accumulate<P, LPS, R, decltype(load), false, ROWS>(a.g, (const typename P::link_t *)a.links[par],
-                                                                   a.nbr[par], par, s, sub, act, acc, load);
+                                                                   a.nbr[par], par, s, sub, acc, load);
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (!cg[r])
-                    continue;
-                const int j = js[r];
-                const void *pb = spin_at<P>(a.p[pnew[r]], j, Vh);
-                v2 *rv = (v2 *)a.r + (size_t)j * 3 * Vh;
+            for (int g = 0; g < R; g += Own::G) {
+                if constexpr (!Own::kBeforeHop)
+                    own.load_k2(a, js, cg, pnew, s, sub, g);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    if (!owns_colour<LPS>(sub, c))
+                for (int q = 0; q < Own::G; ++q) {
+                    const int r = g + q;
+                    if (r >= R || !cg[r])
                         continue;
-                    const cplx<real> pv = own.pc(r, c, pb, Vh, s);
-                    const int64_t o = (int64_t)c * Vh + s;
-                    if constexpr (P::id == 0) {
-                        dbl2 *x = a.xhi[j];
-                        const dbl2 xv = own.x(r, c, a, j, Vh, s);
-                        x[o] = dbl2{fma(alpha[r], pv.re, xv.x), fma(alpha[r], pv.im, xv.y)};
-                    } else {
-                        flt2 *xl = a.xlo + (size_t)j * 3 * Vh;
-                        const flt2 xv = own.x(r, c, a, j, Vh, s);
-                        xl[o] = flt2{fmaf(alpha[r], pv.re, xv.x), fmaf(alpha[r], pv.im, xv.y)};
+                    const int j = js[r];
+                    v2 *rv = (v2 *)a.r + (size_t)j * 3 * Vh;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        if (!owns_colour<LPS>(sub, c))
+                            continue;
+                        const cplx<real> pv = own.ps_[q][c];
+                        const int64_t o = (int64_t)c * Vh + s;
+                        if constexpr (P::id == 0) {
+                            const dbl2 xv = own.xx_[q][c];
+                            a.xhi[j][o] = dbl2{fma(alpha[r], pv.re, xv.x), fma(alpha[r], pv.im, xv.y)};
+                        } else {
+                            const flt2 xv = own.xx_[q][c];
+                            a.xlo[(size_t)j * 3 * Vh + o] = flt2{fmaf(alpha[r], pv.re, xv.x), fmaf(alpha[r], pv.im, xv.y)};
+                        }
+                        const real apr = m2[r] * pv.re - acc[r][c].re;
+                        const real api = m2[r] * pv.im - acc[r][c].im;
+                        v2 rr = own.rr_[q][c];
+                        rr.x = fma(-alpha[r], apr, rr.x);
+                        rr.y = fma(-alpha[r], api, rr.y);
+                        rv[o] = rr;
+                        nrm[r] += (double)rr.x * rr.x + (double)rr.y * rr.y;
                     }
-                    const real apr = m2[r] * pv.re - acc[r][c].re;
-                    const real api = m2[r] * pv.im - acc[r][c].im;
-                    v2 rr = own.r(r, c, rv, Vh, s);
-                    rr.x = fma(-alpha[r], apr, rr.x);
-                    rr.y = fma(-alpha[r], api, rr.y);
-                    rv[o] = rr;
-                    nrm[r] += (double)rr.x * rr.x + (double)rr.y * rr.y;
                 }
             }
         }
@@ -811,11 +765,10 @@ __global__ void __launch_bounds__(256) k_cg_step2(CgArgs a, int ver)
                     continue;
                 const int j = js[r];
                 const dbl2 *t = a.tmp + (size_t)j * 3 * Vh;
-                const bool one[1] = {true};
                 cplx<double> acc[1][3] = {{czero<double>(), czero<double>(), czero<double>()}};
                 auto load = [&](int, int n, cplx<double> *chi) { PrecF64::load_spinor(t, Vh, n, chi); };
                 hop_accumulate<PrecF64, LPS, 1, decltype(load), true, ROWS, kRecomputeUnroll>(
-                    a.g, a.links64[par], a.nbr[par], par, s, sub, one, acc, load);
+                    a.g, a.links64[par], a.nbr[par], par, s, sub, acc, load);
                 const double m2d = uniform(sst[r].mass2);
                 dbl2 *x = a.xhi[j];
                 const dbl2 *b = a.b[j];
@@ -917,10 +870,6 @@ __global__ void __launch_bounds__(256) k_hop_probe(Geom g, const void *links, co
     const size_t vb = (size_t)Vh * P::spinor_bytes;
     const char *inb = (const char *)in + (size_t)blockIdx.y * R * vb;
     char *outb = (char *)out + (size_t)blockIdx.y * R * vb;
-    bool act[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-        act[r] = true;
     cplx<real> acc[R][3];
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -930,7 +879,7 @@ __global__ void __launch_bounds__(256) k_hop_probe(Geom g, const void *links, co
     auto load = [&](int r, int n, cplx<real> *chi) { P::load_spinor(inb + r * vb, Vh, n, chi); };
     const typename P::link_t *lk = (const typename P::link_t *)links + link_parity_entries(ROWS, Vh) * pout;
     hop_accumulate<P, LPS, R, decltype(load), false, ROWS>(g, lk, nbr ? nbr + (size_t)pout * 8 * Vh : nullptr, pout, s,
-                                                           sub, act, acc, load);
+                                                           sub, acc, load);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         void *o = outb + r * vb;

@@ -44,12 +44,11 @@ k_dslash64(Geom g, const dbl2 *__restrict__ links, const int32_t *__restrict__ n
         return;
     const int s = offset + site;
     const dbl2 *src = in + (size_t)(1 - p) * 3 * Vh;
-    const bool act[1] = {true};
     cplx<double> acc[1][3] = {{czero<double>(), czero<double>(), czero<double>()}};
     auto load = [&](int, int n, cplx<double> *chi) { PrecF64::load_spinor(src, Vh, n, chi); };
     hop_accumulate<PrecF64, LPS, 1, decltype(load), false, ROWS>(g, links + link_parity_entries(ROWS, Vh) * p,
                                                                  nbr ? nbr + (size_t)p * 8 * Vh : nullptr, p, s, sub,
-                                                                 act, acc, load);
+                                                                 acc, load);
     dbl2 *o = out + (size_t)p * 3 * Vh;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {

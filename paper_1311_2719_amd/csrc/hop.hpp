@@ -46,7 +46,11 @@ template <int LPS, typename T> __device__ __forceinline__ T lane_sum(T v)
 
 // acc[r][a] += sum over this lane's directions of L_d(s)[a][b] in_r(n_d(s))[b],
 // then summed over the LPS lanes of the site.  load(r, n, chi) fetches the
-// input colour vector of right-hand side r at neighbour site n.  LEAN keeps
+// input colour vector of right-hand side r at neighbour site n.  Every
+// right-hand side of the tile is computed, so load must stay in bounds for
+// each r; callers discard the sums of systems they do not update (a
+// per-system test inside the direction loop would split it into blocks that
+// each wait for their loads).  LEAN keeps
 // the direction loop rolled (LEAN_UNROLL directions' loads in flight at a
 // time), for rarely taken paths that must not raise the register budget of
 // the kernel they live in.  ROWS = 3: all 9 link entries are stored; ROWS = 2:
@@ -54,7 +58,7 @@ template <int LPS, typename T> __device__ __forceinline__ T lane_sum(T v)
 template <class P, int LPS, int R, class Load, bool LEAN, int ROWS, int LEAN_UNROLL, bool TABLES>
 __device__ __forceinline__ void hop_accumulate_impl(const Geom &g, const typename P::link_t *__restrict__ links,
                                                     const int32_t *__restrict__ nbr, int p_out, int s, int sub,
-                                                    const bool *act, cplx<typename P::real> (*acc)[3], Load load)
+                                                    cplx<typename P::real> (*acc)[3], Load load)
 {
     using real = typename P::real;
     static_assert(ROWS == 2 || ROWS == 3, "links are stored with 2 or 3 rows");
@@ -77,8 +81,6 @@ __device__ __forceinline__ void hop_accumulate_impl(const Geom &g, const typenam
             third_row(U, folded_negative(g, c, d) ? real(-2) : real(2));
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            if (!act[r])
-                continue;
             cplx<real> chi[3];
             load(r, n, chi);
 #pragma unroll
@@ -113,13 +115,13 @@ __device__ __forceinline__ void hop_accumulate_impl(const Geom &g, const typenam
 template <class P, int LPS, int R, class Load, bool LEAN = false, int ROWS = 3, int LEAN_UNROLL = 1>
 __device__ __forceinline__ void hop_accumulate(const Geom &g, const typename P::link_t *__restrict__ links,
                                                const int32_t *__restrict__ nbr, int p_out, int s, int sub,
-                                               const bool *act, cplx<typename P::real> (*acc)[3], Load load)
+                                               cplx<typename P::real> (*acc)[3], Load load)
 {
     if (nbr)
-        hop_accumulate_impl<P, LPS, R, Load, LEAN, ROWS, LEAN_UNROLL, true>(g, links, nbr, p_out, s, sub, act, acc,
+        hop_accumulate_impl<P, LPS, R, Load, LEAN, ROWS, LEAN_UNROLL, true>(g, links, nbr, p_out, s, sub, acc,
                                                                              load);
     else
-        hop_accumulate_impl<P, LPS, R, Load, LEAN, ROWS, LEAN_UNROLL, false>(g, links, nbr, p_out, s, sub, act, acc,
+        hop_accumulate_impl<P, LPS, R, Load, LEAN, ROWS, LEAN_UNROLL, false>(g, links, nbr, p_out, s, sub, acc,
                                                                               load);
 }
 

@@ -241,14 +241,13 @@ struct PrecF16 {
         hlf2 v = *p;
         return {(float)v.x, (float)v.y};
     }
-    static __device__ __forceinline__ void load_spinor(const void *base, int, int s, cplx<real> out[3])
+    static __device__ __forceinline__ void decode(const HalfSpinor &h, cplx<real> out[3])
     {
-        const HalfSpinor h = ((const HalfSpinor *)base)[s];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             out[c] = {(float)h.c[c].x * h.norm, (float)h.c[c].y * h.norm};
     }
-    static __device__ __forceinline__ void store_spinor(void *base, int, int s, const cplx<real> v[3])
+    static __device__ __forceinline__ HalfSpinor encode(const cplx<real> v[3])
     {
         float m = 0.f;
 #pragma unroll
@@ -260,9 +259,24 @@ struct PrecF16 {
         for (int c = 0; c < 3; ++c)
             h.c[c] = hlf2{(_Float16)(v[c].re * inv), (_Float16)(v[c].im * inv)};
         h.norm = m;
-        ((HalfSpinor *)base)[s] = h;
+        return h;
     }
-    // value as it will be read back after store_spinor (for norms of stored vectors)
+    static __device__ __forceinline__ void load_spinor(const void *base, int, int s, cplx<real> out[3])
+    {
+        decode(((const HalfSpinor *)base)[s], out);
+    }
+    static __device__ __forceinline__ void store_spinor(void *base, int, int s, const cplx<real> v[3])
+    {
+        ((HalfSpinor *)base)[s] = encode(v);
+    }
+    // store v and replace it by the value a later load_spinor returns
+    // (for norms of stored vectors, without reading the store back)
+    static __device__ __forceinline__ void store_spinor_read_back(void *base, int, int s, cplx<real> v[3])
+    {
+        const HalfSpinor h = encode(v);
+        ((HalfSpinor *)base)[s] = h;
+        decode(h, v);
+    }
     static constexpr size_t spinor_bytes = 16;
     static constexpr size_t link_bytes = 4;
 };
