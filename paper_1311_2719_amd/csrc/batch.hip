@@ -57,9 +57,10 @@ size_t Batch::workspace_bytes(const Geom &g, int prec, int slots, int pstride)
     return b;
 }
 
-// Blocks per tile row: enough to cover the sites once, capped so that the
-// partial sums every block reads back in the next kernel's prologue stay small
-// (the kernels stride over the sites when capped).
+// Blocks per tile row of shape c: enough to cover the sites once, capped so
+// that the partial sums every block reads back in the next kernel's prologue
+// stay small (the kernels stride over the sites when capped).  The tuned
+// shape's count becomes the batch's fixed count (nblk_).
 int Batch::grid_x(const KernelCfg &c) const
 {
     const int need = blocks_for(f_->g.Vh, c.lps, c.block);
@@ -125,11 +126,25 @@ int Batch::create()
             have = true;
         }
     }
-    if (!have) {
-        cfg_ = tune_cg();
+    auto small_key = [&](int R) {
+        return ((uint64_t)2 << 40) | ((uint64_t)prec_ << 32) | ((uint64_t)S_ << 8) | (uint64_t)R;
+    };
+    if (have) {
+        std::lock_guard<std::mutex> lk(ctx_->mu);
+        for (int R = 1; R < cfg_.rtile; ++R) {
+            auto it = f_->tuned.find(small_key(R));
+            if (it != f_->tuned.end())
+                small_.push_back(it->second);
+        }
+    } else {
+        cfg_ = tune_cg();  // also fills small_
         std::lock_guard<std::mutex> lk(ctx_->mu);
         f_->tuned[key] = cfg_;
+        for (const KernelCfg &c : small_)
+            f_->tuned[small_key(c.rtile)] = c;
     }
+    nblk_ = grid_x(cfg_);
+    live_ = S_;
     // every system starts idle, all systems listed
     STAG_HIP_CHECK(hipMemcpyAsync(st_d_[0], stage_, nsys * sizeof(SysState), hipMemcpyHostToDevice, s_));
     STAG_HIP_CHECK(hipMemcpyAsync(st_d_[1], stage_, nsys * sizeof(SysState), hipMemcpyHostToDevice, s_));
@@ -138,10 +153,12 @@ int Batch::create()
     STAG_HIP_CHECK(hipMemcpyAsync(perm_d_, perm_h_, nsys * sizeof(int), hipMemcpyHostToDevice, s_));
     STAG_HIP_CHECK(hipEventRecord(stage_ev_, s_));
     stage_busy_ = true;
-    // record the epochs the solve driver chooses from (powers of two) now,
-    // outside any solve
+    // record the epochs the solve driver chooses from (powers of two), for
+    // every tile shape, now, outside any solve
     for (int E = 2; use_graphs_ && E <= kEpochMax; E *= 2) {
-        int rc = record_epoch(E);
+        int rc = record_epoch(E, cfg_);
+        for (size_t i = 0; i < small_.size() && rc == STAG_OK; ++i)
+            rc = record_epoch(E, small_[i]);
         if (rc != STAG_OK)
             return rc;
     }
@@ -152,11 +169,13 @@ int Batch::set_running(const std::vector<char> &running)
 {
     const int n = nsys();
     std::vector<int> order(n, -1);
+    live_ = 0;
     for (int par = 0; par < 2; ++par) {
         int k = par * S_;
         for (int i = 0; i < S_; ++i)
             if (running[par * S_ + i])
                 order[k++] = par * S_ + i;
+        live_ = std::max(live_, k - par * S_);
     }
     if (order == perm_last_)
         return STAG_OK;
@@ -173,14 +192,14 @@ int Batch::set_running(const std::vector<char> &running)
 }
 
 // Time K1 + K2 of one step with every system in a CG step on filled vectors.
-double Batch::time_cg_config(const KernelCfg &c)
+double Batch::time_cg_config(const KernelCfg &c, int nblk)
 {
     const CgLaunchTable &t = cg_table(prec_, f_->rows);
     CgArgs a = args();
     for (int par = 0; par < 2; ++par)
         a.nbr[par] = c.tables ? f_->nbr_for(par) : nullptr;
     a.remap = c.remap;
-    dim3 grid((unsigned)grid_x(c), (unsigned)(nsys() / c.rtile)), blk(c.block);
+    dim3 grid((unsigned)nblk, (unsigned)(nsys() / c.rtile)), blk(c.block);
     if (t.step1(c.lps, c.rtile, grid, blk, s_, a, 0) != hipSuccess ||
         t.step2(c.lps, c.rtile, grid, blk, s_, a, 0) != hipSuccess)
         return 1e30;
@@ -264,7 +283,7 @@ KernelCfg Batch::tune_cg()
                 c.rtile = R;
                 c.tables = 0;
                 c.remap = 1;
-                const double ms = time_cg_config(c);
+                const double ms = time_cg_config(c, grid_x(c));
                 if (verbose)
                     fprintf(stderr, "[stag tune cg] V=%d prec=%d slots=%d lps=%d block=%d rtile=%d: %.2f us\n",
                             2 * f_->g.Vh, prec_, S_, L, B, R, ms * 1e3);
@@ -279,7 +298,7 @@ KernelCfg Batch::tune_cg()
             KernelCfg c = best;
             c.tables = T;
             c.remap = X;
-            const double ms = time_cg_config(c);
+            const double ms = time_cg_config(c, grid_x(c));
             if (verbose)
                 fprintf(stderr, "[stag tune cg] V=%d prec=%d slots=%d lps=%d block=%d rtile=%d tables=%d remap=%d: "
                                 "%.2f us\n", 2 * f_->g.Vh, prec_, S_, c.lps, c.block, c.rtile, T, X, ms * 1e3);
@@ -288,6 +307,35 @@ KernelCfg Batch::tune_cg()
                 best = c;
             }
         }
+    // Smaller tiles, for when fewer systems run than the tuned tile takes: a
+    // tile's empty places still gather (they read the first system's values),
+    // so a lone system in a large tile pays for the whole tile.  Each is tuned
+    // at the tuned shape's block count, which every kernel of the batch keeps.
+    const int nblk = grid_x(best);
+    small_.clear();
+    for (int i = 0; i < t.n_rtiles; ++i) {
+        const int R = t.rtiles[i];
+        if (R >= best.rtile || S_ % R)
+            continue;
+        KernelCfg sb;
+        double sb_t = 1e30;
+        for (int L : lps_c)
+            for (int B : blk_c) {
+                KernelCfg c = best;
+                c.lps = L;
+                c.block = B;
+                c.rtile = R;
+                const double ms = time_cg_config(c, nblk);
+                if (verbose)
+                    fprintf(stderr, "[stag tune cg] small tile: V=%d prec=%d slots=%d lps=%d block=%d rtile=%d "
+                                    "blocks=%d: %.2f us\n", 2 * f_->g.Vh, prec_, S_, L, B, R, nblk, ms * 1e3);
+                if (ms < sb_t * 0.99) {
+                    sb_t = ms;
+                    sb = c;
+                }
+            }
+        small_.push_back(sb);
+    }
     (void)hipStreamSynchronize(s_);
     (void)hipGetLastError();
     return best;
@@ -332,7 +380,7 @@ int Batch::upload_and_init(const std::vector<int> &systems)
     stage_busy_ = true;
     const CgArgs a = args();
     const CgLaunchTable &t = cg_table(prec_, f_->rows);
-    dim3 grid((unsigned)grid_x(cfg_), (unsigned)nsys());
+    dim3 grid((unsigned)nblk_, (unsigned)nsys());
     hipError_t e = t.init(grid, dim3(cfg_.block), s_, a, cfg_.lps);
     if (e != hipSuccess)
         return set_error(STAG_EHIP, "init launch failed: %s", hipGetErrorString(e));
@@ -367,30 +415,31 @@ CgArgs Batch::args() const
     return a;
 }
 
-int Batch::launch_step(int ver, hipStream_t st)
+int Batch::launch_step(int ver, hipStream_t st, const KernelCfg &c)
 {
     const CgLaunchTable &t = cg_table(prec_, f_->rows);
     const CgArgs a = args();
-    const int R = cfg_.rtile;
-    dim3 grid((unsigned)grid_x(cfg_), (unsigned)(nsys() / R)), blk(cfg_.block);
-    hipError_t e = t.step1(cfg_.lps, R, grid, blk, st, a, ver);
+    const int R = c.rtile;
+    dim3 grid((unsigned)nblk_, (unsigned)(nsys() / R)), blk(c.block);
+    hipError_t e = t.step1(c.lps, R, grid, blk, st, a, ver);
     if (e == hipSuccess)
-        e = t.step2(cfg_.lps, R, grid, blk, st, a, ver);
+        e = t.step2(c.lps, R, grid, blk, st, a, ver);
     if (e != hipSuccess)
         return set_error(STAG_EHIP, "CG kernel launch failed: %s", hipGetErrorString(e));
     return STAG_OK;
 }
 
-int Batch::record_epoch(int steps)
+int Batch::record_epoch(int steps, const KernelCfg &c)
 {
-    if (graphs_.count(steps))
+    const int key = c.rtile * 1024 + steps;
+    if (graphs_.count(key))
         return STAG_OK;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     STAG_HIP_CHECK(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
     int rc = STAG_OK;
     for (int k = 0; k < steps && rc == STAG_OK; ++k)
-        rc = launch_step(k & 1, cap_stream_);
+        rc = launch_step(k & 1, cap_stream_, c);
     hipError_t e = hipStreamEndCapture(cap_stream_, &graph);
     if (rc != STAG_OK) {
         if (graph)
@@ -403,16 +452,25 @@ int Batch::record_epoch(int steps)
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess)
         return set_error(STAG_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
-    graphs_.emplace(steps, exec);
+    graphs_.emplace(key, exec);
     return STAG_OK;
+}
+
+const KernelCfg &Batch::epoch_cfg() const
+{
+    for (const KernelCfg &c : small_)
+        if (c.rtile >= live_)
+            return c;
+    return cfg_;
 }
 
 int Batch::enqueue_epoch(int steps)
 {
     steps += steps & 1;
+    const KernelCfg &c = epoch_cfg();
     if (!use_graphs_) {
         for (int k = 0; k < steps; ++k) {
-            int rc = launch_step(k & 1, s_);
+            int rc = launch_step(k & 1, s_, c);
             if (rc != STAG_OK)
                 return rc;
         }
@@ -421,10 +479,10 @@ int Batch::enqueue_epoch(int steps)
     // The kernel arguments of an epoch depend only on this workspace, so an
     // epoch of a given length is recorded once and replayed: the launches of
     // all its kernels cost one graph launch on the host.
-    int rc = record_epoch(steps);
+    int rc = record_epoch(steps, c);
     if (rc != STAG_OK)
         return rc;
-    auto it = graphs_.find(steps);
+    auto it = graphs_.find(c.rtile * 1024 + steps);
     STAG_HIP_CHECK(hipGraphLaunch(it->second, s_));
     return STAG_OK;
 }
@@ -628,6 +686,7 @@ int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs, con
     } drain{s};
     const size_t half = (size_t)3 * f->g.Vh * 2;  // doubles per parity half
     std::vector<int> systems;
+    std::vector<char> running(B.nsys(), 0);
     int max_iter = 0;
     for (int i = 0; i < nrhs; ++i) {
         max_iter = std::max(max_iter, params[i].maxiter);
@@ -636,9 +695,11 @@ int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs, con
             const bool on = params[i].parity == STAG_ALL || params[i].parity == par;
             B.stage_system(j, params[i], on ? b[i] + par * half : nullptr, on ? x[i] + par * half : nullptr);
             systems.push_back(j);
+            running[j] = on;
         }
     }
-    if ((rc = B.upload_and_init(systems)) != STAG_OK)
+    // a workspace taken from the cache keeps the tile order of its last solve
+    if ((rc = B.upload_and_init(systems)) != STAG_OK || (rc = B.set_running(running)) != STAG_OK)
         return rc;
     int E = 8, Emax = kEpochMax;
     const bool fixed_epoch = getenv("STAG_EPOCH") != nullptr;
@@ -665,7 +726,7 @@ int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs, con
                 done = false;
         }
         if (!done) {
-            std::vector<char> running(B.nsys());
+            running.assign(B.nsys(), 0);
             for (int j = 0; j < B.nsys(); ++j)
                 running[j] = B.state(j).mode == M_INIT || B.state(j).mode == M_CG || B.state(j).mode == M_RU;
             if ((rc = B.set_running(running)) != STAG_OK)

@@ -38,10 +38,11 @@ public:
     // Copy staged systems [j0, j0 + n) to the device and run the init kernel.
     int upload_and_init(const std::vector<int> &systems);
     // Enqueue `steps` CG steps (rounded up to an even number, so that every
-    // epoch starts from state buffer 0).
+    // epoch starts from state buffer 0), with the tile shape for the number of
+    // running systems given to the last set_running.
     int enqueue_epoch(int steps);
-    // Record (once) the graph of an epoch of `steps` steps.
-    int record_epoch(int steps);
+    // Record (once) the graph of an epoch of `steps` steps with shape c.
+    int record_epoch(int steps, const KernelCfg &c);
     // Enqueue a copy of the device state into the host snapshot and record an
     // event; wait_snapshot blocks until it has arrived.
     int enqueue_snapshot();
@@ -57,12 +58,16 @@ public:
     // `running` first (per parity), the rest left out.  Stream-ordered: applies
     // to the kernels enqueued after this call.
     int set_running(const std::vector<char> &running);
+    // Tile shape of the next epoch: the tuned shape, or while fewer systems
+    // run per parity than it takes, the smallest tuned tile that holds them.
+    const KernelCfg &epoch_cfg() const;
 
 private:
-    int launch_step(int ver, hipStream_t st);
+    int launch_step(int ver, hipStream_t st, const KernelCfg &c);
     int grid_x(const KernelCfg &c) const;
+    // Tune the tile shape on this workspace; also fills small_.
     KernelCfg tune_cg();
-    double time_cg_config(const KernelCfg &c);
+    double time_cg_config(const KernelCfg &c, int nblk);
     CgArgs args() const;
 
     Ctx *ctx_;
@@ -70,6 +75,13 @@ private:
     int prec_, S_;
     hipStream_t s_;
     KernelCfg cfg_;
+    // tuned shapes of tiles smaller than cfg_.rtile, ascending
+    std::vector<KernelCfg> small_;
+    // blocks per tile row of every kernel of this batch: a prologue reduces
+    // one partial sum per block of the kernel before it, so the count never
+    // changes between shapes
+    int nblk_ = 0;
+    int live_ = 0;  // running systems per parity (the larger count), from set_running
     int pstride_ = 0;
     void *mem_ = nullptr;
     size_t bytes_ = 0;
@@ -95,7 +107,7 @@ private:
     // epochs recorded once as HIP graphs (kernel nodes only) and replayed
     bool use_graphs_ = true;
     hipStream_t cap_stream_ = nullptr;
-    std::map<int, hipGraphExec_t> graphs_;
+    std::map<int, hipGraphExec_t> graphs_;  // key: rtile * 1024 + steps
 };
 
 }  // namespace stag
