@@ -54,18 +54,57 @@ size_t Batch::workspace_bytes(const Geom &g, int prec, int slots, int pstride)
     b += align256(nsys * sizeof(SysState)) * 2;                  // two state buffers
     b += align256(nsys * sizeof(int));                           // tile order
     b += align256(2 * nsys * 3 * (size_t)pstride * sizeof(double));  // partials
+    b += align256(2 * nsys * 3 * sizeof(double));                    // their totals
     return b;
 }
 
-// Blocks per tile row of shape c: enough to cover the sites once, capped so
-// that the partial sums every block reads back in the next kernel's prologue
-// stay small (the kernels stride over the sites when capped).  The tuned
+// Blocks per tile row of shape c: enough to cover the sites once (the
+// kernels stride over the sites when capped).  Without a reduction kernel the
+// count is capped so that the partial sums every block reads back in the next
+// kernel's prologue stay few; with one, only by the partial buffer.  The tuned
 // shape's count becomes the batch's fixed count (nblk_).
 int Batch::grid_x(const KernelCfg &c) const
 {
     const int need = blocks_for(f_->g.Vh, c.lps, c.block);
-    const int cap = std::max(128, 2048 / c.rtile);
-    return std::min(need, cap);
+    if (uses_reduction(c))
+        return std::min(need, pstride_);
+    return std::min(need, std::max(128, 2048 / c.rtile));
+}
+
+// A reduction kernel between the step kernels pays for itself once every
+// prologue would otherwise sum about a thousand partials per slot set (its
+// cost: one small launch after each step kernel).
+bool Batch::uses_reduction(const KernelCfg &c) const
+{
+    if (const char *e = getenv("STAG_CG_REDUCE"))  // "1": always, "0": never (tests, experiments)
+        if (e[0] == '0' || e[0] == '1')
+            return e[0] == '1';
+    const int need = blocks_for(f_->g.Vh, c.lps, c.block);
+    const int fused = std::min(need, std::max(128, 2048 / c.rtile));
+    return (int64_t)fused * c.rtile >= 1024;
+}
+
+namespace {
+// Total of the per-block partials [0, nblk) of slot slot0 + blockIdx.y of
+// partial buffer buf, system blockIdx.x, in a fixed order, into that slot's
+// entry of `totals` ([2 buffers][nsys][3 slots]).  Partials are only read, so
+// running it again over unchanged partials gives the same totals.
+__global__ void __launch_bounds__(256) k_cg_reduce(const double *partials, double *totals, int nsys, int pstride,
+                                                   int buf, int slot0, int nblk)
+{
+    __shared__ double lds[4];
+    const size_t k = ((size_t)buf * nsys + blockIdx.x) * 3 + slot0 + blockIdx.y;
+    const double t = reduce_partials(partials + k * pstride, nblk, lds);
+    if (threadIdx.x == 0)
+        totals[k] = t;
+}
+}  // namespace
+
+hipError_t Batch::launch_reduce(hipStream_t st, int buf, int slot0, int nslots, int nblk) const
+{
+    hipLaunchKernelGGL(k_cg_reduce, dim3((unsigned)nsys(), (unsigned)nslots), dim3(256), 0, st, partials_, totals_,
+                       nsys(), pstride_, buf, slot0, nblk);
+    return hipGetLastError();
 }
 
 int Batch::create()
@@ -98,6 +137,7 @@ int Batch::create()
     st_d_[1] = st_d_[0] ? st_d_[0] + nsys : nullptr;
     perm_d_ = (int *)take(nsys * sizeof(int));
     partials_ = (double *)take(2 * nsys * 3 * (size_t)pstride_ * sizeof(double));
+    totals_ = (double *)take(2 * nsys * 3 * sizeof(double));
 
     const size_t host_bytes = 3 * nsys * sizeof(SysState) + 2 * nsys * sizeof(void *) + nsys * sizeof(int);
     STAG_HIP_CHECK(hipHostMalloc((void **)&stage_, host_bytes, hipHostMallocDefault));
@@ -144,6 +184,7 @@ int Batch::create()
             f_->tuned[small_key(c.rtile)] = c;
     }
     nblk_ = grid_x(cfg_);
+    reduce_ = uses_reduction(cfg_);
     live_ = S_;
     // every system starts idle, all systems listed
     STAG_HIP_CHECK(hipMemcpyAsync(st_d_[0], stage_, nsys * sizeof(SysState), hipMemcpyHostToDevice, s_));
@@ -192,16 +233,28 @@ int Batch::set_running(const std::vector<char> &running)
 }
 
 // Time K1 + K2 of one step with every system in a CG step on filled vectors.
-double Batch::time_cg_config(const KernelCfg &c, int nblk)
+double Batch::time_cg_config(const KernelCfg &c, int nblk, bool reduce)
 {
     const CgLaunchTable &t = cg_table(prec_, f_->rows);
     CgArgs a = args();
     for (int par = 0; par < 2; ++par)
         a.nbr[par] = c.tables ? f_->nbr_for(par) : nullptr;
     a.remap = c.remap;
+    a.psum = reduce ? totals_ : partials_;
+    a.psum_stride = reduce ? 1 : pstride_;
+    a.nread = reduce ? 1 : nblk;
     dim3 grid((unsigned)nblk, (unsigned)(nsys() / c.rtile)), blk(c.block);
-    if (t.step1(c.lps, c.rtile, grid, blk, s_, a, 0) != hipSuccess ||
-        t.step2(c.lps, c.rtile, grid, blk, s_, a, 0) != hipSuccess)
+    auto step = [&]() {
+        hipError_t e = t.step1(c.lps, c.rtile, grid, blk, s_, a, 0);
+        if (e == hipSuccess && reduce)
+            e = launch_reduce(s_, 1, 0, 2, nblk);
+        if (e == hipSuccess)
+            e = t.step2(c.lps, c.rtile, grid, blk, s_, a, 0);
+        if (e == hipSuccess && reduce)
+            e = launch_reduce(s_, 1, 2, 1, nblk);
+        return e;
+    };
+    if (step() != hipSuccess)
         return 1e30;
     // the faster of two runs of 5 steps: single short runs vary by more than
     // the differences between the leading shapes
@@ -209,10 +262,8 @@ double Batch::time_cg_config(const KernelCfg &c, int nblk)
     double best = 1e30;
     for (int run = 0; run < 2; ++run) {
         (void)hipEventRecord(tune_ev_[0], s_);
-        for (int i = 0; i < reps; ++i) {
-            (void)t.step1(c.lps, c.rtile, grid, blk, s_, a, 0);
-            (void)t.step2(c.lps, c.rtile, grid, blk, s_, a, 0);
-        }
+        for (int i = 0; i < reps; ++i)
+            (void)step();
         (void)hipEventRecord(tune_ev_[1], s_);
         if (hipEventSynchronize(tune_ev_[1]) != hipSuccess)
             return 1e30;
@@ -271,6 +322,7 @@ KernelCfg Batch::tune_cg()
         hipMemcpyAsync(perm_d_, perm_h_, nsys * sizeof(int), hipMemcpyHostToDevice, s_) != hipSuccess ||
         hipMemsetAsync(p_[0], 0x3f, vec_bytes, s_) != hipSuccess ||
         hipMemsetAsync(partials_, 0x3f, 2 * nsys * 3 * (size_t)pstride_ * sizeof(double), s_) != hipSuccess ||
+        hipMemsetAsync(totals_, 0x3f, 2 * nsys * 3 * sizeof(double), s_) != hipSuccess ||
         hipEventCreate(&tune_ev_[0]) != hipSuccess || hipEventCreate(&tune_ev_[1]) != hipSuccess) {
         (void)hipStreamSynchronize(s_);
         return best;
@@ -289,7 +341,7 @@ KernelCfg Batch::tune_cg()
                 c.rtile = R;
                 c.tables = 0;
                 c.remap = 1;
-                const double ms = time_cg_config(c, grid_x(c));
+                const double ms = time_cg_config(c, grid_x(c), uses_reduction(c));
                 if (verbose)
                     fprintf(stderr, "[stag tune cg] V=%d prec=%d slots=%d lps=%d block=%d rtile=%d: %.2f us\n",
                             2 * f_->g.Vh, prec_, S_, L, B, R, ms * 1e3);
@@ -304,7 +356,7 @@ KernelCfg Batch::tune_cg()
             KernelCfg c = best;
             c.tables = T;
             c.remap = X;
-            const double ms = time_cg_config(c, grid_x(c));
+            const double ms = time_cg_config(c, grid_x(c), uses_reduction(c));
             if (verbose)
                 fprintf(stderr, "[stag tune cg] V=%d prec=%d slots=%d lps=%d block=%d rtile=%d tables=%d remap=%d: "
                                 "%.2f us\n", 2 * f_->g.Vh, prec_, S_, c.lps, c.block, c.rtile, T, X, ms * 1e3);
@@ -318,6 +370,7 @@ KernelCfg Batch::tune_cg()
     // so a lone system in a large tile pays for the whole tile.  Each is tuned
     // at the tuned shape's block count, which every kernel of the batch keeps.
     const int nblk = grid_x(best);
+    const bool reduce = uses_reduction(best);
     small_.clear();
     for (int i = 0; i < t.n_rtiles; ++i) {
         const int R = t.rtiles[i];
@@ -331,7 +384,7 @@ KernelCfg Batch::tune_cg()
                 c.lps = L;
                 c.block = B;
                 c.rtile = R;
-                const double ms = time_cg_config(c, nblk);
+                const double ms = time_cg_config(c, nblk, reduce);
                 if (verbose)
                     fprintf(stderr, "[stag tune cg] small tile: V=%d prec=%d slots=%d lps=%d block=%d rtile=%d "
                                     "blocks=%d: %.2f us\n", 2 * f_->g.Vh, prec_, S_, L, B, R, nblk, ms * 1e3);
@@ -388,6 +441,8 @@ int Batch::upload_and_init(const std::vector<int> &systems)
     const CgLaunchTable &t = cg_table(prec_, f_->rows);
     dim3 grid((unsigned)nblk_, (unsigned)nsys());
     hipError_t e = t.init(grid, dim3(cfg_.block), s_, a, cfg_.lps);
+    if (e == hipSuccess && reduce_)
+        e = launch_reduce(s_, 0, 2, 1, nblk_);
     if (e != hipSuccess)
         return set_error(STAG_EHIP, "init launch failed: %s", hipGetErrorString(e));
     return STAG_OK;
@@ -418,6 +473,9 @@ CgArgs Batch::args() const
     a.S = S_;
     a.pstride = pstride_;
     a.remap = cfg_.remap;
+    a.psum = reduce_ ? totals_ : partials_;
+    a.psum_stride = reduce_ ? 1 : pstride_;
+    a.nread = reduce_ ? 1 : nblk_;
     return a;
 }
 
@@ -428,8 +486,12 @@ int Batch::launch_step(int ver, hipStream_t st, const KernelCfg &c)
     const int R = c.rtile;
     dim3 grid((unsigned)nblk_, (unsigned)(nsys() / R)), blk(c.block);
     hipError_t e = t.step1(c.lps, R, grid, blk, st, a, ver);
+    if (e == hipSuccess && reduce_)  // K1's partials: slots 0, 1 of buffer ver ^ 1
+        e = launch_reduce(st, ver ^ 1, 0, 2, nblk_);
     if (e == hipSuccess)
         e = t.step2(c.lps, R, grid, blk, st, a, ver);
+    if (e == hipSuccess && reduce_)  // K2's partials: slot 2 of buffer ver ^ 1
+        e = launch_reduce(st, ver ^ 1, 2, 1, nblk_);
     if (e != hipSuccess)
         return set_error(STAG_EHIP, "CG kernel launch failed: %s", hipGetErrorString(e));
     return STAG_OK;

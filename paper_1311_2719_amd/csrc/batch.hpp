@@ -65,9 +65,11 @@ public:
 private:
     int launch_step(int ver, hipStream_t st, const KernelCfg &c);
     int grid_x(const KernelCfg &c) const;
+    bool uses_reduction(const KernelCfg &c) const;
+    hipError_t launch_reduce(hipStream_t st, int buf, int slot0, int nslots, int nblk) const;
     // Tune the tile shape on this workspace; also fills small_.
     KernelCfg tune_cg();
-    double time_cg_config(const KernelCfg &c, int nblk);
+    double time_cg_config(const KernelCfg &c, int nblk, bool reduce);
     CgArgs args() const;
 
     Ctx *ctx_;
@@ -81,6 +83,9 @@ private:
     // one partial sum per block of the kernel before it, so the count never
     // changes between shapes
     int nblk_ = 0;
+    // a reduction kernel sums each step kernel's partials before the next
+    // kernel reads them (large grids); otherwise every prologue sums them
+    bool reduce_ = false;
     int live_ = 0;  // running systems per parity (the larger count), from set_running
     int pstride_ = 0;
     void *mem_ = nullptr;
@@ -94,6 +99,7 @@ private:
     SysState *st_d_[2] = {nullptr, nullptr};
     int *perm_d_ = nullptr;
     double *partials_ = nullptr;
+    double *totals_ = nullptr;  // [2][nsys][3] totals of the partials (reduction kernel)
     // pinned host memory
     SysState *stage_ = nullptr;   // [nsys] staged initial states
     SysState *snap_ = nullptr;    // [2][nsys] last snapshot of both state buffers

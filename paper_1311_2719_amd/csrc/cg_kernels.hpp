@@ -21,7 +21,12 @@
 // (fixed summation order), so no block waits for another and no fence or
 // atomic is used; the state advanced by K1 is written by one block into the
 // other of two state buffers, which the following kernels read.  Partial sums
-// alternate between two buffers the same way.
+// alternate between two buffers the same way.  Each block of a prologue sums
+// all per-block partials of the kernel before it, which costs blocks x
+// partials reads; for large grids the host runs a small reduction kernel
+// between the step kernels instead, which writes each slot's total to a
+// separate array (CgArgs::psum, nread = 1), so that the step kernels can use
+// as many blocks as the lattice needs.
 //
 // Systems: nsys = 2*S, system j has parity j / S (x, r, p on that parity; ap
 // and t on the other).  A tile is R systems of one parity processed together
@@ -83,6 +88,12 @@ struct CgArgs {
     int S;                     // systems per parity
     int pstride;
     int remap;
+    // what a prologue sums: nread entries per slot at psum (stride psum_stride
+    // between slots) -- the previous kernel's per-block partials (psum =
+    // partials), or the totals a reduction kernel formed from them (nread = 1)
+    const double *psum;
+    int psum_stride;
+    int nread;
 };
 
 template <typename T> struct vec2_of;
@@ -109,6 +120,12 @@ template <class P> __device__ __forceinline__ cplx<typename P::real> load_colour
 
 // Partial sums: slot 0 <ap,ap>, slot 1 <p',p'>, slot 2 <r,r> (CG, residual
 // recomputation or the source norm at initialisation).
+__device__ __forceinline__ const double *psum_slot(const CgArgs &a, int buf, int j, int slot)
+{
+    const size_t nsys = 2 * (size_t)a.S;
+    return a.psum + (((size_t)buf * nsys + j) * 3 + slot) * a.psum_stride;
+}
+
 __device__ __forceinline__ double *partial_slot(const CgArgs &a, int buf, int j, int slot)
 {
     const size_t nsys = 2 * (size_t)a.S;
@@ -172,7 +189,7 @@ __device__ __forceinline__ void load_prologue(const CgArgs &a, int pbuf, const S
     for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int k = 0; k < NS; ++k)
-            base[r * NS + k] = partial_slot(a, pbuf, js[r], k);
+            base[r * NS + k] = psum_slot(a, pbuf, js[r], k);
 #pragma unroll
     for (int k = 0; k < NS * R; ++k)
         v[k] = 0.0;
@@ -437,7 +454,7 @@ __global__ void __launch_bounds__(256) k_cg_step1(CgArgs a, int ver)
     __shared__ double lds[3 * R * 4];
     const int tpp = a.S / R;
     const int par = blockIdx.y / tpp, k0 = par * a.S + (blockIdx.y % tpp) * R, pout = 1 - par;
-    const int Vh = a.g.Vh, nblk = gridDim.x;
+    const int Vh = a.g.Vh;
     int js[R];
     bool valid[R];
     if (!tile_systems<R>(a.perm + k0, js, valid))
@@ -446,7 +463,7 @@ __global__ void __launch_bounds__(256) k_cg_step1(CgArgs a, int ver)
     __shared__ SysState sst[R];
     {
         double v[3 * R];
-        load_prologue<R, 3>(a, ver, a.st[ver], a.perm + k0, js, valid, nblk, sst, v);
+        load_prologue<R, 3>(a, ver, a.st[ver], a.perm + k0, js, valid, a.nread, sst, v);
         wave_sums_to_lds<3 * R>(v, lds);
         const int r = threadIdx.x;
         if (r < R) {
@@ -634,7 +651,7 @@ __global__ void __launch_bounds__(256) k_cg_step2(CgArgs a, int ver)
     __shared__ double lds[3 * R * 4];
     const int tpp = a.S / R;
     const int par = blockIdx.y / tpp, k0 = par * a.S + (blockIdx.y % tpp) * R;
-    const int Vh = a.g.Vh, nblk = gridDim.x;
+    const int Vh = a.g.Vh;
     const int cur = ver ^ 1;  // the state K1 of this step wrote
     int js[R];
     bool valid[R];
@@ -644,7 +661,7 @@ __global__ void __launch_bounds__(256) k_cg_step2(CgArgs a, int ver)
     __shared__ SysState sst[R];
     {
         double v[2 * R];
-        load_prologue<R, 2>(a, cur, a.st[cur], a.perm + k0, js, valid, nblk, sst, v);
+        load_prologue<R, 2>(a, cur, a.st[cur], a.perm + k0, js, valid, a.nread, sst, v);
         wave_sums_to_lds<2 * R>(v, lds);
         const int r = threadIdx.x;
         if (r < R) {

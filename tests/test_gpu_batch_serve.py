@@ -20,8 +20,13 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("prec", [binding.FP32_RU, binding.FP64, binding.FP16_RU])
-def test_batch_matches_single_solves(gpu_ctx, prec):
+@pytest.mark.parametrize("prec,reduce", [(binding.FP32_RU, None), (binding.FP64, None), (binding.FP16_RU, None),
+                                         (binding.FP32_RU, "1"), (binding.FP64, "0")])
+def test_batch_matches_single_solves(gpu_ctx, monkeypatch, prec, reduce):
+    # reduce: the partial sums of each step kernel summed by a separate kernel
+    # ("1"), by every block of the next kernel ("0"), or as the grid size decides
+    if reduce is not None:
+        monkeypatch.setenv("STAG_CG_REDUCE", reduce)
     dims, tol, n = (8, 8, 8, 8), 1e-10, 12
     U = inputs.smooth_su3(dims, 0.5, 104)
     masses = inputs.masses_uniform(0.01, 0.2, n)
@@ -72,8 +77,13 @@ def test_batch_heterogeneous_parameters(gpu_ctx):
         gpu_ctx.free_gauge(f)
 
 
-def test_serving_alone_equals_in_the_mix(gpu_ctx):
-    # fields of different sizes resident at once; requests arrive while others run
+@pytest.mark.parametrize("reduce", [None, "1"])
+def test_serving_alone_equals_in_the_mix(gpu_ctx, monkeypatch, reduce):
+    # fields of different sizes resident at once; requests arrive while others
+    # run (admission re-initialises slots next to running systems, which must
+    # leave the running systems' sums intact in both reduction modes)
+    if reduce is not None:
+        monkeypatch.setenv("STAG_CG_REDUCE", reduce)
     specs = [((4, 4, 4, 4), 105), ((8, 8, 8, 8), 106), ((6, 6, 6, 8), 107)]
     fields = []
     try:
