@@ -71,14 +71,17 @@ int Batch::grid_x(const KernelCfg &c) const
     return std::min(need, std::max(128, 2048 / c.rtile));
 }
 
-// A reduction kernel between the step kernels pays for itself once every
-// prologue would otherwise sum about a thousand partials per slot set (its
-// cost: one small launch after each step kernel).
+// Whether shape c runs a reduction kernel between its step kernels: as the
+// tuner chose (it times both), else once every prologue would sum about a
+// thousand partials per slot set (the reduction costs one small launch after
+// each step kernel).
 bool Batch::uses_reduction(const KernelCfg &c) const
 {
     if (const char *e = getenv("STAG_CG_REDUCE"))  // "1": always, "0": never (tests, experiments)
         if (e[0] == '0' || e[0] == '1')
             return e[0] == '1';
+    if (c.reduce >= 0)
+        return c.reduce != 0;
     const int need = blocks_for(f_->g.Vh, c.lps, c.block);
     const int fused = std::min(need, std::max(128, 2048 / c.rtile));
     return (int64_t)fused * c.rtile >= 1024;
@@ -334,22 +337,26 @@ KernelCfg Batch::tune_cg()
         if (S_ % R)
             continue;
         for (int L : lps_c)
-            for (int B : blk_c) {
-                KernelCfg c;
-                c.lps = L;
-                c.block = B;
-                c.rtile = R;
-                c.tables = 0;
-                c.remap = 1;
-                const double ms = time_cg_config(c, grid_x(c), uses_reduction(c));
-                if (verbose)
-                    fprintf(stderr, "[stag tune cg] V=%d prec=%d slots=%d lps=%d block=%d rtile=%d: %.2f us\n",
-                            2 * f_->g.Vh, prec_, S_, L, B, R, ms * 1e3);
-                if (ms < best_t * 0.99) {
-                    best_t = ms;
-                    best = c;
+            for (int B : blk_c)
+                for (int D = 0; D < 2; ++D) {
+                    KernelCfg c;
+                    c.lps = L;
+                    c.block = B;
+                    c.rtile = R;
+                    c.tables = 0;
+                    c.remap = 1;
+                    c.reduce = D;
+                    if (D == 1 && uses_reduction(c) == uses_reduction(KernelCfg{L, B, R, 0, 1, 0}))
+                        continue;  // the mode is forced from the environment
+                    const double ms = time_cg_config(c, grid_x(c), uses_reduction(c));
+                    if (verbose)
+                        fprintf(stderr, "[stag tune cg] V=%d prec=%d slots=%d lps=%d block=%d rtile=%d reduce=%d: "
+                                        "%.2f us\n", 2 * f_->g.Vh, prec_, S_, L, B, R, D, ms * 1e3);
+                    if (ms < best_t * 0.99) {
+                        best_t = ms;
+                        best = c;
+                    }
                 }
-            }
     }
     for (int T = 0; T < 2; ++T)
         for (int X = 0; X < 2; ++X) {

@@ -2,8 +2,9 @@
 // batched over systems that share a gauge field.
 //
 // The iteration is the loop of the paper's Sec. 4 with the mass explicit,
-// arranged as two kernels per step so that every vector is streamed once,
-// every scalar stays on the device and no other kernel is needed:
+// arranged as two kernels per step so that every vector is streamed once and
+// every scalar stays on the device (large grids add a small reduction kernel
+// after each, see below):
 //   K1  prologue: reduce the previous step's partial sums and advance the
 //       system's scalar state (beta, the stopping test, reliable-update
 //       decisions); then, for a CG step, p' = r + beta p (formed on the fly at

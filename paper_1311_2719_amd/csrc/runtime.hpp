@@ -62,6 +62,8 @@ struct KernelCfg {
     int rtile = 1;      // right-hand sides per link read
     int tables = 0;     // 1: read iup/idn tables, 0: compute neighbours
     int remap = 1;      // XCD-aware block order
+    int reduce = -1;    // CG: 1 reduction kernel between step kernels, 0 prologues sum the
+                        // partials, -1 chosen by grid size
 };
 
 // ---- gauge field -------------------------------------------------------------
