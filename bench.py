@@ -402,7 +402,7 @@ def run_batch24(args):
         out[name] = {"solves_per_s": n / tb, "seconds": tb, "ratio_vs_fp64_single": (n / tb) / (n / t64),
                      "iters": [i["iters"] for i in infos], "true_rel_resid_max": max(i["true_rel_resid"] for i in infos),
                      "ok": all(i["status"] == 0 and i["true_rel_resid"] <= tol for i in infos),
-                     "config": ctx.tune_info(f, precision=prec, nrhs=n)}
+                     "cg_shape": ctx.cg_tune_info(f, precision=prec, nrhs=n)}
     ctx.close()
     _emit({"suite": "batch24", "workload": "24^4, eps=0.5 links seed 104, 12 sources seeds 2040-2051, "
                                            "m = linspace(0.01, 0.2, 12), true residual 1e-10", "results": out})

@@ -266,6 +266,22 @@ int stag_tune_info(stag_ctx *ctx, int32_t gauge_id, int32_t precision,
                    int32_t nrhs, int32_t *lanes_per_site, int32_t *block,
                    int32_t *rhs_tile, int32_t *use_tables);
 
+/*
+ * Describe the CG step-kernel shape tuned for a gauge field, a precision
+ * (0 FP64, 1 FP32_RU, 2 FP16_RU) and a number of right-hand sides (the
+ * slots of the solve: 1 for stag_cg_solve, nrhs for stag_cg_solve_batch,
+ * slots_per_field for the server): lanes per site, threads per block,
+ * systems per tile, neighbour tables read (1) or computed (0), and whether a
+ * reduction kernel sums each step kernel's partial sums (1) or every block of
+ * the next kernel does (0).  While fewer systems run than a tile takes, the
+ * solve may use smaller tiles tuned alongside.  Does not tune: ENOENT until a
+ * solve of that shape has run on the field; EINVAL for a bad precision or
+ * count, or a Wilson field.
+ */
+int stag_cg_tune_info(stag_ctx *ctx, int32_t gauge_id, int32_t precision, int32_t nrhs,
+                      int32_t *lanes_per_site, int32_t *block, int32_t *rhs_tile,
+                      int32_t *use_tables, int32_t *reduce);
+
 /* Library version string. */
 /* ---- Wilson fermions (the paper's second workload, Sec. 5) ------------
  *

@@ -101,6 +101,7 @@ def load():
             "stag_serve_config": ([P, I32, I32, I32], ctypes.c_int),
             "stag_tune_info": ([P, I32, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32),
                                 ctypes.POINTER(I32)], ctypes.c_int),
+            "stag_cg_tune_info": ([P, I32, I32, I32] + [ctypes.POINTER(I32)] * 5, ctypes.c_int),
             "stag_version": ([], ctypes.c_char_p),
             "stag_set_gauge_wilson": ([P, P, P, I32, I32, ctypes.POINTER(I32)], ctypes.c_int),
             "stag_pack_spinor": ([P, P, P, P, P], ctypes.c_int),
@@ -123,7 +124,7 @@ def exported_symbols():
         "stag_create", "stag_destroy", "stag_last_error", "stag_arena_usage", "stag_set_gauge",
         "stag_free_gauge", "stag_gauge_dims", "stag_gauge_link_rows", "stag_pack_fermion", "stag_unpack_fermion", "stag_dslash",
         "stag_cg_solve", "stag_cg_solve_batch", "stag_submit", "stag_poll", "stag_wait",
-        "stag_release_ticket", "stag_serve_config", "stag_tune_info", "stag_version",
+        "stag_release_ticket", "stag_serve_config", "stag_tune_info", "stag_cg_tune_info", "stag_version",
         "stag_set_gauge_wilson", "stag_pack_spinor", "stag_unpack_spinor", "stag_wilson_dslash",
         "stag_wilson_solve",
     ]
@@ -421,6 +422,15 @@ class Context:
                                        *[ctypes.byref(t) for t in v]), "stag_tune_info")
         return {"lanes_per_site": v[0].value, "block": v[1].value, "rhs_tile": v[2].value,
                 "use_tables": v[3].value}
+
+    def cg_tune_info(self, field: Field, precision=FP64, nrhs=1):
+        """The CG step shape tuned for (field, precision, nrhs) once such a
+        solve has run (StagError ENOENT before)."""
+        v = [ctypes.c_int32() for _ in range(5)]
+        _check(self.lib.stag_cg_tune_info(self.h, field.gauge_id, int(precision), int(nrhs),
+                                          *[ctypes.byref(t) for t in v]), "stag_cg_tune_info")
+        return {"lanes_per_site": v[0].value, "block": v[1].value, "rhs_tile": v[2].value,
+                "use_tables": v[3].value, "reduction_kernel": v[4].value}
 
 
 def version() -> str:

@@ -75,16 +75,30 @@ int Batch::grid_x(const KernelCfg &c) const
 // tuner chose (it times both), else once every prologue would sum about a
 // thousand partials per slot set (the reduction costs one small launch after
 // each step kernel).
-bool Batch::uses_reduction(const KernelCfg &c) const
+bool cg_uses_reduction(const Geom &g, const KernelCfg &c)
 {
     if (const char *e = getenv("STAG_CG_REDUCE"))  // "1": always, "0": never (tests, experiments)
         if (e[0] == '0' || e[0] == '1')
             return e[0] == '1';
     if (c.reduce >= 0)
         return c.reduce != 0;
-    const int need = blocks_for(f_->g.Vh, c.lps, c.block);
+    const int need = blocks_for(g.Vh, c.lps, c.block);
     const int fused = std::min(need, std::max(128, 2048 / c.rtile));
     return (int64_t)fused * c.rtile >= 1024;
+}
+
+bool Batch::uses_reduction(const KernelCfg &c) const { return cg_uses_reduction(f_->g, c); }
+
+bool cg_tuned_shape(Ctx *ctx, const GaugeField *f, int prec, int slots, KernelCfg &out, bool &reduce)
+{
+    const uint64_t key = ((uint64_t)1 << 40) | ((uint64_t)prec << 32) | (uint32_t)slots;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = f->tuned.find(key);
+    if (it == f->tuned.end())
+        return false;
+    out = it->second;
+    reduce = cg_uses_reduction(f->g, out);
+    return true;
 }
 
 namespace {

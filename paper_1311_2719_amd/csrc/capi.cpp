@@ -498,6 +498,38 @@ int stag_tune_info(stag_ctx *ctx, int32_t gauge_id, int32_t precision, int32_t n
     STAG_GUARD_END
 }
 
+int stag_cg_tune_info(stag_ctx *ctx, int32_t gauge_id, int32_t precision, int32_t nrhs, int32_t *lanes_per_site,
+                      int32_t *block, int32_t *rhs_tile, int32_t *use_tables, int32_t *reduce)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx || precision < 0 || precision > 2 || nrhs <= 0)
+        return set_error(STAG_EINVAL, "stag_cg_tune_info: bad argument");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    auto f = c->field(gauge_id);
+    if (!f)
+        return set_error(STAG_ENOENT, "unknown gauge id %d", gauge_id);
+    if (f->kind != FIELD_STAGGERED)
+        return set_error(STAG_EINVAL, "gauge id %d holds Wilson-fermion links", gauge_id);
+    KernelCfg k;
+    bool red = false;
+    if (!cg_tuned_shape(c, f.get(), precision, nrhs, k, red))
+        return set_error(STAG_ENOENT, "no CG solve with %d right-hand side(s) at precision %d has run on gauge id %d",
+                         nrhs, precision, gauge_id);
+    if (lanes_per_site)
+        *lanes_per_site = k.lps;
+    if (block)
+        *block = k.block;
+    if (rhs_tile)
+        *rhs_tile = k.rtile;
+    if (use_tables)
+        *use_tables = k.tables;
+    if (reduce)
+        *reduce = red ? 1 : 0;
+    return STAG_OK;
+    STAG_GUARD_END
+}
+
 // ---- serving ------------------------------------------------------------------
 
 static Server *server_of(Ctx *c)

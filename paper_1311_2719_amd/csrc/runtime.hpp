@@ -158,6 +158,10 @@ int launch_pack(const Geom &g, const double *lex, double *eo, int to_eo, hipStre
 int dslash_f64(Ctx *ctx, GaugeField *f, int out_parity, int64_t offset, int64_t count,
                const double *in, double *out, int accumulate, hipStream_t s);
 KernelCfg tune_config(Ctx *ctx, GaugeField *f, int prec, int nrhs, hipStream_t s);
+// CG step shape tuned for (field, precision, slots), if a solve with that many
+// slots has run; reduce: whether a reduction kernel runs between the steps.
+bool cg_tuned_shape(Ctx *ctx, const GaugeField *f, int prec, int slots, KernelCfg &out, bool &reduce);
+bool cg_uses_reduction(const Geom &g, const KernelCfg &c);
 
 // Take a workspace for (field, precision, slots, stream) from the cache or
 // create one; give it back with release_batch.  ENOMEM after evicting the cache.

@@ -36,8 +36,16 @@ def test_batch_matches_single_solves(gpu_ctx, monkeypatch, prec, reduce):
         bs = [gpu_ctx.pack(f, s) for s in srcs]
         xs = [gpu_ctx.new_fermion(f) for _ in range(n)]
         plist = [binding.params(float(mm), tol=tol, precision=prec) for mm in masses]
+        with pytest.raises(binding.StagError) as e:  # nothing tuned for this shape yet
+            gpu_ctx.cg_tune_info(f, precision=prec, nrhs=n)
+        assert e.value.code == binding.ENOENT
         infos = gpu_ctx.cg_solve_batch(f, bs, xs, plist)
         torch.cuda.synchronize()
+        shape = gpu_ctx.cg_tune_info(f, precision=prec, nrhs=n)
+        assert n % shape["rhs_tile"] == 0 and shape["lanes_per_site"] in (1, 2, 4, 8)
+        assert shape["block"] in (64, 128, 256) and shape["reduction_kernel"] in (0, 1)
+        if reduce is not None:
+            assert shape["reduction_kernel"] == int(reduce)
         for i in range(n):
             assert infos[i]["status"] == 0
             x = gpu_ctx.unpack(f, xs[i]).cpu().numpy()
