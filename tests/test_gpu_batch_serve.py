@@ -61,6 +61,32 @@ def test_batch_matches_single_solves(gpu_ctx, monkeypatch, prec, reduce):
         gpu_ctx.free_gauge(f)
 
 
+@pytest.mark.parametrize("reduce", ["0", "1"])
+def test_batch_bitwise_repeatable(gpu_ctx, monkeypatch, reduce):
+    # fixed reduction trees (in the prologues or in the reduction kernel) and
+    # a deterministic choice of tile per epoch: the same batch solved twice
+    # gives the same bits
+    monkeypatch.setenv("STAG_CG_REDUCE", reduce)
+    dims, n = (8, 8, 4, 8), 6
+    U = inputs.smooth_su3(dims, 0.5, 151)
+    f = gpu_ctx.set_gauge(dims, U)
+    try:
+        masses = inputs.masses_uniform(0.02, 0.3, n)
+        bs = [gpu_ctx.pack(f, inputs.gaussian_source(dims, 160 + i)) for i in range(n)]
+        plist = [binding.params(float(m), tol=1e-10, precision=binding.FP32_RU) for m in masses]
+        runs = []
+        for _ in range(2):
+            xs = [gpu_ctx.new_fermion(f) for _ in range(n)]
+            infos = gpu_ctx.cg_solve_batch(f, bs, xs, plist)
+            torch.cuda.synchronize()
+            runs.append(([gpu_ctx.unpack(f, x).cpu().numpy() for x in xs], [i["iters"] for i in infos]))
+        assert runs[0][1] == runs[1][1]
+        for a, b in zip(runs[0][0], runs[1][0]):
+            assert np.array_equal(a, b)
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
 def test_batch_heterogeneous_parameters(gpu_ctx):
     # different parities, tolerances and iteration limits in one batch
     dims = (4, 4, 4, 8)
