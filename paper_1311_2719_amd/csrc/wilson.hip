@@ -227,13 +227,13 @@ template <int ROWS, int LPS> constexpr WTable wtable()
     return {WLaunch<ROWS, LPS>::hop, WLaunch<ROWS, LPS>::init, WLaunch<ROWS, LPS>::step, WLaunch<ROWS, LPS>::finish};
 }
 
-constexpr int kWLps[3] = {1, 2, 4};
+constexpr int kWLps[4] = {1, 2, 4, 8};
 
 const WTable &wilson_table(int rows, int lps)
 {
-    static const WTable t[2][3] = {{wtable<2, 1>(), wtable<2, 2>(), wtable<2, 4>()},
-                                   {wtable<3, 1>(), wtable<3, 2>(), wtable<3, 4>()}};
-    return t[rows == 2 ? 0 : 1][lps == 1 ? 0 : lps == 2 ? 1 : 2];
+    static const WTable t[2][4] = {{wtable<2, 1>(), wtable<2, 2>(), wtable<2, 4>(), wtable<2, 8>()},
+                                   {wtable<3, 1>(), wtable<3, 2>(), wtable<3, 4>(), wtable<3, 8>()}};
+    return t[rows == 2 ? 0 : 1][lps == 1 ? 0 : lps == 2 ? 1 : lps == 4 ? 2 : 3];
 }
 
 // Lanes per site for the Wilson kernels of a field: STAG_WILSON_LPS, else the
@@ -244,7 +244,7 @@ int wilson_lps(Ctx *ctx, GaugeField *f, const double *in, double *out, hipStream
     const uint64_t key = (uint64_t)3 << 40;
     if (const char *e = getenv("STAG_WILSON_LPS")) {
         const int v = atoi(e);
-        if (v == 1 || v == 2 || v == 4)
+        if (v == 1 || v == 2 || v == 4 || v == 8)
             return v;
     }
     {
@@ -307,7 +307,7 @@ int wilson_cg_solve(Ctx *ctx, GaugeField *f, double kappa, double tol, int maxit
     const Geom &g = f->g;
     const int Vh = g.Vh;
     // partial sums sized for the most lanes per site (the most blocks)
-    const int nblk_max = (int)(((int64_t)Vh * 4 + kWBlock - 1) / kWBlock);
+    const int nblk_max = (int)(((int64_t)Vh * 8 + kWBlock - 1) / kWBlock);
     const int pstride = (nblk_max + 63) & ~63;
     const size_t vec = (size_t)12 * Vh * sizeof(dbl2);
     const size_t bytes = 6 * vec + 256 + (size_t)4 * pstride * sizeof(double);

@@ -201,9 +201,9 @@ def test_solve_edge_cases_and_errors(gpu_ctx):
         gpu_ctx.free_gauge(fs)
 
 
-@pytest.mark.parametrize("lps", ["1", "2", "4"])
+@pytest.mark.parametrize("lps", ["1", "2", "4", "8"])
 def test_every_lanes_per_site(lps):
-    # the tuner may pick 1, 2 or 4 lanes per site for the Wilson kernels: each
+    # the tuner may pick 1, 2, 4 or 8 lanes per site for the Wilson kernels: each
     # must give the same hop and the same solve
     dims = (6, 4, 2, 10)
     U = inputs.haar_su3(dims, 61)
