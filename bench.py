@@ -200,6 +200,26 @@ def run_default(args):
     if any(i["status"] != 0 or i["true_rel_resid"] > tol for i in infos):
         raise SystemExit("FP64 solve failed: %s" % infos)
 
+    # the same solves with the source coming from and the solution going to
+    # pinned host memory (PCIe both ways inside the timed region); reported
+    # beside the device-resident rate, never as the value
+    print("bench: FP64 CG with host transfers", file=sys.stderr, flush=True)
+    b_host = torch.empty(b.shape, dtype=b.dtype, pin_memory=True)
+    b_host.copy_(b.cpu())
+    x_host = torch.empty(x.shape, dtype=x.dtype, pin_memory=True)
+    n_pcie = max(3, args.steps // 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_pcie):
+        b.copy_(b_host)
+        torch.cuda.synchronize()
+        ctx.cg_solve(f, b, x, mass=m, tol=tol)
+        x_host.copy_(x)
+    torch.cuda.synchronize()
+    pcie = {"solves_per_s": n_pcie / (time.perf_counter() - t0), "solves": n_pcie,
+            "bytes_each_way": int(b.numel() * b.element_size()),
+            "what": "source copied from pinned host memory, solve, solution copied back, per solve"}
+
     print("bench: D_slash x%d" % args.dslash_reps, file=sys.stderr, flush=True)
     durs, mean = dslash_timing(ctx, f, b, args.dslash_reps)
     rows = ctx.link_rows(f)
@@ -286,6 +306,7 @@ def run_default(args):
         "solve": {"iters": info["iters"], "reliable_updates": info["reliable_updates"],
                   "true_rel_resid": info["true_rel_resid"]},
         "mixed": mixed,
+        "pcie_inclusive": pcie,
         "dslash_16_cold": cold,
         "dslash_32": d32,
         "dslash_32_share": shard,
