@@ -177,12 +177,16 @@ class Context:
                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "stag_create")
         self.h = h
         self.fields = {}
+        # tensors a queued request borrows (b, x), held until its ticket is
+        # released so that Python cannot free them while the server uses them
+        self._borrowed = {}
 
     # -- lifetime ------------------------------------------------------------
     def close(self):
         if getattr(self, "h", None):
             _check(self.lib.stag_destroy(self.h), "stag_destroy")
             self.h = None
+            self._borrowed = {}
 
     def __enter__(self):
         return self
@@ -391,6 +395,7 @@ class Context:
         t = ctypes.c_uint64()
         _check(self.lib.stag_submit(self.h, field.gauge_id, ctypes.byref(p), ctypes.c_void_p(b.data_ptr()),
                                     ctypes.c_void_p(x.data_ptr()), ctypes.byref(t)), "stag_submit")
+        self._borrowed[t.value] = (b, x)
         return t.value
 
     def poll(self, ticket: int):
@@ -415,6 +420,7 @@ class Context:
 
     def release(self, ticket: int):
         _check(self.lib.stag_release_ticket(self.h, ctypes.c_uint64(ticket)), "stag_release_ticket")
+        self._borrowed.pop(int(ticket), None)
 
     def tune_info(self, field: Field, precision=FP64, nrhs=1):
         v = [ctypes.c_int32() for _ in range(4)]

@@ -77,3 +77,39 @@ def test_config3_24_batch(gpu_ctx):
         assert all(i["status"] == 0 and i["true_rel_resid"] <= tol for i in infos)
     finally:
         gpu_ctx.free_gauge(f)
+
+
+def test_config4_serving_full_size_fields(gpu_ctx):
+    # two of the serving workload's resident fields (16^4, 24^4, eps = 0.5),
+    # requests arriving in two waves so the second is admitted next to running
+    # systems; every result checked by the oracle's FP64 true residual
+    specs = [((16, 16, 16, 16), 106), ((24, 24, 24, 24), 107)]
+    fields = []
+    try:
+        for dims, seed in specs:
+            U = inputs.smooth_su3(dims, 0.5, seed)
+            fields.append((dims, U, gpu_ctx.set_gauge(dims, U)))
+        rng = np.random.default_rng(405)
+        reqs = []
+        for wave in range(2):
+            for i in range(6):
+                k = int(rng.integers(0, len(fields)))
+                dims, U, f = fields[k]
+                m = float(np.exp(rng.uniform(np.log(0.01), np.log(0.2))))
+                src = inputs.gaussian_source(dims, 20000 + 6 * wave + i)
+                b = gpu_ctx.pack(f, src)
+                x = gpu_ctx.new_fermion(f)
+                torch.cuda.synchronize()
+                t = gpu_ctx.submit(f, b, x, mass=m, tol=1e-10, precision=binding.FP32_RU)
+                reqs.append((t, k, m, src, b, x))  # b and x are borrowed until completion
+            if wave == 0:
+                gpu_ctx.wait(reqs[0][0])  # the second wave arrives while the first runs
+        for t, k, m, src, b, x in reqs:
+            info = gpu_ctx.wait(t)
+            assert info["rc"] == 0 and info["status"] == 0, info
+            gpu_ctx.release(t)
+            dims, U, f = fields[k]
+            assert oracle.true_residual(dims, U, m, src, gpu_ctx.unpack(f, x).cpu().numpy()) <= 1e-10
+    finally:
+        for _, _, f in fields:
+            gpu_ctx.free_gauge(f)
