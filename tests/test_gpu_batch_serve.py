@@ -252,3 +252,31 @@ def test_serving_limits_and_shutdown():
         ts = [ctx.submit(f, b, x, mass=0.1) for x in xs]
         ctx.wait(ts[0])
     # (the context is gone: the remaining tickets were completed or cancelled)
+
+
+def test_serving_keeps_borrowed_buffers(gpu_ctx):
+    # the caller drops its own references to b right after submitting; the
+    # binding holds them until release, so the server never reads freed memory
+    import gc
+
+    dims = (8, 8, 8, 8)
+    U = inputs.smooth_su3(dims, 0.5, 171)
+    f = gpu_ctx.set_gauge(dims, U)
+    try:
+        reqs = []
+        for i in range(4):
+            src = inputs.gaussian_source(dims, 180 + i)
+            x = gpu_ctx.new_fermion(f)
+            t = gpu_ctx.submit(f, gpu_ctx.pack(f, src), x, mass=0.05, tol=1e-10, precision=binding.FP32_RU)
+            reqs.append((t, src, x))
+            gc.collect()
+            torch.cuda.empty_cache()
+            junk = torch.full((4 << 20,), 7.0, dtype=torch.float64, device="cuda")  # reuse freed memory
+            del junk
+        for t, src, x in reqs:
+            info = gpu_ctx.wait(t)
+            assert info["rc"] == 0 and info["status"] == 0, info
+            gpu_ctx.release(t)
+            assert oracle.true_residual(dims, U, 0.05, src, gpu_ctx.unpack(f, x).cpu().numpy()) <= 1e-10
+    finally:
+        gpu_ctx.free_gauge(f)
