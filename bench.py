@@ -104,11 +104,12 @@ def timed_solves(ctx, f, b, x, steps, warmup, **kw):
     return time.perf_counter() - t0, infos
 
 
-def dslash_timing(ctx, f, b, reps, **kw):
+def dslash_timing(ctx, f, b, reps, batches=5, **kw):
     """Per-launch durations (s) of the FP64 D_slash (full lattice unless kw
     names a parity and site range), from HIP events recorded on the stream
-    the library launches on; and the mean over the same launches back to
-    back under one event pair."""
+    the library launches on; and the mean per launch of `reps` launches back
+    to back under one event pair, the median over `batches` such runs (a
+    transient disturbance of one run does not set the figure)."""
     import torch
 
     out = ctx.new_fermion(f)
@@ -123,13 +124,16 @@ def dslash_timing(ctx, f, b, reps, **kw):
         e1.record(s)
     torch.cuda.synchronize()
     per_launch = np.array([e0.elapsed_time(e1) * 1e-3 for e0, e1 in ev])
-    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a0.record(s)
-    for _ in range(reps):
-        ctx.dslash(f, b, out, **kw)
-    a1.record(s)
-    torch.cuda.synchronize()
-    return per_launch, a0.elapsed_time(a1) * 1e-3 / reps
+    means = []
+    for _ in range(batches):
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a0.record(s)
+        for _ in range(reps):
+            ctx.dslash(f, b, out, **kw)
+        a1.record(s)
+        torch.cuda.synchronize()
+        means.append(a0.elapsed_time(a1) * 1e-3 / reps)
+    return per_launch, float(np.median(means))
 
 
 def dslash_cold(ctx, dims, copies, reps):
@@ -301,8 +305,8 @@ def run_default(args):
                      "bytes_per_site": dslash_bytes_per_site(rows), "link_rows": rows, "mean_us": mean * 1e6},
         "dslash": {"p50_us": float(np.percentile(durs, 50) * 1e6), "p99_us": float(np.percentile(durs, 99) * 1e6),
                    "mean_event_pair_us": float(durs.mean() * 1e6), "launches": int(len(durs)), "config": tune,
-                   "timing": "mean_us: one event pair around %d back-to-back launches; p50/p99: an event pair "
-                             "around each launch" % len(durs)},
+                   "timing": "mean_us: median over 5 runs of %d back-to-back launches under one event pair; p50/p99: "
+                             "an event pair around each launch" % len(durs)},
         "solve": {"iters": info["iters"], "reliable_updates": info["reliable_updates"],
                   "true_rel_resid": info["true_rel_resid"]},
         "mixed": mixed,

@@ -449,12 +449,29 @@ void Batch::stage_system(int j, const stag_cg_params &p, const double *b_half, d
 
 int Batch::upload_and_init(const std::vector<int> &systems)
 {
-    for (int j : systems) {
-        // the staged state goes into both buffers: the first step reads buffer 0
-        STAG_HIP_CHECK(hipMemcpyAsync(st_d_[0] + j, stage_ + j, sizeof(SysState), hipMemcpyHostToDevice, s_));
-        STAG_HIP_CHECK(hipMemcpyAsync(st_d_[1] + j, stage_ + j, sizeof(SysState), hipMemcpyHostToDevice, s_));
-        STAG_HIP_CHECK(hipMemcpyAsync(xhi_d_ + j, xhi_h_ + j, sizeof(void *), hipMemcpyHostToDevice, s_));
-        STAG_HIP_CHECK(hipMemcpyAsync(b_d_ + j, b_h_ + j, sizeof(void *), hipMemcpyHostToDevice, s_));
+    // every system at once (a blocking solve): whole arrays, four copies;
+    // otherwise (admission next to running systems) only the staged ones
+    std::vector<char> seen(nsys(), 0);
+    int distinct = 0;
+    for (int j : systems)
+        if (j >= 0 && j < nsys() && !seen[j]) {
+            seen[j] = 1;
+            ++distinct;
+        }
+    if (distinct == nsys()) {
+        const size_t ns = (size_t)nsys();
+        STAG_HIP_CHECK(hipMemcpyAsync(st_d_[0], stage_, ns * sizeof(SysState), hipMemcpyHostToDevice, s_));
+        STAG_HIP_CHECK(hipMemcpyAsync(st_d_[1], stage_, ns * sizeof(SysState), hipMemcpyHostToDevice, s_));
+        STAG_HIP_CHECK(hipMemcpyAsync(xhi_d_, xhi_h_, ns * sizeof(void *), hipMemcpyHostToDevice, s_));
+        STAG_HIP_CHECK(hipMemcpyAsync(b_d_, b_h_, ns * sizeof(void *), hipMemcpyHostToDevice, s_));
+    } else {
+        for (int j : systems) {
+            // the staged state goes into both buffers: the first step reads buffer 0
+            STAG_HIP_CHECK(hipMemcpyAsync(st_d_[0] + j, stage_ + j, sizeof(SysState), hipMemcpyHostToDevice, s_));
+            STAG_HIP_CHECK(hipMemcpyAsync(st_d_[1] + j, stage_ + j, sizeof(SysState), hipMemcpyHostToDevice, s_));
+            STAG_HIP_CHECK(hipMemcpyAsync(xhi_d_ + j, xhi_h_ + j, sizeof(void *), hipMemcpyHostToDevice, s_));
+            STAG_HIP_CHECK(hipMemcpyAsync(b_d_ + j, b_h_ + j, sizeof(void *), hipMemcpyHostToDevice, s_));
+        }
     }
     STAG_HIP_CHECK(hipEventRecord(stage_ev_, s_));
     stage_busy_ = true;
@@ -578,8 +595,9 @@ int Batch::enqueue_epoch(int steps)
 
 int Batch::enqueue_snapshot()
 {
-    STAG_HIP_CHECK(hipMemcpyAsync(snap_, st_d_[0], nsys() * sizeof(SysState), hipMemcpyDeviceToHost, s_));
-    STAG_HIP_CHECK(hipMemcpyAsync(snap_ + nsys(), st_d_[1], nsys() * sizeof(SysState), hipMemcpyDeviceToHost, s_));
+    // both state buffers in one copy (they are adjacent, as are their host
+    // mirrors): each copy costs a few microseconds of stream time
+    STAG_HIP_CHECK(hipMemcpyAsync(snap_, st_d_[0], 2 * nsys() * sizeof(SysState), hipMemcpyDeviceToHost, s_));
     STAG_HIP_CHECK(hipEventRecord(snap_ev_, s_));
     return STAG_OK;
 }
