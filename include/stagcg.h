@@ -282,7 +282,6 @@ int stag_cg_tune_info(stag_ctx *ctx, int32_t gauge_id, int32_t precision, int32_
                       int32_t *lanes_per_site, int32_t *block, int32_t *rhs_tile,
                       int32_t *use_tables, int32_t *reduce);
 
-/* Library version string. */
 /* ---- Wilson fermions (the paper's second workload, Sec. 5) ------------
  *
  * The paper runs an N_f = 2 Wilson-fermion program without writing the
@@ -339,6 +338,7 @@ int stag_wilson_solve(stag_ctx *ctx, int32_t gauge_id, double kappa, double tol,
                       int32_t maxiter, const double *b, double *x, void *stream,
                       stag_cg_info *info);
 
+/* Library version string. */
 const char *stag_version(void);
 
 #ifdef __cplusplus
