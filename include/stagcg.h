@@ -90,7 +90,8 @@ typedef struct {
     int32_t max_restarts;  /* FP64: restarts from the true residual (>= 0) */
     double delta;          /* reliable-update threshold (mixed precision): update when
                               ||r|| < delta * (largest ||r|| since the last update);
-                              <= 0 selects 0.1 */
+                              <= 0 selects the default: 0.01 for STAG_FP32_RU,
+                              0.1 for STAG_FP16_RU */
 } stag_cg_params;
 
 typedef struct {

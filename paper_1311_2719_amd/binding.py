@@ -143,7 +143,8 @@ def _torch():
     return torch
 
 
-def params(mass, tol=1e-10, maxiter=20000, precision=FP64, parity=ALL, max_restarts=10, delta=0.1) -> CGParams:
+def params(mass, tol=1e-10, maxiter=20000, precision=FP64, parity=ALL, max_restarts=10, delta=0.0) -> CGParams:
+    """CG parameters; delta <= 0 leaves the reliable-update threshold to the library default."""
     return CGParams(float(mass), float(tol), int(maxiter), int(precision), int(parity), int(max_restarts),
                     float(delta))
 

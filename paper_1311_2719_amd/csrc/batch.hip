@@ -441,7 +441,10 @@ void Batch::stage_system(int j, const stag_cg_params &p, const double *b_half, d
     st.maxiter = p.maxiter;
     st.max_restarts = p.max_restarts;
     st.mixed = prec_ != STAG_FP64;
-    const double delta = p.delta > 0 ? p.delta : 0.1;
+    // default threshold per precision: FP32 keeps the residual to ~1e-7
+    // relative, so it can run two decades between updates; FP16 (~1e-3)
+    // needs one, or its iterate drifts and CG takes many more steps
+    const double delta = p.delta > 0 ? p.delta : (prec_ == STAG_FP32_RU ? 0.01 : 0.1);
     st.delta2 = st.mixed ? delta * delta : 0.0;
     xhi_h_[j] = (dbl2 *)x_half;
     b_h_[j] = (const dbl2 *)b_half;
