@@ -177,6 +177,31 @@ def test_mixed_precision_true_residual(gpu_ctx, prec, dims, m, eps):
         gpu_ctx.free_gauge(f)
 
 
+def test_reliable_update_threshold_defaults(gpu_ctx):
+    # delta <= 0 selects 0.01 for FP32 and 0.1 for FP16: passing those values
+    # explicitly must give the same solve bit for bit; a larger FP32 threshold
+    # corrects more often and still reaches the true residual
+    dims, m, tol = (8, 8, 8, 8), 0.01, 1e-10
+    U = inputs.smooth_su3(dims, 0.5, 104)
+    b = inputs.gaussian_source(dims, 204)
+    f = gpu_ctx.set_gauge(dims, U)
+    try:
+        for prec, dflt in ((binding.FP32_RU, 0.01), (binding.FP16_RU, 0.1)):
+            xd, _, infod = solve(gpu_ctx, f, b, mass=m, tol=tol, precision=prec)
+            xe, _, infoe = solve(gpu_ctx, f, b, mass=m, tol=tol, precision=prec, delta=dflt)
+            assert infod["status"] == 0 and infoe["status"] == 0
+            assert infod["iters"] == infoe["iters"]
+            assert infod["reliable_updates"] == infoe["reliable_updates"]
+            assert np.array_equal(xd, xe)
+        xl, _, infol = solve(gpu_ctx, f, b, mass=m, tol=tol, precision=binding.FP32_RU, delta=0.1)
+        _, _, info32 = solve(gpu_ctx, f, b, mass=m, tol=tol, precision=binding.FP32_RU)
+        assert infol["status"] == 0
+        assert infol["reliable_updates"] > info32["reliable_updates"]
+        assert oracle.true_residual(dims, U, m, b, xl) <= tol
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
 def test_edge_cases(gpu_ctx):
     dims = (4, 4, 4, 4)
     U = inputs.haar_su3(dims, 111)
