@@ -70,6 +70,9 @@ extern "C" {
 #define STAG_EHIP       -9   /* HIP runtime error */
 #define STAG_ECANCELED -10   /* request cancelled (context destroyed) */
 
+/* Smallest reliable-update threshold accepted for STAG_FP16_RU. */
+#define STAG_FP16_DELTA_MIN 0.01
+
 /* ---- enumerations ---------------------------------------------------- */
 enum { STAG_EVEN = 0, STAG_ODD = 1, STAG_ALL = 2 };
 enum {
@@ -78,6 +81,17 @@ enum {
     STAG_FP16_RU = 2   /* FP16 storage with per-site norm, FP32 arithmetic,
                           FP64 reliable updates */
 };
+
+/* Storage precision of a fermion field handed to stag_dslash and
+ * stag_convert_fermion (even-odd layout, see above):
+ *   STAG_F64  complex128 [parity 2][colour 3][Vh]   (48 bytes per site)
+ *   STAG_F32  complex64  [parity 2][colour 3][Vh]   (24 bytes per site)
+ *   STAG_F16  [parity 2][Vh] records of 16 bytes: three colours as
+ *             (re, im) pairs of IEEE binary16 divided by the site's scale,
+ *             then the scale as an IEEE binary32 = the largest |re| or |im|
+ *             of the site (0 for a zero site).
+ * Links follow the same precision (FP16 links unscaled). */
+enum { STAG_F64 = 0, STAG_F32 = 1, STAG_F16 = 2 };
 
 typedef struct stag_ctx stag_ctx;
 
@@ -91,7 +105,11 @@ typedef struct {
     double delta;          /* reliable-update threshold (mixed precision): update when
                               ||r|| < delta * (largest ||r|| since the last update);
                               <= 0 selects the default: 0.01 for STAG_FP32_RU,
-                              0.1 for STAG_FP16_RU */
+                              0.1 for STAG_FP16_RU.  STAG_FP16_RU rejects (EINVAL)
+                              a threshold below STAG_FP16_DELTA_MIN: FP16 vectors
+                              carry about three decimal digits, and an iterated
+                              residual pushed further below its last FP64 value
+                              drifts from the true one */
 } stag_cg_params;
 
 typedef struct {
@@ -102,6 +120,7 @@ typedef struct {
     double true_rel_resid;     /* ||b - A x|| / ||b|| in FP64 on the GPU, over the solved parities */
     double seconds;            /* wall time of the solve (cg_solve) or submit->completion (serving) */
     double queue_seconds;      /* serving: submit -> admission into a batch slot */
+    int32_t iters_parity[2];   /* CG iterations of the even / odd parity system (-1: not solved) */
 } stag_cg_info;
 
 /* ---- context --------------------------------------------------------- */
@@ -122,8 +141,11 @@ int stag_create(int device, void *arena_dev, size_t arena_bytes, void *stream,
  * not freed (the caller owns it). */
 int stag_destroy(stag_ctx *ctx);
 
-/* Message of the last error raised on the calling thread ("" if none). */
-const char *stag_last_error(void);
+/* Message of the last error raised on the calling thread by any call of the
+ * library ("" if none).  The message is kept per thread, so `ctx` only names
+ * the context the caller asks about and may be NULL (after a failed
+ * stag_create).  The string stays valid until the thread's next call. */
+const char *stag_last_error(const stag_ctx *ctx);
 
 /* Bytes of the arena in use / total. */
 int stag_arena_usage(const stag_ctx *ctx, size_t *used, size_t *total);
@@ -176,36 +198,65 @@ int stag_unpack_fermion(stag_ctx *ctx, const int32_t dims[4], const double *eo,
  * out(x) = (accumulate ? out(x) : 0) + (D in)(x) for the output sites x of
  * parity out_parity whose checkerboard index lies in [offset, offset+count)
  * (count = -1: to the end of the parity).  This is the paper's
- * matrix-vector(offset, local_length, v, w) restricted to one parity.
- * out_parity = STAG_ALL applies D to every site (offset must be 0, count -1).
- * in, out: device full-lattice fields in the even-odd layout (only the
- * other parity of `in` is read); they must not overlap.  Sites outside the
- * range are untouched.  FP64.  Asynchronous on `stream`.
- * Errors: ENOENT, EINVAL (parity, range, NULL).
+ * matrix-vector(offset, local_length, v, w) of Sec. 3, restricted to one
+ * parity.  out_parity = STAG_ALL applies D to every site (offset must be 0,
+ * count -1).  in, out: full-lattice fields in the even-odd layout, stored in
+ * `precision` (STAG_F64, STAG_F32 or STAG_F16, layouts above; the links and
+ * the arithmetic are of the same precision, FP32 arithmetic for STAG_F16).
+ * Only the other parity of `in` is read.  Sites outside the range are
+ * untouched.
+ * on_device = 1: in and out are device pointers; the call is asynchronous
+ *   on `stream` (NULL = the context's stream); they must not overlap.
+ * on_device = 0: in and out are host pointers (the paper's copyin / copyout
+ *   of Sec. 4): the input half is copied to the device, D applied there, the
+ *   output range copied back into `out` (and first copied in when
+ *   accumulating); the call returns when `out` is complete.  Staging memory
+ *   comes from the arena (ENOMEM if it cannot hold two fields).
+ * Errors: ENOENT, EINVAL (parity, range, precision, NULL, overlap), ENOMEM,
+ * EHIP.
  */
 int stag_dslash(stag_ctx *ctx, int32_t gauge_id, int32_t out_parity,
-                int64_t offset, int64_t count, const double *in, double *out,
-                int32_t accumulate, void *stream);
+                int64_t offset, int64_t count, const void *in, void *out,
+                int32_t accumulate, int32_t precision, int32_t on_device,
+                void *stream);
+
+/*
+ * Convert a full-lattice fermion field of the field shape `dims` between
+ * storage precisions (STAG_F64 / STAG_F32 / STAG_F16, even-odd layout):
+ * rounding to nearest; to STAG_F16 each site is divided by its scale first.
+ * in, out: device pointers, not overlapping.  Asynchronous on `stream`.
+ * Errors: EINVAL.
+ */
+int stag_convert_fermion(stag_ctx *ctx, const int32_t dims[4], const void *in,
+                         int32_t in_precision, void *out, int32_t out_precision,
+                         void *stream);
 
 /* ---- the conjugate-gradient solve (Sec. 4) --------------------------- */
 
 /*
  * Solve (m^2 - D^2) x = b on the parity systems selected by params->parity,
- * from x = 0 (Sec. 4).  b, x: device full-lattice fields in the even-odd
+ * from x = 0 (Sec. 4).  b, x: full-lattice FP64 fields in the even-odd
  * layout; only the selected parities are read / written.  y (nullable): if
- * given, y = D x on the opposite parity of every solved system (the paper's
- * "solution on the second half lattice").  Every iteration runs on the GPU
- * with the scalars and the stopping test kept in device memory; the host
- * only polls a status word every few iterations.  The result is accepted
- * when the FP64 true residual on the GPU satisfies ||b - A x|| <= tol ||b||
- * for each parity system.  Blocks until done; info (nullable) receives the
- * outcome.  Returns STAG_OK or the solve's error (ENOCONV: x holds the last
- * iterate).  Errors: ENOENT, EINVAL (m <= 0, tol <= 0, bad parity or
- * precision), ENOMEM, ENOCONV, EBREAKDOWN, ENONFINITE.
+ * given, y = D x on the opposite parity of every solved system (the paper
+ * reconstructs the other half of the lattice from the solution after the
+ * loop, Sec. 4).  Every iteration runs on the GPU with the scalars and the
+ * stopping test kept in device memory; the host only looks at a status
+ * record every few iterations.  The result is accepted when the FP64 true
+ * residual on the GPU satisfies ||b - A x|| <= tol ||b|| for each parity
+ * system.
+ * on_device = 1: b, x, y are device pointers, and the solve runs on
+ *   `stream` (NULL = the context's stream).
+ * on_device = 0: they are host pointers (the paper's copyin / copyout data
+ *   region of Sec. 4): b is copied to the device, the solve runs there and
+ *   x (and y) are copied back; staging memory comes from the arena.
+ * Blocks until done; info (nullable) receives the outcome.  Returns STAG_OK
+ * or the solve's error (ENOCONV: x holds the last iterate).  Errors: ENOENT,
+ * EINVAL (m <= 0, tol <= 0, bad parity or precision, an FP16 threshold
+ * below its floor), ENOMEM, ENOCONV, EBREAKDOWN, ENONFINITE.
  */
 int stag_cg_solve(stag_ctx *ctx, int32_t gauge_id, const stag_cg_params *params,
-                  const double *b, double *x, double *y, void *stream,
-                  stag_cg_info *info);
+                  const double *b, double *x, double *y, int32_t on_device,
+                  void *stream, stag_cg_info *info);
 
 /*
  * Solve nrhs systems that share one gauge field in one batched solve: every
@@ -213,9 +264,14 @@ int stag_cg_solve(stag_ctx *ctx, int32_t gauge_id, const stag_cg_params *params,
  * may differ in mass, tol, maxiter and parity; precision must be the same for
  * all.  b[i], x[i]: device full-lattice fields (even-odd layout).  The tile
  * of right-hand sides processed per link read and the kernel shapes are
- * chosen by the library's autotuner.  Each system's iteration sequence
- * (and therefore its result) does not depend on which other systems share the
- * batch.  infos[i] receives each outcome.  Blocks until all are done.
+ * chosen by the library's autotuner; while fewer systems are still running
+ * than a tile takes, smaller tiles (tuned alongside, possibly with other
+ * lanes per site and block sizes) take over.  A system's arithmetic is that
+ * of the single solve up to the order in which its sums are formed, so its
+ * result can differ from the same system solved alone (or in another batch)
+ * by rounding: both meet the FP64 true residual tol, and the solutions agree
+ * within the error that residual allows.  The same batch solved twice gives
+ * the same bits.  infos[i] receives each outcome.  Blocks until all are done.
  * Returns STAG_OK if every system converged, else the first error.
  */
 int stag_cg_solve_batch(stag_ctx *ctx, int32_t gauge_id, int32_t nrhs,
@@ -226,7 +282,10 @@ int stag_cg_solve_batch(stag_ctx *ctx, int32_t gauge_id, int32_t nrhs,
 
 /*
  * Queue a solve.  b_dev / x_dev are device full-lattice fields (even-odd
- * layout) borrowed until stag_poll / stag_wait report completion.  A
+ * layout) borrowed until stag_poll / stag_wait report completion.  The
+ * request is ordered after the work enqueued on the context's stream before
+ * this call (an event recorded there is waited on before b is read and x
+ * written), so a source written on that stream needs no synchronisation.  A
  * scheduler thread admits queued requests into batch slots of their gauge
  * field while memory (the arena) and slots allow, runs the batch in epochs
  * of CG iterations on the field's own stream, and between epochs retires
@@ -283,7 +342,7 @@ int stag_cg_tune_info(stag_ctx *ctx, int32_t gauge_id, int32_t precision, int32_
                       int32_t *lanes_per_site, int32_t *block, int32_t *rhs_tile,
                       int32_t *use_tables, int32_t *reduce);
 
-/* ---- Wilson fermions (the paper's second workload, Sec. 5) ------------
+/* ---- Wilson fermions (the paper's second workload, Sec. 2 and Sec. 6) ------------
  *
  * The paper runs an N_f = 2 Wilson-fermion program without writing the
  * operator out; the library takes the textbook form

@@ -9,7 +9,7 @@
  * it shares no code, header, table or constant with the HIP path.
  *
  * Source: P. Majumdar, arXiv:1311.2719.  The paper's second workload is an
- * N_f = 2 Wilson-fermion HMC program (Sec. 5, "Performance & Discussion"); it
+ * N_f = 2 Wilson-fermion HMC program (Sec. 2 and Sec. 6, "Performance & Discussion"); it
  * does not write the operator out, so the textbook form is taken (each point
  * a documented reading):
  *   (H psi)(x) = sum_mu [ (1 - gamma_mu) U_mu(x) psi(x + mu)

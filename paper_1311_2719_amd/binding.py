@@ -30,6 +30,9 @@ ERRORS = {
 EINVAL, ENOMEM, ENOENT, EBUSY, EAGAIN, ENOCONV, EBREAKDOWN, ENONFINITE, EHIP, ECANCELED = range(-1, -11, -1)
 EVEN, ODD, ALL = 0, 1, 2
 FP64, FP32_RU, FP16_RU = 0, 1, 2
+F64, F32, F16 = 0, 1, 2  # storage precision of a fermion field (stag_dslash, stag_convert_fermion)
+SPINOR_BYTES = {F64: 48, F32: 24, F16: 16}  # per site
+FP16_DELTA_MIN = 0.01
 
 _lock = threading.Lock()
 _lib = None
@@ -62,10 +65,13 @@ class CGInfo(ctypes.Structure):
         ("true_rel_resid", ctypes.c_double),
         ("seconds", ctypes.c_double),
         ("queue_seconds", ctypes.c_double),
+        ("iters_parity", ctypes.c_int32 * 2),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["iters_parity"] = [int(v) for v in self.iters_parity]
+        return d
 
 
 def load():
@@ -82,7 +88,7 @@ def load():
         sig = {
             "stag_create": ([ctypes.c_int, P, SZ, P, ctypes.POINTER(P)], ctypes.c_int),
             "stag_destroy": ([P], ctypes.c_int),
-            "stag_last_error": ([], ctypes.c_char_p),
+            "stag_last_error": ([P], ctypes.c_char_p),
             "stag_arena_usage": ([P, ctypes.POINTER(SZ), ctypes.POINTER(SZ)], ctypes.c_int),
             "stag_set_gauge": ([P, P, P, I32, I32, ctypes.POINTER(I32)], ctypes.c_int),
             "stag_free_gauge": ([P, I32], ctypes.c_int),
@@ -90,8 +96,10 @@ def load():
             "stag_gauge_link_rows": ([P, I32, ctypes.POINTER(I32)], ctypes.c_int),
             "stag_pack_fermion": ([P, P, P, P, P], ctypes.c_int),
             "stag_unpack_fermion": ([P, P, P, P, P], ctypes.c_int),
-            "stag_dslash": ([P, I32, I32, I64, I64, P, P, I32, P], ctypes.c_int),
-            "stag_cg_solve": ([P, I32, ctypes.POINTER(CGParams), P, P, P, P, ctypes.POINTER(CGInfo)], ctypes.c_int),
+            "stag_dslash": ([P, I32, I32, I64, I64, P, P, I32, I32, I32, P], ctypes.c_int),
+            "stag_convert_fermion": ([P, P, P, I32, P, I32, P], ctypes.c_int),
+            "stag_cg_solve": ([P, I32, ctypes.POINTER(CGParams), P, P, P, I32, P, ctypes.POINTER(CGInfo)],
+                              ctypes.c_int),
             "stag_cg_solve_batch": ([P, I32, I32, ctypes.POINTER(CGParams), P, P, P, ctypes.POINTER(CGInfo)],
                                     ctypes.c_int),
             "stag_submit": ([P, I32, ctypes.POINTER(CGParams), P, P, ctypes.POINTER(U64)], ctypes.c_int),
@@ -123,7 +131,7 @@ def exported_symbols():
     return [
         "stag_create", "stag_destroy", "stag_last_error", "stag_arena_usage", "stag_set_gauge",
         "stag_free_gauge", "stag_gauge_dims", "stag_gauge_link_rows", "stag_pack_fermion", "stag_unpack_fermion", "stag_dslash",
-        "stag_cg_solve", "stag_cg_solve_batch", "stag_submit", "stag_poll", "stag_wait",
+        "stag_convert_fermion", "stag_cg_solve", "stag_cg_solve_batch", "stag_submit", "stag_poll", "stag_wait",
         "stag_release_ticket", "stag_serve_config", "stag_tune_info", "stag_cg_tune_info", "stag_version",
         "stag_set_gauge_wilson", "stag_pack_spinor", "stag_unpack_spinor", "stag_wilson_dslash",
         "stag_wilson_solve",
@@ -132,7 +140,7 @@ def exported_symbols():
 
 def _check(rc: int, what: str) -> int:
     if rc < 0:
-        msg = load().stag_last_error()
+        msg = load().stag_last_error(None)
         raise StagError(rc, "%s: %s" % (what, msg.decode() if msg else ""))
     return rc
 
@@ -247,9 +255,39 @@ class Context:
         self.fields.pop(field.gauge_id, None)
 
     # -- fields ----------------------------------------------------------------
-    def new_fermion(self, field: Field):
+    def new_fermion(self, field: Field, precision=F64):
+        """A zero field on the device in the even-odd layout: complex128 or
+        complex64 (2, 3, V/2) for F64 / F32, 16-byte records uint8 (2, V/2, 16)
+        for F16."""
         torch = _torch()
-        return torch.zeros((2, 3, field.volume // 2), dtype=torch.complex128, device=self.torch_device)
+        vh = field.volume // 2
+        if precision == F16:
+            return torch.zeros((2, vh, 16), dtype=torch.uint8, device=self.torch_device)
+        dt = torch.complex128 if precision == F64 else torch.complex64
+        return torch.zeros((2, 3, vh), dtype=dt, device=self.torch_device)
+
+    def convert(self, field: Field, inp, out, in_precision, out_precision, stream=None):
+        """out = inp converted between storage precisions (device tensors)."""
+        for t, pr in ((inp, in_precision), (out, out_precision)):
+            self._check_prec(field, t, pr, device=True)
+        d = np.asarray(field.dims, dtype=np.int32)
+        s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+        _check(self.lib.stag_convert_fermion(self.h, d.ctypes.data, ctypes.c_void_p(inp.data_ptr()), int(in_precision),
+                                             ctypes.c_void_p(out.data_ptr()), int(out_precision), s),
+               "stag_convert_fermion")
+        return out
+
+    def _check_prec(self, field, t, precision, device):
+        """t: a contiguous torch CUDA tensor (device) or numpy array (host)
+        holding one full-lattice field of `precision`."""
+        torch = _torch()
+        need = field.volume // 2 * 2 * SPINOR_BYTES[int(precision)]
+        if device:
+            ok = isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous() and t.numel() * t.element_size() == need
+        else:
+            ok = isinstance(t, np.ndarray) and t.flags.c_contiguous and t.nbytes == need
+        if not ok:
+            raise ValueError("expected a contiguous %s field of %d bytes" % ("device" if device else "host", need))
 
     def pack(self, field: Field, lex):
         """(V,3) complex128 (numpy or torch) -> device even-odd tensor (2,3,V/2)."""
@@ -339,25 +377,38 @@ class Context:
         return d
 
     # -- operator and solves ------------------------------------------------------
-    def dslash(self, field: Field, inp, out, out_parity=ALL, offset=0, count=-1, accumulate=False, stream=None):
-        self._check_eo(field, inp)
-        self._check_eo(field, out)
+    def dslash(self, field: Field, inp, out, out_parity=ALL, offset=0, count=-1, accumulate=False, stream=None,
+               precision=F64):
+        """out (+)= D inp on a site range of out_parity.  inp/out: torch CUDA
+        tensors (asynchronous on the library's stream), or numpy arrays on
+        the host (copied in and out; returns when out is complete)."""
+        on_device = not isinstance(inp, np.ndarray)
+        self._check_prec(field, inp, precision, on_device)
+        self._check_prec(field, out, precision, on_device)
+        if isinstance(out, np.ndarray) != isinstance(inp, np.ndarray):
+            raise ValueError("inp and out must both be host arrays or both device tensors")
+        ptr = (lambda a: a.ctypes.data) if not on_device else (lambda t: t.data_ptr())
         s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
         _check(self.lib.stag_dslash(self.h, field.gauge_id, int(out_parity), int(offset), int(count),
-                                    ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-                                    int(bool(accumulate)), s), "stag_dslash")
+                                    ctypes.c_void_p(ptr(inp)), ctypes.c_void_p(ptr(out)),
+                                    int(bool(accumulate)), int(precision), int(on_device), s), "stag_dslash")
         return out
 
     def cg_solve(self, field: Field, b, x, y=None, check=True, **kw):
+        """Solve on device tensors (b, x, y complex128 (2,3,V/2) on the GPU) or
+        on host arrays (numpy complex128 (2,3,V/2): copied in and out)."""
         p = params(**kw)
-        self._check_eo(field, b)
-        self._check_eo(field, x)
-        if y is not None:
-            self._check_eo(field, y)
+        on_device = not isinstance(b, np.ndarray)
+        for t in (b, x) + ((y,) if y is not None else ()):
+            if on_device:
+                self._check_eo(field, t)
+            else:
+                self._check_prec(field, t, F64, device=False)
+        ptr = (lambda a: a.ctypes.data) if not on_device else (lambda t: t.data_ptr())
         info = CGInfo()
-        rc = self.lib.stag_cg_solve(self.h, field.gauge_id, ctypes.byref(p), ctypes.c_void_p(b.data_ptr()),
-                                    ctypes.c_void_p(x.data_ptr()),
-                                    ctypes.c_void_p(y.data_ptr()) if y is not None else None, None,
+        rc = self.lib.stag_cg_solve(self.h, field.gauge_id, ctypes.byref(p), ctypes.c_void_p(ptr(b)),
+                                    ctypes.c_void_p(ptr(x)),
+                                    ctypes.c_void_p(ptr(y)) if y is not None else None, int(on_device), None,
                                     ctypes.byref(info))
         if check:
             _check(rc, "stag_cg_solve")

@@ -1,4 +1,4 @@
-"""Build libstagcg.so (HIP, gfx950) in-tree with hipcc, and the CPU oracle.
+"""Build libstagcg.so (HIP, gfx950) in-tree with hipcc.
 
     python -m paper_1311_2719_amd.build [--jobs N]
 
@@ -13,7 +13,6 @@ import concurrent.futures as cf
 import glob
 import os
 import subprocess
-import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -71,19 +70,11 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     return LIB
 
 
-def build_oracle() -> str:
-    sys.path.insert(0, ROOT)
-    import oracle  # the CPU checker is built here too; the library never loads it
-
-    return oracle.build(force=True)
-
-
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
     args = ap.parse_args(argv)
     build(args.jobs, verbose=True)
-    print("built", build_oracle())
 
 
 if __name__ == "__main__":

@@ -629,6 +629,9 @@ static int validate_params(const stag_cg_params &p, int prec0)
         return set_error(STAG_EINVAL, "parity must be STAG_EVEN, STAG_ODD or STAG_ALL");
     if (p.precision < STAG_FP64 || p.precision > STAG_FP16_RU)
         return set_error(STAG_EINVAL, "unknown precision %d", p.precision);
+    if (p.precision == STAG_FP16_RU && p.delta > 0 && p.delta < STAG_FP16_DELTA_MIN)
+        return set_error(STAG_EINVAL, "FP16 reliable-update threshold %g is below its floor %g", p.delta,
+                         (double)STAG_FP16_DELTA_MIN);
     if (p.precision != prec0)
         return set_error(STAG_EINVAL, "all systems of a batch must use the same precision");
     return STAG_OK;
@@ -649,6 +652,7 @@ void fill_info(const Batch &B, int slot, stag_cg_info *info)
     int status = STAG_OK, iters = 0, nru = 0, rst = 0;
     double trr = 0, bb = 0;
     bool any = false;
+    info->iters_parity[0] = info->iters_parity[1] = -1;
     for (int par = 0; par < 2; ++par) {
         const SysState &st = B.state(par * S + slot);
         if (st.mode == M_IDLE)
@@ -656,6 +660,7 @@ void fill_info(const Batch &B, int slot, stag_cg_info *info)
         any = true;
         status = worse(status, st.mode == M_DONE ? st.status : STAG_ENOCONV);
         iters = std::max(iters, st.iters);
+        info->iters_parity[par] = st.iters;
         nru += st.n_ru;
         rst = std::max(rst, st.restarts);
         trr += st.true_rr;

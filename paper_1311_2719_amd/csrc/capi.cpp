@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "runtime.hpp"
@@ -44,7 +45,7 @@ extern "C" {
 
 const char *stag_version(void) { return "stagcg 1.0 (gfx950)"; }
 
-const char *stag_last_error(void) { return last_error_cstr(); }
+const char *stag_last_error(const stag_ctx *) { return last_error_cstr(); }
 
 int stag_create(int device, void *arena_dev, size_t arena_bytes, void *stream, stag_ctx **out)
 {
@@ -388,8 +389,8 @@ int stag_unpack_fermion(stag_ctx *ctx, const int32_t dims[4], const double *eo, 
     STAG_GUARD_END
 }
 
-int stag_dslash(stag_ctx *ctx, int32_t gauge_id, int32_t out_parity, int64_t offset, int64_t count,
-                const double *in, double *out, int32_t accumulate, void *stream)
+int stag_dslash(stag_ctx *ctx, int32_t gauge_id, int32_t out_parity, int64_t offset, int64_t count, const void *in,
+                void *out, int32_t accumulate, int32_t precision, int32_t on_device, void *stream)
 {
     STAG_GUARD_BEGIN
     clear_error();
@@ -397,6 +398,8 @@ int stag_dslash(stag_ctx *ctx, int32_t gauge_id, int32_t out_parity, int64_t off
         return set_error(STAG_EINVAL, "stag_dslash: NULL argument");
     if (in == out)
         return set_error(STAG_EINVAL, "stag_dslash: in and out must not overlap");
+    if (precision < STAG_F64 || precision > STAG_F16)
+        return set_error(STAG_EINVAL, "stag_dslash: unknown precision %d", precision);
     Ctx *c = reinterpret_cast<Ctx *>(ctx);
     auto f = c->field(gauge_id);
     if (!f)
@@ -413,19 +416,86 @@ int stag_dslash(stag_ctx *ctx, int32_t gauge_id, int32_t out_parity, int64_t off
     if (offset < 0 || offset > Vh || count < 0 || offset + count > Vh)
         return set_error(STAG_EINVAL, "stag_dslash: range [%lld, %lld) outside [0, %lld)", (long long)offset,
                          (long long)(offset + count), (long long)Vh);
+    const size_t hb = (size_t)Vh * spinor_bytes_of(precision);  // bytes of one parity half
     const char *a0 = (const char *)in, *b0 = (const char *)out;
-    const size_t fb = (size_t)2 * 3 * Vh * 16;
-    if (a0 < b0 + fb && b0 < a0 + fb)
+    if (a0 < b0 + 2 * hb && b0 < a0 + 2 * hb)
         return set_error(STAG_EINVAL, "stag_dslash: in and out must not overlap");
     if (count == 0)
         return STAG_OK;
     DeviceGuard dg(c->device);
-    return dslash_f64(c, f.get(), out_parity, offset, count, in, out, accumulate, pick_stream(ctx, stream));
+    hipStream_t s = pick_stream(ctx, stream);
+    if (on_device)
+        return dslash(c, f.get(), precision, out_parity, offset, count, in, out, accumulate, s);
+    // host arrays: stage through the arena (the paper's copyin / copyout)
+    struct Staging {
+        Arena &arena;
+        void *p;
+        ~Staging() { arena.release(p); }
+    } st{c->arena, c->arena.alloc(4 * hb)};
+    if (!st.p)
+        return set_error(STAG_ENOMEM, "stag_dslash: arena exhausted (staging %zu bytes)", 4 * hb);
+    char *din = (char *)st.p, *dout = din + 2 * hb;
+    // the written output range: per parity, one piece per colour plane
+    // (FP64 / FP32 [colour][Vh]) or one piece of records (FP16)
+    const size_t esz = precision == STAG_F16 ? 16 : spinor_bytes_of(precision) / 3;
+    const int planes = precision == STAG_F16 ? 1 : 3;
+    auto copy_range = [&](int par, hipMemcpyKind kind) -> hipError_t {
+        for (int pl = 0; pl < planes; ++pl) {
+            const size_t o = (size_t)par * hb + ((size_t)pl * Vh + offset) * esz;
+            hipError_t e = kind == hipMemcpyHostToDevice
+                               ? hipMemcpyAsync(dout + o, b0 + o, (size_t)count * esz, kind, s)
+                               : hipMemcpyAsync((char *)out + o, dout + o, (size_t)count * esz, kind, s);
+            if (e != hipSuccess)
+                return e;
+        }
+        return hipSuccess;
+    };
+    if (out_parity == STAG_ALL)
+        STAG_HIP_CHECK(hipMemcpyAsync(din, in, 2 * hb, hipMemcpyHostToDevice, s));
+    else
+        STAG_HIP_CHECK(hipMemcpyAsync(din + (1 - out_parity) * hb, a0 + (1 - out_parity) * hb, hb,
+                                      hipMemcpyHostToDevice, s));
+    for (int par = 0; par < 2 && accumulate; ++par)
+        if (out_parity == STAG_ALL || out_parity == par)
+            STAG_HIP_CHECK(copy_range(par, hipMemcpyHostToDevice));
+    int rc = dslash(c, f.get(), precision, out_parity, offset, count, din, dout, accumulate, s);
+    if (rc != STAG_OK) {
+        (void)hipStreamSynchronize(s);
+        return rc;
+    }
+    for (int par = 0; par < 2; ++par)
+        if (out_parity == STAG_ALL || out_parity == par)
+            STAG_HIP_CHECK(copy_range(par, hipMemcpyDeviceToHost));
+    STAG_HIP_CHECK(hipStreamSynchronize(s));
+    return STAG_OK;
+    STAG_GUARD_END
+}
+
+int stag_convert_fermion(stag_ctx *ctx, const int32_t dims[4], const void *in, int32_t in_precision, void *out,
+                         int32_t out_precision, void *stream)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx || !in || !out)
+        return set_error(STAG_EINVAL, "stag_convert_fermion: NULL argument");
+    if (!dims_ok(dims))
+        return set_error(STAG_EINVAL, "stag_convert_fermion: every extent must be even and >= 2");
+    if (in_precision < STAG_F64 || in_precision > STAG_F16 || out_precision < STAG_F64 || out_precision > STAG_F16)
+        return set_error(STAG_EINVAL, "stag_convert_fermion: unknown precision");
+    const Geom g = make_geom(dims);
+    const char *a0 = (const char *)in, *b0 = (const char *)out;
+    const size_t na = (size_t)2 * g.Vh * spinor_bytes_of(in_precision);
+    const size_t nb = (size_t)2 * g.Vh * spinor_bytes_of(out_precision);
+    if (a0 < b0 + nb && b0 < a0 + na)
+        return set_error(STAG_EINVAL, "stag_convert_fermion: in and out must not overlap");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    DeviceGuard dg(c->device);
+    return convert_fermion(g, in_precision, in, out_precision, out, pick_stream(ctx, stream));
     STAG_GUARD_END
 }
 
 int stag_cg_solve(stag_ctx *ctx, int32_t gauge_id, const stag_cg_params *params, const double *b, double *x,
-                  double *y, void *stream, stag_cg_info *info)
+                  double *y, int32_t on_device, void *stream, stag_cg_info *info)
 {
     STAG_GUARD_BEGIN
     clear_error();
@@ -441,8 +511,44 @@ int stag_cg_solve(stag_ctx *ctx, int32_t gauge_id, const stag_cg_params *params,
     if (rc != STAG_OK)
         return rc;
     DeviceGuard dg(c->device);
-    double *ys[1] = {y};
-    return cg_solve_batch(c, f, 1, params, &b, &x, ys, pick_stream(ctx, stream), info);
+    hipStream_t s = pick_stream(ctx, stream);
+    if (on_device) {
+        double *ys[1] = {y};
+        return cg_solve_batch(c, f, 1, params, &b, &x, ys, s, info);
+    }
+    // host arrays: b in, x (and y) out, through the arena (the paper's data
+    // region: copyin of the source, copyout of the solution)
+    const size_t hb = (size_t)f->g.Vh * 48, hd = (size_t)f->g.Vh * 6;  // bytes / doubles per parity half
+    const size_t nbuf = y ? 3 : 2;
+    struct Staging {
+        Arena &arena;
+        void *p;
+        ~Staging() { arena.release(p); }
+    } st{c->arena, c->arena.alloc(nbuf * 2 * hb)};
+    if (!st.p)
+        return set_error(STAG_ENOMEM, "stag_cg_solve: arena exhausted (staging %zu bytes)", nbuf * 2 * hb);
+    double *db = (double *)st.p, *dx = db + 2 * hd, *dy = y ? dx + 2 * hd : nullptr;
+    const int par = params->parity;
+    auto solved = [&](int p) { return par == STAG_ALL || par == p; };
+    for (int p = 0; p < 2; ++p)
+        if (solved(p))
+            STAG_HIP_CHECK(hipMemcpyAsync(db + p * hd, b + p * hd, hb, hipMemcpyHostToDevice, s));
+    const double *bs[1] = {db};
+    double *xs[1] = {dx}, *ys[1] = {dy};
+    rc = cg_solve_batch(c, f, 1, params, bs, xs, ys, s, info);
+    // x holds the last iterate also when the solve ran and did not converge
+    const bool ran = rc == STAG_OK || rc == STAG_ENOCONV || rc == STAG_EBREAKDOWN || rc == STAG_ENONFINITE;
+    const std::string msg = rc != STAG_OK ? std::string(last_error_cstr()) : std::string();
+    for (int p = 0; p < 2 && ran; ++p) {
+        if (solved(p))
+            STAG_HIP_CHECK(hipMemcpyAsync(x + p * hd, dx + p * hd, hb, hipMemcpyDeviceToHost, s));
+        if (y && solved(1 - p))
+            STAG_HIP_CHECK(hipMemcpyAsync(y + p * hd, dy + p * hd, hb, hipMemcpyDeviceToHost, s));
+    }
+    STAG_HIP_CHECK(hipStreamSynchronize(s));
+    if (rc != STAG_OK)
+        return set_error(rc, "%s", msg.c_str());
+    return STAG_OK;
     STAG_GUARD_END
 }
 

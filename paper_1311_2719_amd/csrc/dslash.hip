@@ -1,7 +1,7 @@
-// The standalone FP64 D_slash (the paper's matrix-vector routine of Sec. 3,
+// The standalone D_slash (the paper's matrix-vector routine of Sec. 3,
 // `matrix-vector(offset, local_length, v, w)`, restricted to one parity or
-// applied to the whole lattice), the FP64 residual-recomputation hop, and the
-// kernel-configuration tuner.
+// applied to the whole lattice) in FP64, FP32 or FP16, conversion of fermion
+// fields between those storage precisions, and the kernel-configuration tuner.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -30,12 +30,17 @@ const CgLaunchTable &cg_table(int prec, int rows)
 namespace {
 
 // out(x) (+)= (D in)(x) for checkerboard sites [offset, offset + count) of the
-// output parity (blockIdx.y selects the parity when par_fixed < 0).
-template <int LPS, int ROWS>
+// output parity (blockIdx.y selects the parity when par_fixed < 0), with
+// links, vectors and arithmetic of precision P: FP64 / FP32 vectors are
+// [parity][colour][Vh] complex, FP16 vectors [parity][Vh] records of three
+// scaled half2 colours and their FP32 scale.
+template <class P, int LPS, int ROWS>
 __global__ void __launch_bounds__(256)
-k_dslash64(Geom g, const dbl2 *__restrict__ links, const int32_t *__restrict__ nbr, const dbl2 *__restrict__ in,
-           dbl2 *__restrict__ out, int par_fixed, int offset, int count, int accumulate, int remap)
+k_dslash(Geom g, const typename P::link_t *__restrict__ links, const int32_t *__restrict__ nbr,
+         const void *__restrict__ in, void *__restrict__ out, int par_fixed, int offset, int count, int accumulate,
+         int remap)
 {
+    using real = typename P::real;
     const int p = par_fixed >= 0 ? par_fixed : (int)blockIdx.y;
     const int Vh = g.Vh;
     int site, sub;
@@ -43,37 +48,76 @@ k_dslash64(Geom g, const dbl2 *__restrict__ links, const int32_t *__restrict__ n
     if (site >= count)
         return;
     const int s = offset + site;
-    const dbl2 *src = in + (size_t)(1 - p) * 3 * Vh;
-    cplx<double> acc[1][3] = {{czero<double>(), czero<double>(), czero<double>()}};
-    auto load = [&](int, int n, cplx<double> *chi) { PrecF64::load_spinor(src, Vh, n, chi); };
-    hop_accumulate<PrecF64, LPS, 1, decltype(load), false, ROWS>(g, links + link_parity_entries(ROWS, Vh) * p,
-                                                                 nbr ? nbr + (size_t)p * 8 * Vh : nullptr, p, s, sub,
-                                                                 acc, load);
-    dbl2 *o = out + (size_t)p * 3 * Vh;
+    const size_t half = (size_t)Vh * P::spinor_bytes;  // bytes of one parity half
+    const char *src = (const char *)in + (size_t)(1 - p) * half;
+    cplx<real> acc[1][3] = {{czero<real>(), czero<real>(), czero<real>()}};
+    auto load = [&](int, int n, cplx<real> *chi) { P::load_spinor(src, Vh, n, chi); };
+    hop_accumulate<P, LPS, 1, decltype(load), false, ROWS>(g, links + link_parity_entries(ROWS, Vh) * p,
+                                                           nbr ? nbr + (size_t)p * 8 * Vh : nullptr, p, s, sub, acc,
+                                                           load);
+    char *o = (char *)out + (size_t)p * half;
+    if constexpr (P::id == 2) {
+        // one lane writes the whole record (every lane holds the lane sum)
+        if (sub != 0)
+            return;
+        if (accumulate) {
+            cplx<real> old[3];
+            P::load_spinor(o, Vh, s, old);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        if (!owns_colour<LPS>(sub, c))
-            continue;
-        dbl2 v = dbl2{acc[0][c].re, acc[0][c].im};
-        if (accumulate)
-            v += o[(int64_t)c * Vh + s];
-        o[(int64_t)c * Vh + s] = v;
+            for (int c = 0; c < 3; ++c) {
+                acc[0][c].re += old[c].re;
+                acc[0][c].im += old[c].im;
+            }
+        }
+        P::store_spinor(o, Vh, s, acc[0]);
+    } else {
+        using v2 = typename vec2_of<real>::type;
+        v2 *ov = (v2 *)o;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (!owns_colour<LPS>(sub, c))
+                continue;
+            v2 v = v2{acc[0][c].re, acc[0][c].im};
+            if (accumulate)
+                v += ov[(int64_t)c * Vh + s];
+            ov[(int64_t)c * Vh + s] = v;
+        }
     }
 }
 
-}  // namespace
+// Convert a full-lattice field (both parities, 2 Vh sites) between vector
+// storage precisions: FP64 / FP32 [parity][colour][Vh] complex, FP16
+// [parity][Vh] records.  One thread per site.
+template <class PI, class PO>
+__global__ void __launch_bounds__(256) k_convert(int Vh, const void *__restrict__ in, void *__restrict__ out)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)2 * Vh)
+        return;
+    const int p = (int)(gid / Vh), s = (int)(gid % Vh);
+    const char *ib = (const char *)in + (size_t)p * Vh * PI::spinor_bytes;
+    char *ob = (char *)out + (size_t)p * Vh * PO::spinor_bytes;
+    cplx<typename PI::real> v[3];
+    PI::load_spinor(ib, Vh, s, v);
+    cplx<typename PO::real> w[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        w[c] = {(typename PO::real)v[c].re, (typename PO::real)v[c].im};
+    PO::store_spinor(ob, Vh, s, w);
+}
 
-static hipError_t launch_dslash64(const KernelCfg &cfg, const GaugeField *f, int par_fixed, int nparity, int offset,
-                                  int count, const double *in, double *out, int accumulate, hipStream_t s)
+template <class P>
+hipError_t launch_dslash_p(const KernelCfg &cfg, const GaugeField *f, int par_fixed, int nparity, int offset,
+                           int count, const void *in, void *out, int accumulate, hipStream_t s)
 {
     const int64_t threads = (int64_t)count * cfg.lps;  // site = wave * (64/lps) + lane % (64/lps)
     dim3 grid((unsigned)((threads + cfg.block - 1) / cfg.block), (unsigned)nparity);
     dim3 block(cfg.block);
-    const dbl2 *lk = (const dbl2 *)f->links[0];
+    const auto *lk = (const typename P::link_t *)f->links[P::id];
     const int32_t *nb = cfg.tables ? f->nbr : nullptr;
 #define STAG_DSLASH_CASE(L, ROWS)                                                                                    \
-    hipLaunchKernelGGL((k_dslash64<L, ROWS>), grid, block, 0, s, f->g, lk, nb, (const dbl2 *)in, (dbl2 *)out,      \
-                       par_fixed, offset, count, accumulate, cfg.remap)
+    hipLaunchKernelGGL((k_dslash<P, L, ROWS>), grid, block, 0, s, f->g, lk, nb, in, out, par_fixed, offset, count,  \
+                       accumulate, cfg.remap)
     const int key = cfg.lps * 4 + f->rows;
     switch (key) {
     case 1 * 4 + 3: STAG_DSLASH_CASE(1, 3); break;
@@ -90,18 +134,56 @@ static hipError_t launch_dslash64(const KernelCfg &cfg, const GaugeField *f, int
     return hipGetLastError();
 }
 
+}  // namespace
+
+int dslash(Ctx *ctx, GaugeField *f, int prec, int out_parity, int64_t offset, int64_t count, const void *in,
+           void *out, int accumulate, hipStream_t s)
+{
+    const KernelCfg cfg = tune_config(ctx, f, prec, 1, s);
+    const int Vh = f->g.Vh;
+    const int par_fixed = out_parity == STAG_ALL ? -1 : out_parity;
+    const int nparity = out_parity == STAG_ALL ? 2 : 1;
+    const int off = out_parity == STAG_ALL ? 0 : (int)offset;
+    const int cnt = out_parity == STAG_ALL ? Vh : (int)count;
+    hipError_t e;
+    switch (prec) {
+    case 0: e = launch_dslash_p<PrecF64>(cfg, f, par_fixed, nparity, off, cnt, in, out, accumulate, s); break;
+    case 1: e = launch_dslash_p<PrecF32>(cfg, f, par_fixed, nparity, off, cnt, in, out, accumulate, s); break;
+    case 2: e = launch_dslash_p<PrecF16>(cfg, f, par_fixed, nparity, off, cnt, in, out, accumulate, s); break;
+    default: return set_error(STAG_EINVAL, "dslash: unknown precision %d", prec);
+    }
+    if (e != hipSuccess)
+        return set_error(STAG_EHIP, "dslash launch failed: %s", hipGetErrorString(e));
+    return STAG_OK;
+}
+
 int dslash_f64(Ctx *ctx, GaugeField *f, int out_parity, int64_t offset, int64_t count, const double *in,
                double *out, int accumulate, hipStream_t s)
 {
-    const KernelCfg cfg = tune_config(ctx, f, 0, 1, s);
-    const int Vh = f->g.Vh;
-    hipError_t e;
-    if (out_parity == STAG_ALL)
-        e = launch_dslash64(cfg, f, -1, 2, 0, Vh, in, out, accumulate, s);
-    else
-        e = launch_dslash64(cfg, f, out_parity, 1, (int)offset, (int)count, in, out, accumulate, s);
+    return dslash(ctx, f, 0, out_parity, offset, count, in, out, accumulate, s);
+}
+
+int convert_fermion(const Geom &g, int prec_in, const void *in, int prec_out, void *out, hipStream_t s)
+{
+    const int64_t n = (int64_t)2 * g.Vh;
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+#define STAG_CONVERT_CASE(PI, PO) hipLaunchKernelGGL((k_convert<PI, PO>), grid, block, 0, s, g.Vh, in, out)
+    switch (prec_in * 3 + prec_out) {
+    case 0: STAG_CONVERT_CASE(PrecF64, PrecF64); break;
+    case 1: STAG_CONVERT_CASE(PrecF64, PrecF32); break;
+    case 2: STAG_CONVERT_CASE(PrecF64, PrecF16); break;
+    case 3: STAG_CONVERT_CASE(PrecF32, PrecF64); break;
+    case 4: STAG_CONVERT_CASE(PrecF32, PrecF32); break;
+    case 5: STAG_CONVERT_CASE(PrecF32, PrecF16); break;
+    case 6: STAG_CONVERT_CASE(PrecF16, PrecF64); break;
+    case 7: STAG_CONVERT_CASE(PrecF16, PrecF32); break;
+    case 8: STAG_CONVERT_CASE(PrecF16, PrecF16); break;
+    default: return set_error(STAG_EINVAL, "convert: unknown precision");
+    }
+#undef STAG_CONVERT_CASE
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess)
-        return set_error(STAG_EHIP, "dslash launch failed: %s", hipGetErrorString(e));
+        return set_error(STAG_EHIP, "convert launch failed: %s", hipGetErrorString(e));
     return STAG_OK;
 }
 

@@ -155,8 +155,14 @@ int wilson_dslash(Ctx *ctx, GaugeField *f, int out_parity, const double *in, dou
 int wilson_cg_solve(Ctx *ctx, GaugeField *f, double kappa, double tol, int maxiter, const double *b, double *x,
                     hipStream_t s, stag_cg_info *info);
 int launch_pack(const Geom &g, const double *lex, double *eo, int to_eo, hipStream_t s);
+// out (+)= D in over a site range of one parity or the whole lattice, links,
+// vectors and arithmetic in precision prec (0 FP64, 1 FP32, 2 FP16)
+int dslash(Ctx *ctx, GaugeField *f, int prec, int out_parity, int64_t offset, int64_t count, const void *in,
+           void *out, int accumulate, hipStream_t s);
 int dslash_f64(Ctx *ctx, GaugeField *f, int out_parity, int64_t offset, int64_t count,
                const double *in, double *out, int accumulate, hipStream_t s);
+// full-lattice fermion field from one storage precision to another
+int convert_fermion(const Geom &g, int prec_in, const void *in, int prec_out, void *out, hipStream_t s);
 KernelCfg tune_config(Ctx *ctx, GaugeField *f, int prec, int nrhs, hipStream_t s);
 // CG step shape tuned for (field, precision, slots), if a solve with that many
 // slots has run; reduce: whether a reduction kernel runs between the steps.

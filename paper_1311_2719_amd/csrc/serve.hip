@@ -40,8 +40,34 @@ Server::~Server()
             r.info.status = STAG_ECANCELED;
             r.field->users.fetch_sub(1);
         }
+        if (r.ready) {
+            (void)hipEventDestroy(r.ready);
+            r.ready = nullptr;
+        }
     }
+    for (hipEvent_t e : events_)
+        (void)hipEventDestroy(e);
+    events_.clear();
     cv_done_.notify_all();
+}
+
+hipEvent_t Server::take_event()
+{
+    if (!events_.empty()) {
+        hipEvent_t e = events_.back();
+        events_.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+void Server::give_event(hipEvent_t e)
+{
+    if (e)
+        events_.push_back(e);
 }
 
 int Server::submit(const std::shared_ptr<GaugeField> &f, const stag_cg_params &p, const double *b, double *x,
@@ -59,6 +85,11 @@ int Server::submit(const std::shared_ptr<GaugeField> &f, const stag_cg_params &p
             return set_error(STAG_ECANCELED, "server is shutting down");
         if (outstanding_ >= ctx_->queue_capacity)
             return set_error(STAG_EAGAIN, "request queue full (%d outstanding)", outstanding_);
+        r->ready = take_event();
+        if (!r->ready || hipEventRecord(r->ready, ctx_->stream) != hipSuccess) {
+            give_event(r->ready);
+            return set_error(STAG_EHIP, "stag_submit: could not record the ordering event");
+        }
         r->ticket = next_ticket_++;
         ++outstanding_;
         f->users.fetch_add(1);
@@ -206,10 +237,19 @@ bool Server::step_lane(Lane &l)
                 l.queue.pop_front();
                 l.slot[s] = r;
                 ++l.active;
+                // the caller's work on b and x, enqueued before submit, comes first
+                hipEvent_t ready = nullptr;
                 {
                     std::lock_guard<std::mutex> lk(mu_);
                     r->t_admit = now();
                     r->state = 1;
+                    ready = r->ready;
+                    r->ready = nullptr;
+                }
+                if (ready) {
+                    (void)hipStreamWaitEvent(l.stream, ready, 0);
+                    std::lock_guard<std::mutex> lk(mu_);
+                    give_event(ready);
                 }
                 for (int par = 0; par < 2; ++par) {
                     const bool on = r->params.parity == STAG_ALL || r->params.parity == par;
@@ -282,6 +322,8 @@ void Server::run()
                 nl->prec = r->params.precision;
                 if (hipStreamCreateWithFlags(&nl->stream, hipStreamNonBlocking) != hipSuccess) {
                     std::lock_guard<std::mutex> lk(mu_);
+                    give_event(r->ready);
+                    r->ready = nullptr;
                     r->state = 2;
                     r->info.status = STAG_EHIP;
                     --outstanding_;
@@ -308,6 +350,8 @@ void Server::run()
                         std::shared_ptr<Request> r = l->queue.front();
                         l->queue.pop_front();
                         std::lock_guard<std::mutex> lk(mu_);
+                        give_event(r->ready);
+                        r->ready = nullptr;
                         r->state = 2;
                         r->info.status = STAG_ENOMEM;
                         --outstanding_;

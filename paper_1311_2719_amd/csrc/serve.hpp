@@ -21,6 +21,9 @@ struct Request {
     double t_submit = 0, t_admit = 0, t_done = 0;
     int state = 0;  // 0 queued, 1 running, 2 done
     stag_cg_info info{};
+    // recorded on the context's stream at submit; the lane waits on it before
+    // the request's first kernel, so the caller's earlier work on b and x is done
+    hipEvent_t ready = nullptr;
 };
 
 struct Lane {
@@ -52,6 +55,8 @@ private:
     int ensure_batch(Lane &l);
     void retire(Lane &l, int slot, int status_override);
     static double now();
+    hipEvent_t take_event();            // from the pool (or a new one); caller holds mu_
+    void give_event(hipEvent_t e);      // back to the pool; caller holds mu_
 
     Ctx *ctx_;
     std::mutex mu_;
@@ -60,6 +65,7 @@ private:
     std::deque<std::shared_ptr<Request>> incoming_;
     std::vector<std::unique_ptr<Lane>> lanes_;  // touched by the scheduler thread only
     std::vector<int32_t> dropped_;
+    std::vector<hipEvent_t> events_;  // idle events for Request::ready
     uint64_t next_ticket_ = 1;
     int outstanding_ = 0;
     bool stop_ = false;

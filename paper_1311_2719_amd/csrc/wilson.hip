@@ -1,4 +1,4 @@
-// Wilson fermions (the paper's second workload, Sec. 5): gauge preparation,
+// Wilson fermions (the paper's second workload, named in Sec. 2 and Sec. 6): gauge preparation,
 // spin-colour vector layout, the standalone hop and the even-odd CG driver.
 // The operator and the kernels are described in wilson_kernels.hpp.
 #include <chrono>
@@ -426,6 +426,8 @@ int wilson_cg_solve(Ctx *ctx, GaugeField *f, double kappa, double tol, int maxit
     memset(&inf, 0, sizeof(inf));
     inf.status = last.mode == wil::W_DONE ? last.status : STAG_ENOCONV;
     inf.iters = last.iters;
+    inf.iters_parity[0] = last.iters;  // the CG runs on the even sites
+    inf.iters_parity[1] = -1;
     inf.true_rel_resid = bb > 0 ? std::sqrt(res2 / bb) : 0.0;
     inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info)

@@ -1,7 +1,7 @@
 // Wilson-fermion kernels: the hopping term H of M = 1 - kappa H and the fused
 // even-odd CG on Mhat^dagger Mhat, Mhat = 1 - kappa^2 D_eo D_oe (FP64).
 //
-// The paper's second workload is an N_f = 2 Wilson-fermion program (Sec. 5);
+// The paper's second workload is an N_f = 2 Wilson-fermion program (Sec. 2, Sec. 6);
 // it does not write the operator out, so the textbook form is used:
 //   (H psi)(x) = sum_mu [(1 - gamma_mu) W_mu(x) psi(x + mu) + (1 + gamma_mu) B_mu(x) psi(x - mu)],
 //   W_mu(x) = s U_mu(x), B_mu(x) = s U_mu(x - mu)^dagger (s: the t-boundary sign),

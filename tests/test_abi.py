@@ -52,10 +52,27 @@ def test_binding_covers_the_header(lib_path):
     assert binding.version().startswith("stagcg")
 
 
-def test_struct_layouts_match_header():
-    # stag_cg_params: 2 doubles, 4 int32, 1 double = 40 bytes; stag_cg_info: 4 int32 + 3 doubles = 40
-    assert ctypes.sizeof(binding.CGParams) == 40
-    assert ctypes.sizeof(binding.CGInfo) == 40
+def test_struct_layouts_match_header(tmp_path):
+    # sizes and field offsets of the ABI structs as a C compiler lays them out
+    # from the header, against the binding's ctypes mirrors
+    fields = {"stag_cg_params": [n for n, _ in binding.CGParams._fields_],
+              "stag_cg_info": [n for n, _ in binding.CGInfo._fields_]}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "stagcg.h"', "int main(void) {"]
+    for st, names in fields.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (st, st))
+        for n in names:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (st, n, st, n))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                       check=True).stdout.splitlines())
+    for st, cls in (("stag_cg_params", binding.CGParams), ("stag_cg_info", binding.CGInfo)):
+        assert int(got[st]) == ctypes.sizeof(cls), st
+        for n, _ in cls._fields_:
+            assert int(got["%s.%s" % (st, n)]) == getattr(cls, n).offset, (st, n)
 
 
 def test_error_paths_without_gpu(lib_path):
@@ -63,5 +80,5 @@ def test_error_paths_without_gpu(lib_path):
     h = ctypes.c_void_p()
     # NULL arena is rejected before any device call
     assert lib.stag_create(0, None, 1 << 30, None, ctypes.byref(h)) == binding.EINVAL
-    assert b"arena" in lib.stag_last_error()
+    assert b"arena" in lib.stag_last_error(None)
     assert lib.stag_destroy(None) == binding.EINVAL

@@ -1,6 +1,6 @@
 """Pins of the Wilson-fermion oracle against facts fixed by the mathematics.
 
-The paper runs an N_f = 2 Wilson-fermion program (Sec. 5) without writing the
+The paper runs an N_f = 2 Wilson-fermion program (Sec. 2, Sec. 6) without writing the
 operator out; the oracle takes the textbook M = 1 - kappa H (see
 oracle/wilson_oracle.c).  None of these checks re-calls the oracle's own
 routine as its reference:
