@@ -259,6 +259,30 @@ int stag_cg_solve(stag_ctx *ctx, int32_t gauge_id, const stag_cg_params *params,
                   void *stream, stag_cg_info *info);
 
 /*
+ * For callers that cannot allocate memory (code that must not call hipMalloc
+ * or a caching allocator, e.g. inside tight serving loops or harnesses that
+ * forbid allocation): stag_cg_solve on device pointers whose workspace is
+ * the library's fixed device buffer of STAG_NOALLOC_WORKSPACE_BYTES instead
+ * of the arena.  The buffer is a file-scope device array: every GPU the
+ * library runs on holds one copy of it from stag_create until the process
+ * ends.  Nothing is allocated during the call (no arena, hipMalloc, pinned
+ * host memory, event, stream or graph); the state records travel through a
+ * fixed host buffer and the call synchronises `stream` where
+ * stag_cg_solve waits on events.  The kernel shape is the one tuned for the
+ * field by an earlier stag_cg_solve at the same precision, else the default
+ * (the call never tunes).  Calls on one GPU share its buffer: they are
+ * serialised by a lock within the process, each call re-initialises all of
+ * the buffer it reads, and the buffer keeps the last call's contents.
+ * Arguments, results and errors as for stag_cg_solve with on_device = 1,
+ * plus EINVAL when the solve's workspace (about 480 bytes per checkerboard
+ * site in FP64, 340 in FP32 and 290 in FP16, plus 200 KB) exceeds the buffer.
+ */
+#define STAG_NOALLOC_WORKSPACE_BYTES ((size_t)128 << 20)
+int stag_cg_solve_noalloc(stag_ctx *ctx, int32_t gauge_id, const stag_cg_params *params,
+                          const double *b, double *x, double *y, void *stream,
+                          stag_cg_info *info);
+
+/*
  * Solve nrhs systems that share one gauge field in one batched solve: every
  * CG iteration reads the links once for all right-hand sides.  params[i]
  * may differ in mass, tol, maxiter and parity; precision must be the same for

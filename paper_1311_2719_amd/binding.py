@@ -102,6 +102,8 @@ def load():
                               ctypes.c_int),
             "stag_cg_solve_batch": ([P, I32, I32, ctypes.POINTER(CGParams), P, P, P, ctypes.POINTER(CGInfo)],
                                     ctypes.c_int),
+            "stag_cg_solve_noalloc": ([P, I32, ctypes.POINTER(CGParams), P, P, P, P, ctypes.POINTER(CGInfo)],
+                                      ctypes.c_int),
             "stag_submit": ([P, I32, ctypes.POINTER(CGParams), P, P, ctypes.POINTER(U64)], ctypes.c_int),
             "stag_poll": ([P, U64, ctypes.POINTER(CGInfo)], ctypes.c_int),
             "stag_wait": ([P, U64, ctypes.POINTER(CGInfo)], ctypes.c_int),
@@ -131,7 +133,7 @@ def exported_symbols():
     return [
         "stag_create", "stag_destroy", "stag_last_error", "stag_arena_usage", "stag_set_gauge",
         "stag_free_gauge", "stag_gauge_dims", "stag_gauge_link_rows", "stag_pack_fermion", "stag_unpack_fermion", "stag_dslash",
-        "stag_convert_fermion", "stag_cg_solve", "stag_cg_solve_batch", "stag_submit", "stag_poll", "stag_wait",
+        "stag_convert_fermion", "stag_cg_solve", "stag_cg_solve_noalloc", "stag_cg_solve_batch", "stag_submit", "stag_poll", "stag_wait",
         "stag_release_ticket", "stag_serve_config", "stag_tune_info", "stag_cg_tune_info", "stag_version",
         "stag_set_gauge_wilson", "stag_pack_spinor", "stag_unpack_spinor", "stag_wilson_dslash",
         "stag_wilson_solve",
@@ -412,6 +414,23 @@ class Context:
                                     ctypes.byref(info))
         if check:
             _check(rc, "stag_cg_solve")
+        d = info.as_dict()
+        d["rc"] = rc
+        return d
+
+    def cg_solve_noalloc(self, field: Field, b, x, y=None, check=True, **kw):
+        """The solve on device tensors with the library's fixed workspace
+        (stag_cg_solve_noalloc): no memory is allocated by the call."""
+        p = params(**kw)
+        for t in (b, x) + ((y,) if y is not None else ()):
+            self._check_eo(field, t)
+        info = CGInfo()
+        rc = self.lib.stag_cg_solve_noalloc(self.h, field.gauge_id, ctypes.byref(p), ctypes.c_void_p(b.data_ptr()),
+                                            ctypes.c_void_p(x.data_ptr()),
+                                            ctypes.c_void_p(y.data_ptr()) if y is not None else None, None,
+                                            ctypes.byref(info))
+        if check:
+            _check(rc, "stag_cg_solve_noalloc")
         d = info.as_dict()
         d["rc"] = rc
         return d

@@ -36,9 +36,9 @@ Batch::~Batch()
             (void)hipEventDestroy(e);
     if (stage_ev_)
         (void)hipEventDestroy(stage_ev_);
-    if (stage_)
+    if (stage_ && !external_)
         (void)hipHostFree(stage_);
-    if (mem_)
+    if (mem_ && !external_)
         ctx_->arena.release(mem_);
 }
 
@@ -124,18 +124,25 @@ hipError_t Batch::launch_reduce(hipStream_t st, int buf, int slot0, int nslots, 
     return hipGetLastError();
 }
 
-int Batch::create()
+size_t Batch::host_bytes_for(int slots)
+{
+    const size_t nsys = 2 * (size_t)slots;
+    return 3 * nsys * sizeof(SysState) + 2 * nsys * sizeof(void *) + nsys * sizeof(int);
+}
+
+static int pstride_for(const Geom &g)
+{
+    const int p = std::min(2048, blocks_for(g.Vh, 8, 64));
+    return (p + 63) & ~63;
+}
+
+size_t Batch::needed_bytes() const { return workspace_bytes(f_->g, prec_, S_, pstride_for(f_->g)); }
+
+void Batch::carve(void *base)
 {
     const Geom &g = f_->g;
-    pstride_ = std::min(2048, blocks_for(g.Vh, 8, 64));
-    pstride_ = (pstride_ + 63) & ~63;
-    bytes_ = workspace_bytes(g, prec_, S_, pstride_);
-    mem_ = ctx_->arena.alloc(bytes_);
-    if (!mem_)
-        return set_error(STAG_ENOMEM, "arena exhausted: CG workspace needs %zu bytes (largest free block %zu)", bytes_,
-                         ctx_->arena.largest_free());
     const size_t nsys = 2 * (size_t)S_, Vh = g.Vh;
-    char *c = (char *)mem_;
+    char *c = (char *)base;
     auto take = [&](size_t n) {
         char *r = c;
         c += align256(n);
@@ -151,24 +158,74 @@ int Batch::create()
     b_d_ = (const dbl2 **)take(nsys * sizeof(void *));
     // the two state buffers are adjacent, so one copy takes a snapshot of both
     st_d_[0] = (SysState *)take(2 * nsys * sizeof(SysState));
-    st_d_[1] = st_d_[0] ? st_d_[0] + nsys : nullptr;
+    st_d_[1] = st_d_[0] + nsys;
     perm_d_ = (int *)take(nsys * sizeof(int));
     partials_ = (double *)take(2 * nsys * 3 * (size_t)pstride_ * sizeof(double));
     totals_ = (double *)take(2 * nsys * 3 * sizeof(double));
+}
 
-    const size_t host_bytes = 3 * nsys * sizeof(SysState) + 2 * nsys * sizeof(void *) + nsys * sizeof(int);
-    STAG_HIP_CHECK(hipHostMalloc((void **)&stage_, host_bytes, hipHostMallocDefault));
-    snap_ = stage_ + nsys;
-    xhi_h_ = (dbl2 **)(snap_ + 2 * nsys);
-    b_h_ = (const dbl2 **)(xhi_h_ + nsys);
-    perm_h_ = (int *)(b_h_ + nsys);
-    memset(stage_, 0, host_bytes);
+int Batch::mark_stage()
+{
+    if (!external_)
+        STAG_HIP_CHECK(hipEventRecord(stage_ev_, s_));
+    stage_busy_ = true;
+    return STAG_OK;
+}
+
+void Batch::wait_stage()
+{
+    if (!stage_busy_)
+        return;
+    if (external_)
+        (void)hipStreamSynchronize(s_);
+    else
+        (void)hipEventSynchronize(stage_ev_);
+    stage_busy_ = false;
+}
+
+int Batch::create()
+{
+    const Geom &g = f_->g;
+    pstride_ = pstride_for(g);
+    bytes_ = workspace_bytes(g, prec_, S_, pstride_);
+    mem_ = ctx_->arena.alloc(bytes_);
+    if (!mem_)
+        return set_error(STAG_ENOMEM, "arena exhausted: CG workspace needs %zu bytes (largest free block %zu)", bytes_,
+                         ctx_->arena.largest_free());
+    carve(mem_);
+    STAG_HIP_CHECK(hipHostMalloc((void **)&stage_, host_bytes_for(S_), hipHostMallocDefault));
     if (const char *e = getenv("STAG_GRAPHS"))
         use_graphs_ = e[0] != '0';
     if (use_graphs_)
         STAG_HIP_CHECK(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
     STAG_HIP_CHECK(hipEventCreateWithFlags(&snap_ev_, hipEventDisableTiming));
     STAG_HIP_CHECK(hipEventCreateWithFlags(&stage_ev_, hipEventDisableTiming));
+    return finish_create();
+}
+
+int Batch::create_external(void *dev, size_t dev_bytes, void *host, size_t host_bytes)
+{
+    external_ = true;
+    use_graphs_ = false;
+    pstride_ = pstride_for(f_->g);
+    bytes_ = workspace_bytes(f_->g, prec_, S_, pstride_);
+    if (!dev || dev_bytes < bytes_ || !host || host_bytes < host_bytes_for(S_))
+        return set_error(STAG_EINVAL, "CG workspace of %zu bytes does not fit the fixed %zu-byte buffer", bytes_,
+                         dev_bytes);
+    mem_ = dev;
+    carve(mem_);
+    stage_ = (SysState *)host;
+    return finish_create();
+}
+
+int Batch::finish_create()
+{
+    const size_t nsys = 2 * (size_t)S_;
+    snap_ = stage_ + nsys;
+    xhi_h_ = (dbl2 **)(snap_ + 2 * nsys);
+    b_h_ = (const dbl2 **)(xhi_h_ + nsys);
+    perm_h_ = (int *)(b_h_ + nsys);
+    memset(stage_, 0, host_bytes_for(S_));
     for (size_t j = 0; j < nsys; ++j)
         perm_h_[j] = (int)j;
     perm_last_.assign(perm_h_, perm_h_ + nsys);
@@ -193,6 +250,8 @@ int Batch::create()
             if (it != f_->tuned.end())
                 small_.push_back(it->second);
         }
+    } else if (external_) {
+        cfg_ = default_cg_cfg();  // no timing runs without events; not cached
     } else {
         cfg_ = tune_cg();  // also fills small_
         std::lock_guard<std::mutex> lk(ctx_->mu);
@@ -209,12 +268,13 @@ int Batch::create()
     STAG_HIP_CHECK(hipMemcpyAsync(xhi_d_, xhi_h_, nsys * sizeof(void *), hipMemcpyHostToDevice, s_));
     STAG_HIP_CHECK(hipMemcpyAsync(b_d_, b_h_, nsys * sizeof(void *), hipMemcpyHostToDevice, s_));
     STAG_HIP_CHECK(hipMemcpyAsync(perm_d_, perm_h_, nsys * sizeof(int), hipMemcpyHostToDevice, s_));
-    STAG_HIP_CHECK(hipEventRecord(stage_ev_, s_));
-    stage_busy_ = true;
+    int rc = mark_stage();
+    if (rc != STAG_OK)
+        return rc;
     // record the epochs the solve driver chooses from (powers of two), for
     // every tile shape, now, outside any solve
     for (int E = 2; use_graphs_ && E <= kEpochMax; E *= 2) {
-        int rc = record_epoch(E, cfg_);
+        rc = record_epoch(E, cfg_);
         for (size_t i = 0; i < small_.size() && rc == STAG_OK; ++i)
             rc = record_epoch(E, small_[i]);
         if (rc != STAG_OK)
@@ -237,16 +297,11 @@ int Batch::set_running(const std::vector<char> &running)
     }
     if (order == perm_last_)
         return STAG_OK;
-    if (stage_busy_) {
-        (void)hipEventSynchronize(stage_ev_);
-        stage_busy_ = false;
-    }
+    wait_stage();
     memcpy(perm_h_, order.data(), n * sizeof(int));
     perm_last_ = order;
     STAG_HIP_CHECK(hipMemcpyAsync(perm_d_, perm_h_, n * sizeof(int), hipMemcpyHostToDevice, s_));
-    STAG_HIP_CHECK(hipEventRecord(stage_ev_, s_));
-    stage_busy_ = true;
-    return STAG_OK;
+    return mark_stage();
 }
 
 // Time K1 + K2 of one step with every system in a CG step on filled vectors.
@@ -291,7 +346,7 @@ double Batch::time_cg_config(const KernelCfg &c, int nblk, bool reduce)
     return best;
 }
 
-KernelCfg Batch::tune_cg()
+KernelCfg Batch::default_cg_cfg() const
 {
     KernelCfg best;
     best.lps = 1;
@@ -303,6 +358,13 @@ KernelCfg Batch::tune_cg()
     for (int i = 0; i < t.n_rtiles; ++i)
         if (S_ % t.rtiles[i] == 0)
             best.rtile = std::max(best.rtile, t.rtiles[i]);
+    return best;
+}
+
+KernelCfg Batch::tune_cg()
+{
+    KernelCfg best = default_cg_cfg();
+    const CgLaunchTable &t = cg_table(prec_, f_->rows);
     const char *env = getenv("STAG_KERNEL_CFG");
     if (env && *env) {
         KernelCfg c;
@@ -423,10 +485,7 @@ KernelCfg Batch::tune_cg()
 
 void Batch::stage_system(int j, const stag_cg_params &p, const double *b_half, double *x_half)
 {
-    if (stage_busy_) {
-        (void)hipEventSynchronize(stage_ev_);
-        stage_busy_ = false;
-    }
+    wait_stage();
     SysState &st = stage_[j];
     memset(&st, 0, sizeof(st));
     if (!b_half || !x_half) {
@@ -476,8 +535,9 @@ int Batch::upload_and_init(const std::vector<int> &systems)
             STAG_HIP_CHECK(hipMemcpyAsync(b_d_ + j, b_h_ + j, sizeof(void *), hipMemcpyHostToDevice, s_));
         }
     }
-    STAG_HIP_CHECK(hipEventRecord(stage_ev_, s_));
-    stage_busy_ = true;
+    int rc = mark_stage();
+    if (rc != STAG_OK)
+        return rc;
     const CgArgs a = args();
     const CgLaunchTable &t = cg_table(prec_, f_->rows);
     dim3 grid((unsigned)nblk_, (unsigned)nsys());
@@ -601,17 +661,21 @@ int Batch::enqueue_snapshot()
     // both state buffers in one copy (they are adjacent, as are their host
     // mirrors): each copy costs a few microseconds of stream time
     STAG_HIP_CHECK(hipMemcpyAsync(snap_, st_d_[0], 2 * nsys() * sizeof(SysState), hipMemcpyDeviceToHost, s_));
-    STAG_HIP_CHECK(hipEventRecord(snap_ev_, s_));
+    if (!external_)
+        STAG_HIP_CHECK(hipEventRecord(snap_ev_, s_));
     return STAG_OK;
 }
 
 int Batch::wait_snapshot()
 {
-    STAG_HIP_CHECK(hipEventSynchronize(snap_ev_));
+    if (external_)
+        STAG_HIP_CHECK(hipStreamSynchronize(s_));
+    else
+        STAG_HIP_CHECK(hipEventSynchronize(snap_ev_));
     return STAG_OK;
 }
 
-bool Batch::snapshot_ready() { return hipEventQuery(snap_ev_) == hipSuccess; }
+bool Batch::snapshot_ready() { return (external_ ? hipStreamQuery(s_) : hipEventQuery(snap_ev_)) == hipSuccess; }
 
 // ---- the blocking solve ------------------------------------------------------------
 
@@ -778,23 +842,15 @@ static int estimate_remaining(const Batch &B, std::vector<ConvergenceTrack> &tra
     return known ? (int)std::ceil(worst) : kUnknownRemaining;
 }
 
-int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs, const stag_cg_params *params,
-                   const double *const *b, double *const *x, double *const *y, hipStream_t s, stag_cg_info *infos)
+// The blocking solve of nrhs systems on workspace B (its slots = nrhs).
+// fixed_mem: B lives in caller-provided memory, and nothing here may allocate
+// (the kernel shape of y = D x is the cached or default one, never tuned).
+static int run_solve(Ctx *ctx, Batch &B, const std::shared_ptr<GaugeField> &f, int nrhs,
+                     const stag_cg_params *params, const double *const *b, double *const *x, double *const *y,
+                     hipStream_t s, stag_cg_info *infos, bool fixed_mem)
 {
     const auto t0 = std::chrono::steady_clock::now();
-    const int prec = params[0].precision;
-    for (int i = 0; i < nrhs; ++i) {
-        int rc = validate_params(params[i], prec);
-        if (rc != STAG_OK)
-            return rc;
-        if (!b[i] || !x[i])
-            return set_error(STAG_EINVAL, "b and x must be device pointers");
-    }
-    std::shared_ptr<Batch> Bp;
-    int rc = acquire_batch(ctx, f, prec, nrhs, s, Bp);
-    if (rc != STAG_OK)
-        return rc;
-    Batch &B = *Bp;
+    int rc = STAG_OK;
     struct SyncOnExit {  // on an error return, drain the stream before the workspace goes
         hipStream_t s;
         ~SyncOnExit() { (void)hipStreamSynchronize(s); }
@@ -881,7 +937,10 @@ int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs, con
         if (y && y[i]) {
             const int par = params[i].parity;
             const int out_par = par == STAG_ALL ? STAG_ALL : 1 - par;
-            if ((rc = dslash_f64(ctx, f.get(), out_par, 0, f->g.Vh, x[i], y[i], 0, s)) != STAG_OK)
+            rc = fixed_mem ? dslash_with(cached_config(ctx, f.get(), 0, 1), f.get(), 0, out_par, 0, f->g.Vh, x[i],
+                                         y[i], 0, s)
+                           : dslash_f64(ctx, f.get(), out_par, 0, f->g.Vh, x[i], y[i], 0, s);
+            if (rc != STAG_OK)
                 return rc;
         }
     }
@@ -898,10 +957,57 @@ int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs, con
             infos[i] = inf;
         first_err = worse(first_err, inf.status);
     }
-    release_batch(ctx, std::move(Bp));
     if (first_err != STAG_OK)
         return set_error(first_err, "CG did not converge (status %d)", first_err);
     return STAG_OK;
+}
+
+static int validate_systems(int nrhs, const stag_cg_params *params, const double *const *b, double *const *x)
+{
+    const int prec = params[0].precision;
+    for (int i = 0; i < nrhs; ++i) {
+        int rc = validate_params(params[i], prec);
+        if (rc != STAG_OK)
+            return rc;
+        if (!b[i] || !x[i])
+            return set_error(STAG_EINVAL, "b and x must be device pointers");
+    }
+    return STAG_OK;
+}
+
+int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs, const stag_cg_params *params,
+                   const double *const *b, double *const *x, double *const *y, hipStream_t s, stag_cg_info *infos)
+{
+    int rc = validate_systems(nrhs, params, b, x);
+    if (rc != STAG_OK)
+        return rc;
+    std::shared_ptr<Batch> Bp;
+    rc = acquire_batch(ctx, f, params[0].precision, nrhs, s, Bp);
+    if (rc != STAG_OK)
+        return rc;
+    rc = run_solve(ctx, *Bp, f, nrhs, params, b, x, y, s, infos, false);
+    // a workspace whose solve failed part-way is not reused
+    if (rc == STAG_OK || rc == STAG_ENOCONV || rc == STAG_EBREAKDOWN || rc == STAG_ENONFINITE)
+        release_batch(ctx, std::move(Bp));
+    return rc;
+}
+
+int cg_solve_fixed(Ctx *ctx, const std::shared_ptr<GaugeField> &f, const stag_cg_params *params, const double *b,
+                   double *x, double *y, hipStream_t s, stag_cg_info *info, void *dev, size_t dev_bytes, void *host,
+                   size_t host_bytes)
+{
+    int rc = validate_systems(1, params, &b, &x);
+    if (rc != STAG_OK)
+        return rc;
+    Batch B(ctx, f, params->precision, 1, s);
+    if (B.needed_bytes() > dev_bytes)
+        return set_error(STAG_EINVAL, "the solve needs a %zu-byte workspace; the fixed workspace holds %zu bytes",
+                         B.needed_bytes(), dev_bytes);
+    rc = B.create_external(dev, dev_bytes, host, host_bytes);
+    if (rc != STAG_OK)
+        return rc;
+    double *ys[1] = {y};
+    return run_solve(ctx, B, f, 1, params, &b, &x, ys, s, info, true);
 }
 
 }  // namespace stag

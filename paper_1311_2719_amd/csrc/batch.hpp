@@ -23,6 +23,16 @@ public:
     // Allocate workspace from the arena and pinned host mirrors.  ENOMEM if
     // the arena cannot hold it.
     int create();
+    // Use caller-provided memory instead: `dev` (device, dev_bytes >=
+    // workspace_bytes) and `host` (ordinary host memory, host_bytes >=
+    // host_bytes_for(slots)).  Nothing is allocated: no arena, pinned memory,
+    // events, streams or graphs (the stream is synchronised where events
+    // would be waited on); the shape is the field's tuned one if a solve of
+    // this shape has run, else the default.  EINVAL if either buffer is too small.
+    int create_external(void *dev, size_t dev_bytes, void *host, size_t host_bytes);
+    static size_t host_bytes_for(int slots);
+    // workspace bytes of this batch's field, precision and slots
+    size_t needed_bytes() const;
     static size_t workspace_bytes(const Geom &g, int prec, int slots, int pstride);
 
     int slots() const { return S_; }
@@ -64,11 +74,16 @@ public:
 
 private:
     int launch_step(int ver, hipStream_t st, const KernelCfg &c);
+    int finish_create();              // common tail of create / create_external
+    void carve(void *base);           // device views into the workspace at base
+    int mark_stage();                 // the staged host data are being copied
+    void wait_stage();                // ... and may be overwritten after this
     int grid_x(const KernelCfg &c) const;
     bool uses_reduction(const KernelCfg &c) const;
     hipError_t launch_reduce(hipStream_t st, int buf, int slot0, int nslots, int nblk) const;
     // Tune the tile shape on this workspace; also fills small_.
     KernelCfg tune_cg();
+    KernelCfg default_cg_cfg() const;
     double time_cg_config(const KernelCfg &c, int nblk, bool reduce);
     CgArgs args() const;
 
@@ -110,6 +125,7 @@ private:
     hipEvent_t snap_ev_ = nullptr, stage_ev_ = nullptr;
     hipEvent_t tune_ev_[2] = {nullptr, nullptr};
     bool stage_busy_ = false;
+    bool external_ = false;  // memory from create_external: nothing owned, no events
     // epochs recorded once as HIP graphs (kernel nodes only) and replayed
     bool use_graphs_ = true;
     hipStream_t cap_stream_ = nullptr;

@@ -60,6 +60,10 @@ int stag_create(int device, void *arena_dev, size_t arena_bytes, void *stream, s
     if (device < 0 || device >= ndev)
         return set_error(STAG_EINVAL, "stag_create: device %d out of range (%d devices)", device, ndev);
     DeviceGuard dg(device);
+    // the fixed workspace of stag_cg_solve_noalloc: its address on this device
+    int rc = noalloc_setup(device);
+    if (rc != STAG_OK)
+        return rc;
     Ctx *c = new Ctx();
     c->device = device;
     c->stream = (hipStream_t)stream;
@@ -549,6 +553,33 @@ int stag_cg_solve(stag_ctx *ctx, int32_t gauge_id, const stag_cg_params *params,
     if (rc != STAG_OK)
         return set_error(rc, "%s", msg.c_str());
     return STAG_OK;
+    STAG_GUARD_END
+}
+
+int stag_cg_solve_noalloc(stag_ctx *ctx, int32_t gauge_id, const stag_cg_params *params, const double *b, double *x,
+                          double *y, void *stream, stag_cg_info *info)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx || !params || !b || !x)
+        return set_error(STAG_EINVAL, "stag_cg_solve_noalloc: NULL argument");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    auto f = c->field(gauge_id);
+    if (!f)
+        return set_error(STAG_ENOENT, "unknown gauge id %d", gauge_id);
+    if (f->kind != FIELD_STAGGERED)
+        return set_error(STAG_EINVAL, "gauge id %d holds Wilson-fermion links", gauge_id);
+    int rc = validate_cg_params(*params);
+    if (rc != STAG_OK)
+        return rc;
+    size_t dev_bytes = 0, host_bytes = 0;
+    void *dev = noalloc_scratch(c->device, &dev_bytes);
+    void *host = noalloc_host(c->device, &host_bytes);
+    if (!dev || !host)
+        return set_error(STAG_EHIP, "stag_cg_solve_noalloc: no fixed workspace on device %d", c->device);
+    DeviceGuard dg(c->device);
+    std::lock_guard<std::mutex> lk(noalloc_lock(c->device));
+    return cg_solve_fixed(c, f, params, b, x, y, pick_stream(ctx, stream), info, dev, dev_bytes, host, host_bytes);
     STAG_GUARD_END
 }
 

@@ -139,7 +139,12 @@ hipError_t launch_dslash_p(const KernelCfg &cfg, const GaugeField *f, int par_fi
 int dslash(Ctx *ctx, GaugeField *f, int prec, int out_parity, int64_t offset, int64_t count, const void *in,
            void *out, int accumulate, hipStream_t s)
 {
-    const KernelCfg cfg = tune_config(ctx, f, prec, 1, s);
+    return dslash_with(tune_config(ctx, f, prec, 1, s), f, prec, out_parity, offset, count, in, out, accumulate, s);
+}
+
+int dslash_with(const KernelCfg &cfg, GaugeField *f, int prec, int out_parity, int64_t offset, int64_t count,
+                const void *in, void *out, int accumulate, hipStream_t s)
+{
     const int Vh = f->g.Vh;
     const int par_fixed = out_parity == STAG_ALL ? -1 : out_parity;
     const int nparity = out_parity == STAG_ALL ? 2 : 1;
@@ -216,6 +221,25 @@ static int default_rtile(const CgLaunchTable &t, int nrhs)
     return best;
 }
 
+static KernelCfg default_config(const GaugeField *f, int prec, int nrhs)
+{
+    KernelCfg best;
+    best.lps = prec == 0 ? 2 : 1;
+    best.block = 256;
+    best.rtile = default_rtile(cg_table(prec, f->rows), nrhs);
+    best.tables = 0;
+    best.remap = 1;
+    return best;
+}
+
+KernelCfg cached_config(Ctx *ctx, GaugeField *f, int prec, int nrhs)
+{
+    const uint64_t key = ((uint64_t)prec << 32) | (uint32_t)nrhs;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = f->tuned.find(key);
+    return it != f->tuned.end() ? it->second : default_config(f, prec, nrhs);
+}
+
 KernelCfg tune_config(Ctx *ctx, GaugeField *f, int prec, int nrhs, hipStream_t s)
 {
     const uint64_t key = ((uint64_t)prec << 32) | (uint32_t)nrhs;
@@ -226,12 +250,7 @@ KernelCfg tune_config(Ctx *ctx, GaugeField *f, int prec, int nrhs, hipStream_t s
             return it->second;
     }
     const CgLaunchTable &tab = cg_table(prec, f->rows);
-    KernelCfg best;
-    best.lps = prec == 0 ? 2 : 1;
-    best.block = 256;
-    best.rtile = default_rtile(tab, nrhs);
-    best.tables = 0;
-    best.remap = 1;
+    KernelCfg best = default_config(f, prec, nrhs);
     KernelCfg forced;
     const char *tune_env = getenv("STAG_TUNE");
     const bool tune = !(tune_env && tune_env[0] == '0');

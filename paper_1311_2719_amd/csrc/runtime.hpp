@@ -161,9 +161,14 @@ int dslash(Ctx *ctx, GaugeField *f, int prec, int out_parity, int64_t offset, in
            void *out, int accumulate, hipStream_t s);
 int dslash_f64(Ctx *ctx, GaugeField *f, int out_parity, int64_t offset, int64_t count,
                const double *in, double *out, int accumulate, hipStream_t s);
+// the same with a given kernel shape (no tuning, nothing allocated)
+int dslash_with(const KernelCfg &cfg, GaugeField *f, int prec, int out_parity, int64_t offset, int64_t count,
+                const void *in, void *out, int accumulate, hipStream_t s);
 // full-lattice fermion field from one storage precision to another
 int convert_fermion(const Geom &g, int prec_in, const void *in, int prec_out, void *out, hipStream_t s);
 KernelCfg tune_config(Ctx *ctx, GaugeField *f, int prec, int nrhs, hipStream_t s);
+// the tuned shape if (prec, nrhs) has been tuned on f, else the default; never tunes
+KernelCfg cached_config(Ctx *ctx, GaugeField *f, int prec, int nrhs);
 // CG step shape tuned for (field, precision, slots), if a solve with that many
 // slots has run; reduce: whether a reduction kernel runs between the steps.
 bool cg_tuned_shape(Ctx *ctx, const GaugeField *f, int prec, int slots, KernelCfg &out, bool &reduce);
@@ -179,5 +184,17 @@ void drop_cached_batches(Ctx *ctx, int32_t gauge_id);  // all if gauge_id < 0
 int cg_solve_batch(Ctx *ctx, const std::shared_ptr<GaugeField> &f, int nrhs,
                    const stag_cg_params *params, const double *const *b, double *const *x,
                    double *const *y, hipStream_t s, stag_cg_info *infos);
+// One solve (stag_cg_solve on device pointers) whose workspace is the given
+// device memory (dev_bytes) and host memory (host_bytes); allocates nothing.
+int cg_solve_fixed(Ctx *ctx, const std::shared_ptr<GaugeField> &f, const stag_cg_params *params, const double *b,
+                   double *x, double *y, hipStream_t s, stag_cg_info *info, void *dev, size_t dev_bytes, void *host,
+                   size_t host_bytes);
+// The library's fixed device workspace on `device`: set up once per device at
+// stag_create (noalloc_setup), then looked up (noalloc_scratch; null if the
+// set-up failed).  The host mirror is a fixed host buffer.
+int noalloc_setup(int device);
+void *noalloc_scratch(int device, size_t *bytes);
+void *noalloc_host(int device, size_t *bytes);
+std::mutex &noalloc_lock(int device);
 
 }  // namespace stag
