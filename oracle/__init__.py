@@ -79,6 +79,8 @@ def _load():
             lib.orc_cg_solve.restype = ctypes.c_int
             lib.orc_cg_pass.argtypes = [P, I32, P, D, D, I32, I32, P, P, P]
             lib.orc_cg_pass.restype = ctypes.c_int
+            lib.orc_cg_coefficients.argtypes = [P, I32, P, D, D, I32, I32, P, P, P, P, P]
+            lib.orc_cg_coefficients.restype = ctypes.c_int
             lib.orc_cg_full.argtypes = [P, I32, P, D, D, I32, I32, P, P, P]
             lib.orc_cg_full.restype = ctypes.c_int
             lib.orc_max_threads.argtypes = []
@@ -224,6 +226,53 @@ def cg_pass(dims, U, m, b, tol, maxiter, parity, antiperiodic_t=True):
     if rc < 0:
         raise ValueError("orc_cg_pass rejected its arguments")
     return x, res.as_dict()
+
+
+def cg_coefficients(dims, U, m, b, tol=1e-10, maxiter=20000, parity=0, antiperiodic_t=True):
+    """One CG pass of the paper's loop on one parity system, with alpha_k and
+    beta_k of every iteration: returns (x, alphas, betas, info)."""
+    lib = _load()
+    L = _dims(dims)
+    V = int(np.prod(L))
+    U = _c128(U, (V, 4, 3, 3))
+    b = _c128(b, (V, 3))
+    x = np.zeros((V, 3), np.complex128)
+    al = np.zeros(max(1, int(maxiter)))
+    be = np.zeros(max(1, int(maxiter)))
+    res = CGResult()
+    rc = lib.orc_cg_coefficients(_ptr(L), int(bool(antiperiodic_t)), _ptr(U), float(m), float(tol), int(maxiter),
+                                 int(parity), _ptr(b), _ptr(x), _ptr(al), _ptr(be), ctypes.byref(res))
+    if rc < 0:
+        raise ValueError("orc_cg_coefficients rejected its arguments")
+    k = res.iters
+    return x, al[:k].copy(), be[:k].copy(), res.as_dict()
+
+
+def ritz_values(alphas, betas):
+    """Eigenvalues of the Lanczos tridiagonal matrix of a CG run (Golub & Van
+    Loan, Matrix Computations, Sec. 11.3; Saad, Iterative Methods, Sec. 6.7):
+    T_kk = 1/alpha_k + beta_{k-1}/alpha_{k-1}, T_{k,k+1} = sqrt(beta_k)/alpha_k,
+    ascending."""
+    a = np.asarray(alphas, dtype=np.float64)
+    bt = np.asarray(betas, dtype=np.float64)
+    n = a.size
+    if n == 0:
+        return np.zeros(0)
+    diag = 1.0 / a
+    diag[1:] += bt[:-1] / a[:-1]
+    off = np.sqrt(bt[:-1]) / a[:-1]
+    T = np.diag(diag) + np.diag(off, 1) + np.diag(off, -1)
+    return np.linalg.eigvalsh(T)
+
+
+def kappa_estimate(dims, U, m, b, tol=1e-10, parity=0, maxiter=20000):
+    """Condition-number estimate of the parity system's operator from the
+    extreme Ritz values of a CG run on source b: (lambda_max, lambda_min,
+    kappa).  Ritz values lie inside the spectrum, so this estimate is a lower
+    bound of the true kappa that tightens as the run converges."""
+    _, al, be, _ = cg_coefficients(dims, U, m, b, tol=tol, maxiter=maxiter, parity=parity)
+    th = ritz_values(al, be)
+    return float(th[-1]), float(th[0]), float(th[-1] / th[0])
 
 
 def cg_full(dims, U, m, b, tol=1e-13, maxiter=100000, max_restarts=20,

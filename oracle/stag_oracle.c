@@ -352,12 +352,15 @@ double orc_true_residual(const int32_t L[4], int32_t tap, const double *U,
  *           rn = <r,r>; stop if rn < stop2; beta = rn/rr; p = r + beta p.
  * The stop threshold is passed in (tol^2 <b,b> of the original source, so
  * that a restart on a residual keeps the original target).
- * Returns the number of iterations; *rr_out holds the last <r,r>.
+ * Returns the number of iterations; *rr_out holds the last <r,r>.  If
+ * alphas / betas are not NULL they receive alpha and beta of every
+ * iteration (beta of the last one is the ratio rn/rr that would have been
+ * used next).
  */
 static int cg_pass(const int32_t L[4], int32_t tap, const double *U, double m,
                    int32_t par, double stop2, int32_t maxiter, const double *b,
                    double *x, double *r, double *p, double *ap, double *atap,
-                   double *rr_out)
+                   double *rr_out, double *alphas, double *betas)
 {
     const int32_t other = 1 - par;
     set_zero(L, par, x);
@@ -379,6 +382,10 @@ static int cg_pass(const int32_t L[4], int32_t tap, const double *U, double m,
         axpby(L, par, m * m, p, -1.0, atap);                 /* m^2 p - D ap  */
         axpby(L, par, -alpha, atap, 1.0, r);                 /* r -= alpha Ap */
         double rn = norm2(L, par, r);
+        if (alphas)
+            alphas[it - 1] = alpha;
+        if (betas)
+            betas[it - 1] = rn / rr;
         if (rn < stop2) {
             rr = rn;
             break;
@@ -438,7 +445,7 @@ int orc_cg_solve(const int32_t L[4], int32_t tap, const double *U, double m,
     copy_par(L, par, b, src);
     for (;;) {
         int it = cg_pass(L, tap, U, m, par, stop2, maxiter - total, src, dx, r, p,
-                         ap, atap, &rr);
+                         ap, atap, &rr, NULL, NULL);
         total += it;
         axpby(L, par, 1.0, dx, 1.0, x);                      /* x += correction */
         /* true residual in FP64: src = b - A x */
@@ -487,7 +494,39 @@ int orc_cg_pass(const int32_t L[4], int32_t tap, const double *U, double m,
     double *ap = calloc(n, sizeof(double)), *atap = calloc(n, sizeof(double));
     const double bb = norm2(L, par, b);
     double rr = 0;
-    int it = cg_pass(L, tap, U, m, par, tol * tol * bb, maxiter, b, x, r, p, ap, atap, &rr);
+    int it = cg_pass(L, tap, U, m, par, tol * tol * bb, maxiter, b, x, r, p, ap, atap, &rr, NULL, NULL);
+    if (res) {
+        res->status = rr < tol * tol * bb ? 0 : 1;
+        res->iters = it;
+        res->restarts = 0;
+        res->rr = rr;
+        res->bb = bb;
+        res->true_rel = orc_true_residual(L, tap, U, m, par, b, x);
+    }
+    free(r); free(p); free(ap); free(atap);
+    return 0;
+}
+
+/*
+ * The same single pass, also returning alpha_k and beta_k of every iteration
+ * k = 1..iters (arrays of maxiter doubles).  These are the coefficients of
+ * the Lanczos process that CG carries out implicitly; the eigenvalues of the
+ * tridiagonal matrix built from them (the Ritz values) approximate the
+ * spectrum of the parity system's operator from the inside, extreme ones
+ * first, which gives an estimate of its condition number.
+ */
+int orc_cg_coefficients(const int32_t L[4], int32_t tap, const double *U, double m,
+                        double tol, int32_t maxiter, int32_t par, const double *b,
+                        double *x, double *alphas, double *betas, orc_cg_result *res)
+{
+    if (bad_dims(L) || par < 0 || par > 1 || !(m > 0) || tol < 0 || maxiter < 0 || !alphas || !betas)
+        return -1;
+    const int64_t n = 6 * volume(L);
+    double *r = calloc(n, sizeof(double)), *p = calloc(n, sizeof(double));
+    double *ap = calloc(n, sizeof(double)), *atap = calloc(n, sizeof(double));
+    const double bb = norm2(L, par, b);
+    double rr = 0;
+    int it = cg_pass(L, tap, U, m, par, tol * tol * bb, maxiter, b, x, r, p, ap, atap, &rr, alphas, betas);
     if (res) {
         res->status = rr < tol * tol * bb ? 0 : 1;
         res->iters = it;

@@ -149,3 +149,36 @@ def test_bad_arguments_rejected():
         oracle.cg_solve(dims, U, 0.0, b)
     with pytest.raises(ValueError):
         oracle.cg_solve(dims, U, 0.1, b, tol=0.0)
+
+
+def test_ritz_values_free_field_exact():
+    # the free 4^4 parity operator has the four eigenvalues m^2 + {1/2, 3/2,
+    # 5/2, 7/2} (the hand-derived spectrum of -D^2): CG stops after four
+    # iterations and the Lanczos matrix of its coefficients has exactly them
+    dims, m = (4, 4, 4, 4), 0.1
+    b = inputs.gaussian_source(dims, 11)
+    for par in (oracle.EVEN, oracle.ODD):
+        _, al, be, info = oracle.cg_coefficients(dims, inputs.unit_links(dims), m, b, tol=1e-14, parity=par)
+        assert info["iters"] == 4
+        th = oracle.ritz_values(al, be)
+        assert np.max(np.abs(th - (m * m + np.array([0.5, 1.5, 2.5, 3.5])))) < 1e-12
+
+
+def test_kappa_estimate_against_dense_spectrum():
+    # Haar 4^4: the extreme Ritz values of a converged CG run approach the
+    # extreme eigenvalues of the parity operator from the inside; the
+    # reference spectrum comes from the independent dense builder
+    dims, m = (4, 4, 4, 4), 0.1
+    U = inputs.haar_su3(dims, 101)
+    A = dense.dense_normal(dense.dense_dslash(dims, U), m)
+    even = np.repeat(~dense.parity_mask(dims), 3)
+    lam = np.linalg.eigvalsh(A[np.ix_(even, even)])
+    lmax, lmin, kappa = oracle.kappa_estimate(dims, U, m, inputs.gaussian_source(dims, 201), tol=1e-12, parity=0)
+    assert lmin >= lam[0] * (1 - 1e-12) and lmax <= lam[-1] * (1 + 1e-12)
+    # the largest converges first; the smallest to a few 1e-4 at this residual
+    assert abs(lmax / lam[-1] - 1) < 1e-8 and abs(lmin / lam[0] - 1) < 2e-3
+    assert abs(kappa / (lam[-1] / lam[0]) - 1) < 2e-3
+    # a planted mistake: coefficients of a run on a different mass give a
+    # spectrum shifted by the mass difference, which the pin sees
+    _, al, be, _ = oracle.cg_coefficients(dims, U, 0.2, inputs.gaussian_source(dims, 201), tol=1e-12, parity=0)
+    assert abs(oracle.ritz_values(al, be)[0] - lam[0]) > 0.02
