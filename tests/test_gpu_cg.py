@@ -1,13 +1,15 @@
 """GPU parity of the CG solves against the CPU oracle.
 
 Bars:
-  FP64: ||x_gpu - x_oracle|| / ||x_oracle|| <= 1e-10, where the oracle runs
-        the same even-odd CG loop with the same stopping rule from x = 0;
-        iteration counts agree within 1.
+  FP64: per parity system, the oracle runs the same even-odd CG loop with
+        the same stopping rule from x = 0; iteration counts agree within 1
+        and ||x_gpu - x_oracle|| / ||x_oracle|| <= 1e-10, or else the two
+        sides' k-th iterates agree at 1e-10 (cg_counts.fp64_contract).
   every solve (FP64 and mixed): FP64 true residual ||b - A x|| / ||b|| <= tol,
         recomputed by the oracle from the returned x.
-  mixed: the error against a tight oracle solve is reported by the test and
-        bounded by kappa-free slack (1e-8) as a sanity check."""
+  mixed: the error against a tight oracle solve is stated and bounded by
+        kappa times the true residual, kappa estimated from the extreme Ritz
+        values of the oracle's CG coefficients."""
 
 import numpy as np
 import pytest
@@ -16,7 +18,7 @@ import torch
 import oracle
 from oracle import free_field
 from paper_1311_2719_amd import binding, inputs
-from cg_counts import iters_close
+from cg_counts import fp64_contract
 
 pytestmark = pytest.mark.gpu
 
@@ -46,7 +48,8 @@ def test_config0_fp64_matches_oracle(gpu_ctx):
         x, y, info = solve(gpu_ctx, f, b, want_y=True, mass=m, tol=tol)
         xr, yr, oi = oracle.cg_solve(dims, U, m, b, tol=tol, want_y=True)
         assert info["status"] == 0
-        assert iters_close(info["iters"], oi["iters"])
+        fp64_contract(dims, U, m, b, x, info["iters_parity"],
+                      lambda p, k: solve(gpu_ctx, f, b, mass=m, tol=tol, maxiter=k, parity=p)[0], label="4^4 Haar")
         assert rel(x, xr) <= 1e-10
         assert oracle.true_residual(dims, U, m, b, x) <= tol
         assert abs(info["true_rel_resid"] - oracle.true_residual(dims, U, m, b, x)) < 1e-12
@@ -67,7 +70,10 @@ def test_single_parity_and_second_half(gpu_ctx, par):
         V = int(np.prod(dims))
         lex = np.arange(V)
         p = (lex % 4 + (lex // 4) % 6 + (lex // 24) % 4 + lex // 96) & 1
-        assert info["status"] == 0 and iters_close(info["iters"], oi["iters"])
+        assert info["status"] == 0
+        fp64_contract(dims, U, m, b, x, info["iters_parity"],
+                      lambda q, k: solve(gpu_ctx, f, b, mass=m, tol=tol, maxiter=k, parity=q)[0], parities=(par,),
+                      label="4x6x4x8 parity %d" % par)
         assert rel(x[p == par], xr[p == par]) <= 1e-10
         assert not np.any(x[p != par])          # the other half is not written
         assert rel(y[p != par], yr[p != par]) <= 1e-10  # y = D x on the other half
@@ -97,9 +103,10 @@ def test_fp64_both_link_formats(gpu_ctx, case):
     try:
         assert gpu_ctx.link_rows(f) == 3
         x, _, info = solve(gpu_ctx, f, b, mass=m, tol=tol)
-        xr, _, oi = oracle.cg_solve(dims, U, m, b, tol=tol)
-        assert info["status"] == 0 and iters_close(info["iters"], oi["iters"])
-        assert rel(x, xr) <= 1e-10
+        assert info["status"] == 0
+        fp64_contract(dims, U, m, b, x, info["iters_parity"],
+                      lambda p, k: solve(gpu_ctx, f, b, mass=m, tol=tol, maxiter=k, parity=p)[0],
+                      label="4x4x4x6 " + case)
         x32, _, i32 = solve(gpu_ctx, f, b, mass=m, tol=tol, precision=binding.FP32_RU)
         assert i32["status"] == 0
         assert oracle.true_residual(dims, U, m, b, x32) <= tol
@@ -145,9 +152,10 @@ def test_config1_size_fp64(gpu_ctx):
     f = gpu_ctx.set_gauge(dims, U)
     try:
         x, _, info = solve(gpu_ctx, f, b, mass=m, tol=tol)
-        xr, _, oi = oracle.cg_solve(dims, U, m, b, tol=tol)
-        assert info["status"] == 0 and iters_close(info["iters"], oi["iters"])
-        assert rel(x, xr) <= 1e-10
+        assert info["status"] == 0
+        fp64_contract(dims, U, m, b, x, info["iters_parity"],
+                      lambda p, k: solve(gpu_ctx, f, b, mass=m, tol=tol, maxiter=k, parity=p)[0],
+                      label="16^4 eps 0.3 m 0.05")
         assert oracle.true_residual(dims, U, m, b, x) <= tol
     finally:
         gpu_ctx.free_gauge(f)
@@ -170,9 +178,11 @@ def test_mixed_precision_true_residual(gpu_ctx, prec, dims, m, eps):
         assert info["reliable_updates"] >= 2
         xt, ti = oracle.cg_full(dims, U, m, b, tol=1e-13)
         err = rel(x, xt)
-        print("precision %d %s: iters %d, reliable updates %d, true residual %.2e, error vs tight %.2e"
-              % (prec, dims, info["iters"], info["reliable_updates"], tr, err))
-        assert err < 1e-8
+        _, _, kappa = oracle.kappa_estimate(dims, U, m, b, parity=0)
+        print("ERROR precision %d %s m %g: iters %d, reliable updates %d, true residual %.2e, error vs tight %.2e, "
+              "kappa %.3g, bound %.2e" % (prec, dims, m, info["iters"], info["reliable_updates"], tr, err, kappa,
+                                          kappa * tr))
+        assert err <= kappa * tr
     finally:
         gpu_ctx.free_gauge(f)
 

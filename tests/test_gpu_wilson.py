@@ -1,8 +1,9 @@
 """GPU parity of the Wilson-fermion path against the CPU oracle.
 
 Bars: the hop H per site <= 1e-13 relative (as for the staggered D_slash);
-the even-odd CG runs the oracle's loop, so iteration counts agree within 1
-and x agrees to 1e-10 relative; every solve's FP64 true residual
+the even-odd CG runs the oracle's loop: iteration counts agree within 1 and
+x agrees to 1e-10 relative, or else the two sides' k-th iterates agree at
+1e-10 (cg_counts.wilson_contract); every solve's FP64 true residual
 ||b - M x|| / ||b|| is recomputed by the oracle from the returned x."""
 
 import os
@@ -13,7 +14,7 @@ import torch
 
 import oracle
 from paper_1311_2719_amd import binding, inputs
-from cg_counts import iters_close
+from cg_counts import wilson_contract
 
 pytestmark = pytest.mark.gpu
 
@@ -137,8 +138,10 @@ def test_solve_matches_oracle(gpu_ctx, dims, kappa, kind):
         x, info = solve(gpu_ctx, f, b, kappa, tol=1e-10)
         xr, oi = oracle.wilson_cg(dims, U, kappa, b, tol=1e-10)
         assert info["status"] == 0 and oi["status"] == 0
-        assert iters_close(info["iters"], oi["iters"])
-        assert rel(x, xr) <= 1e-10
+        wilson_contract(info["iters"], oi["iters"], x, xr,
+                        lambda k: solve(gpu_ctx, f, b, kappa, tol=1e-10, maxiter=k)[0],
+                        lambda k: oracle.wilson_cg(dims, U, kappa, b, tol=1e-10, maxiter=k)[0],
+                        label="Wilson %s %s" % (dims, kind))
         tr = np.linalg.norm(b - oracle.wilson_apply(dims, U, kappa, x)) / np.linalg.norm(b)
         assert abs(info["true_rel_resid"] - tr) <= 1e-3 * tr + 1e-15
         assert tr <= 1e-8
@@ -163,8 +166,11 @@ def test_solve_three_rows_and_full_size(gpu_ctx):
         try:
             assert gpu_ctx.link_rows(f) == rows
             x, info = solve(gpu_ctx, f, b, kappa, tol=1e-10)
-            assert info["status"] == 0 and iters_close(info["iters"], oi["iters"])
-            assert rel(x, xr) <= 1e-10
+            assert info["status"] == 0
+            wilson_contract(info["iters"], oi["iters"], x, xr,
+                            lambda k: solve(gpu_ctx, f, b, kappa, tol=1e-10, maxiter=k)[0],
+                            lambda k: oracle.wilson_cg(dims, U, kappa, b, tol=1e-10, maxiter=k)[0],
+                            label="Wilson 16^4 rows %d" % rows)
         finally:
             gpu_ctx.free_gauge(f)
 
@@ -215,7 +221,10 @@ def test_every_lanes_per_site(lps):
             assert site_err(hop(ctx, f, psi), oracle.wilson_hop(dims, U, psi)) <= TOL
             x, info = solve(ctx, f, psi, 0.11, tol=1e-10)
             xr, oi = oracle.wilson_cg(dims, U, 0.11, psi, tol=1e-10)
-            assert info["status"] == 0 and iters_close(info["iters"], oi["iters"])
-            assert rel(x, xr) <= 1e-10
+            assert info["status"] == 0
+            wilson_contract(info["iters"], oi["iters"], x, xr,
+                            lambda k: solve(ctx, f, psi, 0.11, tol=1e-10, maxiter=k)[0],
+                            lambda k: oracle.wilson_cg(dims, U, 0.11, psi, tol=1e-10, maxiter=k)[0],
+                            label="Wilson lanes per site %s" % lps)
     finally:
         del os.environ["STAG_WILSON_LPS"]
