@@ -262,6 +262,11 @@ int Batch::finish_create()
     nblk_ = grid_x(cfg_);
     reduce_ = uses_reduction(cfg_);
     live_ = S_;
+    // every block of a step kernel writes its partial sum at [blockIdx.x] of a
+    // slot of pstride_ entries, and the prologues / the reduction kernel read
+    // nblk_ of them: the grid must never be wider than a slot
+    if (nblk_ < 1 || nblk_ > pstride_)
+        return set_error(STAG_EINVAL, "CG grid of %d blocks exceeds the partial-sum slot (%d)", nblk_, pstride_);
     // every system starts idle, all systems listed
     STAG_HIP_CHECK(hipMemcpyAsync(st_d_[0], stage_, nsys * sizeof(SysState), hipMemcpyHostToDevice, s_));
     STAG_HIP_CHECK(hipMemcpyAsync(st_d_[1], stage_, nsys * sizeof(SysState), hipMemcpyHostToDevice, s_));
@@ -307,6 +312,8 @@ int Batch::set_running(const std::vector<char> &running)
 // Time K1 + K2 of one step with every system in a CG step on filled vectors.
 double Batch::time_cg_config(const KernelCfg &c, int nblk, bool reduce)
 {
+    if (nblk < 1 || nblk > pstride_)  // partial sums are indexed by block: never past a slot
+        return 1e30;
     const CgLaunchTable &t = cg_table(prec_, f_->rows);
     CgArgs a = args();
     for (int par = 0; par < 2; ++par)
