@@ -153,3 +153,132 @@ def expi(w, T):
 def derivative_from_force(F, T):
     """dS/dw = 2 Re tr[i T F] for the variation U -> exp(i w T) U."""
     return 2.0 * np.real(np.trace(1j * T @ F))
+
+
+# ---- the gauge action, momenta and the molecular-dynamics trajectory -----------------
+#
+# Readings (the paper names the Wilson gauge action and Hybrid Molecular
+# Dynamics but gives neither the normalisation nor the integrator):
+#   S_G = beta sum_{x, mu < nu} (1 - Re tr P_munu(x) / 3),
+#   P_munu(x) = U_mu(x) U_nu(x + mu) U_mu(x + nu)^dagger U_nu(x)^dagger,
+#   periodic in every direction (the antiperiodic t is a fermion boundary);
+#   momenta Q_mu(x) anti-Hermitian and traceless, H = -sum tr(Q^2) + S_G + S_F;
+#   equations of motion dU/dt = Q U, dQ/dt = F_G + F_F with the forces in the
+#   convention above (dS/dw = 2 Re tr[i T F] for U -> exp(i w T) U), so H is
+#   conserved;
+#   leapfrog: Q += eps/2 F; then n times { U = exp(eps Q) U (each new link
+#   projected back onto SU(3)); Q += eps F } with the last momentum step eps/2;
+#   pseudofermion phi = m chi_e - (D chi)_e on the even sites from a Gaussian
+#   chi on every site, so <phi phi^dagger> = m^2 - D_eo D_oe.
+
+
+def _dagger(A):
+    return np.conj(np.swapaxes(A, -1, -2))
+
+
+def plaquette_field(dims, U, mu, nu):
+    """P_munu(x) for every site, [V, 3, 3]."""
+    fm, fn = forward_site(dims, mu), forward_site(dims, nu)
+    return U[:, mu] @ U[fm, nu] @ _dagger(U[fn, mu]) @ _dagger(U[:, nu])
+
+
+def gauge_action(dims, U, beta):
+    """S_G = beta sum_{x, mu<nu} (1 - Re tr P_munu(x) / 3)."""
+    U = np.asarray(U, dtype=np.complex128)
+    s = 0.0
+    for mu in range(4):
+        for nu in range(mu + 1, 4):
+            s += np.sum(1.0 - np.real(np.trace(plaquette_field(dims, U, mu, nu), axis1=-2, axis2=-1)) / 3.0)
+    return float(beta * s)
+
+
+def backward_site(dims, mu):
+    """Lexicographic index of z - mu (periodic) for every site z."""
+    Lx, Ly, Lz, Lt = dims
+    c = list(_coords(dims))
+    L = (Lx, Ly, Lz, Lt)
+    c[mu] = (c[mu] - 1) % L[mu]
+    return c[0] + Lx * (c[1] + Ly * (c[2] + Lz * c[3]))
+
+
+def staple_sum(dims, U, mu):
+    """Sigma_mu(x) = sum_{nu != mu} [U_nu(x+mu) U_mu(x+nu)^dagger U_nu(x)^dagger
+    + U_nu(x+mu-nu)^dagger U_mu(x-nu)^dagger U_nu(x-nu)], so that the plaquettes
+    holding U_mu(x) sum to Re tr[U_mu(x) Sigma_mu(x)]."""
+    fm = forward_site(dims, mu)
+    S = np.zeros((U.shape[0], 3, 3), np.complex128)
+    for nu in range(4):
+        if nu == mu:
+            continue
+        fn, bn = forward_site(dims, nu), backward_site(dims, nu)
+        fm_bn = backward_site(dims, nu)[fm]  # x + mu - nu
+        S += U[fm, nu] @ _dagger(U[fn, mu]) @ _dagger(U[:, nu])
+        S += _dagger(U[fm_bn, nu]) @ _dagger(U[bn, mu]) @ U[bn, nu]
+    return S
+
+
+def gauge_force(dims, U, beta):
+    """F_G = -(beta / 6) TA[U_mu(x) Sigma_mu(x)], [V, 4, 3, 3]."""
+    U = np.asarray(U, dtype=np.complex128)
+    F = np.zeros_like(U)
+    for mu in range(4):
+        F[:, mu] = -(beta / 6.0) * traceless_antihermitian(U[:, mu] @ staple_sum(dims, U, mu))
+    return F
+
+
+def kinetic_energy(Q):
+    """-sum tr(Q^2) over all links (real, >= 0 for anti-Hermitian Q)."""
+    return float(-np.real(np.sum(np.einsum("...ab,...ba->...", Q, Q))))
+
+
+def expm_antihermitian(A):
+    """exp(A) for anti-Hermitian A (...x3x3), through the eigenvectors of -iA."""
+    lam, Vv = np.linalg.eigh(-1j * A)
+    return (Vv * np.exp(1j * lam)[..., None, :]) @ _dagger(Vv)
+
+
+def reunitarize(U):
+    """Project onto SU(3): Gram-Schmidt on rows 0 and 1, row 2 = conj(row0 x row1)."""
+    r0 = U[..., 0, :] / np.linalg.norm(U[..., 0, :], axis=-1, keepdims=True)
+    r1 = U[..., 1, :] - np.sum(np.conj(r0) * U[..., 1, :], axis=-1, keepdims=True) * r0
+    r1 = r1 / np.linalg.norm(r1, axis=-1, keepdims=True)
+    return np.stack([r0, r1, np.conj(np.cross(r0, r1))], axis=-2)
+
+
+def momenta_from_gaussian(g):
+    """Q = sum_a i g^a T^a from real Gaussians g [..., 8]: the momentum
+    heatbath, <-tr Q^2> = 4 per link."""
+    T = su3_generators()
+    return 1j * np.einsum("...a,aij->...ij", g, T)
+
+
+def pseudofermion_from_gaussian(dims, U, m, chi, antiperiodic_t=True):
+    """phi = m chi - D chi on the even sites, zero on the odd sites."""
+    Dchi = oracle.dslash(dims, U, chi, antiperiodic_t=antiperiodic_t)
+    phi = m * np.asarray(chi) - Dchi
+    phi[parity(dims) == 1] = 0
+    return phi
+
+
+def hamiltonian(dims, U, Q, beta, m, phi, tol=1e-12, antiperiodic_t=True):
+    """(H, kinetic, S_G, S_F)."""
+    k = kinetic_energy(Q)
+    sg = gauge_action(dims, U, beta)
+    sf = fermion_action(dims, U, m, phi, tol=tol, antiperiodic_t=antiperiodic_t)
+    return k + sg + sf, k, sg, sf
+
+
+def total_force(dims, U, beta, m, phi, tol=1e-12, antiperiodic_t=True):
+    return gauge_force(dims, U, beta) + fermion_force(dims, U, m, phi, tol=tol, antiperiodic_t=antiperiodic_t)
+
+
+def leapfrog(dims, U, Q, beta, m, phi, eps, nsteps, tol=1e-12, antiperiodic_t=True):
+    """The leapfrog trajectory of the reading above; returns (U, Q)."""
+    U = np.array(U, dtype=np.complex128)
+    Q = np.array(Q, dtype=np.complex128)
+    Q = Q + 0.5 * eps * total_force(dims, U, beta, m, phi, tol, antiperiodic_t)
+    for k in range(nsteps):
+        U = reunitarize(expm_antihermitian(eps * Q) @ U)
+        w = eps if k < nsteps - 1 else 0.5 * eps
+        Q = Q + w * total_force(dims, U, beta, m, phi, tol, antiperiodic_t)
+    return U, Q
