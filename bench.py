@@ -105,7 +105,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--suite", default="default",
                     choices=["default", "mixed32", "batch24", "serve", "copy", "cpu_baseline", "wilson",
-                             "kernels32"])
+                             "kernels32", "md"])
     ap.add_argument("--oracle-threads-one", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--dslash-reps", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -566,6 +566,65 @@ def run_copy(args):
                       "kernels": "torch copy_, sum, fill_ on float64 buffers of 2 GiB"}), flush=True)
 
 
+def run_md(args):
+    """Molecular dynamics around the solve: one leapfrog trajectory on a 16^4
+    field (links proj_SU3(exp(0.3 i H)) seed 102, momenta seed 702, Gaussian
+    chi seed 703; beta 5.6, m 0.05, 10 steps of 0.02) with FP64 and with FP32
+    reliable-update force solves; the fermion and gauge force kernels timed
+    alone (accumulating into the momenta, as the trajectory uses them)."""
+    import torch
+
+    from paper_1311_2719_amd import binding, inputs
+
+    dims, beta, m, eps, n = (16, 16, 16, 16), 5.6, 0.05, 0.02, 10
+    V = int(np.prod(dims))
+    U = inputs.smooth_su3(dims, 0.3, 102)
+    Q = inputs.gaussian_momenta(dims, 702)
+    ctx = binding.Context(device=0, arena_bytes=8 << 30)
+    f = ctx.set_gauge(dims, U)
+    phi = ctx.pseudofermion(f, ctx.pack(f, inputs.gaussian_source(dims, 703)), m)
+    res = {}
+    for name, prec in (("fp64", binding.FP64), ("fp32_ru", binding.FP32_RU)):
+        Ud = torch.from_numpy(U).cuda()
+        Qd = torch.from_numpy(Q).cuda()
+        stage("md: trajectory %s" % name)
+        info = ctx.md_trajectory(dims, Ud, Qd, phi, beta, m, eps, n, tol=1e-10, precision=prec)
+        res[name] = {"seconds": info["seconds"], "delta_h": info["delta_h"], "cg_iters": info["cg_iters"],
+                     "solves": info["solves"], "kinetic": info["kinetic"], "gauge_action": info["gauge_action"],
+                     "fermion_action": info["fermion_action"]}
+    # the force kernels alone
+    x = ctx.new_fermion(f)
+    y = ctx.new_fermion(f)
+    ctx.cg_solve(f, phi, x, y=y, mass=m, parity=binding.EVEN)
+    w = x.clone()
+    w[1] = y[1]
+    Ud = torch.from_numpy(U).cuda()
+    Qd = torch.from_numpy(Q).cuda()
+
+    def timed(fn, reps=50):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(reps):
+            fn()
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    tf = timed(lambda: ctx.fermion_force(f, w, force=Qd, coeff=1e-9, accumulate=True))
+    tg = timed(lambda: ctx.gauge_force(dims, Ud, beta, force=Qd, coeff=1e-9, accumulate=True))
+    rows = ctx.link_rows(f)
+    fbytes = 4 * 3 * rows * 16 + 48 + 48 + 2 * 4 * 144  # links, W here and at the neighbours, momenta read + written
+    res["fermion_force"] = {"mean_us": tf * 1e6, "bytes_per_site": fbytes, "gbs": fbytes * V / tf / 1e9,
+                            "frac": fbytes * V / tf / 1e9 / HBM_PEAK_GBS,
+                            "note": "working set about 0.2 GB at 16^4, partly Infinity-Cache resident"}
+    res["gauge_force"] = {"mean_us": tg * 1e6, "links": 4 * V}
+    ctx.close()
+    _emit({"suite": "md", "workload": "16^4 eps 0.3 links seed 102, momenta seed 702, chi seed 703, beta 5.6, "
+                                      "m 0.05, leapfrog 10 x 0.02, CG 1e-10", "results": res})
+
+
 def run_kernels32(args):
     """The 32^4 workload's kernels for profilers: the FP64 D_slash
     (args.dslash_reps launches) and one solve in each precision."""
@@ -880,7 +939,7 @@ def run_cpu_baseline(args):
 
 
 SUITES = {"mixed32": run_mixed32, "batch24": run_batch24, "serve": run_serve, "cpu_baseline": run_cpu_baseline,
-          "wilson": run_wilson, "kernels32": run_kernels32}
+          "wilson": run_wilson, "kernels32": run_kernels32, "md": run_md}
 
 
 def main():

@@ -302,6 +302,91 @@ int stag_cg_solve_batch(stag_ctx *ctx, int32_t gauge_id, int32_t nrhs,
                         const stag_cg_params *params, const double *const *b,
                         double *const *x, void *stream, stag_cg_info *infos);
 
+/* ---- molecular dynamics around the solve (Sec. 2, Sec. 6) ------------- */
+
+/*
+ * The force of the staggered pseudofermion action of the paper's HMD
+ * program, which it runs around the CG of Sec. 4 without writing the action
+ * out; the textbook reading for the even-site operator the CG solves:
+ *   S_F = phi^dagger (m^2 - D_eo D_oe)^{-1} phi   (phi on the even sites),
+ *   F_mu(z) = TA[ eps(z) c_mu(z) U_mu(z) W(z + mu) W(z)^dagger ],
+ * with W = x on the even sites and y = D_oe x on the odd sites (exactly what
+ * stag_cg_solve returns for parity STAG_EVEN with y: x's even half and y's
+ * odd half), c_mu(z) = eta_mu(z) b_mu(z) / 2 (b: the t-boundary sign of the
+ * hop from z to z + mu), eps(z) = +1 on even and -1 on odd sites, and
+ * TA(Z) = (Z - Z^dagger)/2 - tr(Z - Z^dagger)/6 the traceless anti-Hermitian
+ * part.  Then dS_F/dw = 2 Re tr[i T F_mu(z)] for U_mu(z) -> exp(i w T) U_mu(z),
+ * T Hermitian and traceless.
+ * w: device even-odd FP64 field (layout above).  force: device complex128
+ * [V][4][3][3] in the gauge-field input layout; force = (accumulate ? force :
+ * 0) + coeff * F.  Asynchronous on `stream`.  Errors: ENOENT, EINVAL (NULL,
+ * overlap, non-finite coeff, a Wilson field).
+ */
+int stag_fermion_force(stag_ctx *ctx, int32_t gauge_id, const double *w, double *force,
+                       double coeff, int32_t accumulate, void *stream);
+
+/*
+ * The Wilson gauge action's force on links given in the input layout
+ * (complex128 [V][4][3][3] lexicographic, device, periodic in every
+ * direction): S_G = beta sum_{x, mu<nu} (1 - Re tr P_munu(x) / 3) and
+ * F_G = -(beta/6) TA[U_mu(x) Sigma_mu(x)] with Sigma the sum of the six
+ * staples, in the convention of stag_fermion_force.  force: same layout;
+ * force = (accumulate ? force : 0) + coeff * F_G.  dims as for set_gauge.
+ * Asynchronous on `stream`.  Errors: EINVAL.
+ */
+int stag_gauge_force(stag_ctx *ctx, const int32_t dims[4], const double *links, double beta,
+                     double *force, double coeff, int32_t accumulate, void *stream);
+
+/*
+ * The pseudofermion of a registered staggered field from a Gaussian field
+ * chi on every site: phi = m chi - D chi on the even sites, phi = 0 on the
+ * odd ones, so that <phi phi^dagger> is proportional to m^2 - D_eo D_oe.
+ * chi, phi: device even-odd FP64 fields, not overlapping.  Asynchronous on
+ * `stream`.  Errors: ENOENT, EINVAL.
+ */
+int stag_pseudofermion(stag_ctx *ctx, int32_t gauge_id, const double *chi, double *phi,
+                       double mass, void *stream);
+
+typedef struct {
+    double beta;            /* Wilson gauge coupling */
+    double mass;            /* staggered mass, > 0 */
+    double eps;             /* molecular-dynamics step, > 0 */
+    double tol;             /* CG tolerance of every force solve */
+    int32_t nsteps;         /* leapfrog steps, >= 1 */
+    int32_t maxiter;        /* CG iteration limit per solve */
+    int32_t precision;      /* CG precision: STAG_FP64, STAG_FP32_RU or STAG_FP16_RU */
+    int32_t t_antiperiodic; /* fermion boundary in t */
+} stag_md_params;
+
+typedef struct {
+    double kinetic[2];        /* -sum tr Q^2 at the start and at the end */
+    double gauge_action[2];   /* S_G at the start and at the end */
+    double fermion_action[2]; /* S_F = Re phi^dagger x at the start and at the end */
+    double delta_h;           /* H(end) - H(start) */
+    double seconds;
+    int32_t cg_iters;         /* CG iterations summed over the force solves */
+    int32_t solves;           /* CG solves (nsteps + 1) */
+} stag_md_info;
+
+/*
+ * One molecular-dynamics trajectory of the HMD program the paper runs
+ * around its CG (Sec. 2, Sec. 6), in the textbook reading the paper leaves
+ * open: H = -sum tr Q^2 + S_G + S_F (S_F as for stag_fermion_force),
+ * dU/dt = Q U and dQ/dt = F_G + F_F; leapfrog with n steps of eps: Q +=
+ * eps/2 F, then n times { U = exp(eps Q) U projected onto SU(3); Q += eps F }
+ * with the last momentum step eps/2.  Every force needs one CG solve of the
+ * even-site system on the current links (stag_cg_solve with parity EVEN and
+ * y), on a private copy of the field rebuilt after each link update.
+ * links (in/out): device complex128 [V][4][3][3] lexicographic, special
+ * unitary.  momenta (in/out): same layout, anti-Hermitian and traceless.
+ * phi: device even-odd FP64 pseudofermion (even sites).  Blocks until done;
+ * info (nullable) receives the energies.  Errors: EINVAL (bad parameters,
+ * links that are not special unitary), ENOMEM, and the errors of the solves.
+ */
+int stag_md_trajectory(stag_ctx *ctx, const int32_t dims[4], double *links, double *momenta,
+                       const double *phi, const stag_md_params *params, void *stream,
+                       stag_md_info *info);
+
 /* ---- serving: continuous batching ------------------------------------ */
 
 /*

@@ -65,7 +65,9 @@ def hop_coefficient(dims, mu, antiperiodic_t=True):
     (-1)^(x_0 + ... + x_{mu-1}); b_mu(z) = -1 for the hop from the last t
     slice forward across the boundary of an antiperiodic field."""
     x = _coords(dims)
-    esum = sum(x[nu] for nu in range(mu))
+    esum = np.zeros_like(x[0])
+    for nu in range(mu):
+        esum = esum + x[nu]
     c = np.where(esum % 2 == 0, 0.5, -0.5)
     if mu == 3 and antiperiodic_t:
         c = np.where(x[3] == dims[3] - 1, -c, c)

@@ -56,6 +56,38 @@ class CGParams(ctypes.Structure):
     ]
 
 
+class MDParams(ctypes.Structure):
+    _fields_ = [
+        ("beta", ctypes.c_double),
+        ("mass", ctypes.c_double),
+        ("eps", ctypes.c_double),
+        ("tol", ctypes.c_double),
+        ("nsteps", ctypes.c_int32),
+        ("maxiter", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("t_antiperiodic", ctypes.c_int32),
+    ]
+
+
+class MDInfo(ctypes.Structure):
+    _fields_ = [
+        ("kinetic", ctypes.c_double * 2),
+        ("gauge_action", ctypes.c_double * 2),
+        ("fermion_action", ctypes.c_double * 2),
+        ("delta_h", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+        ("cg_iters", ctypes.c_int32),
+        ("solves", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        d = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            d[k] = list(v) if isinstance(v, ctypes.Array) else v
+        return d
+
+
 class CGInfo(ctypes.Structure):
     _fields_ = [
         ("status", ctypes.c_int32),
@@ -104,6 +136,11 @@ def load():
                                     ctypes.c_int),
             "stag_cg_solve_noalloc": ([P, I32, ctypes.POINTER(CGParams), P, P, P, P, ctypes.POINTER(CGInfo)],
                                       ctypes.c_int),
+            "stag_fermion_force": ([P, I32, P, P, ctypes.c_double, I32, P], ctypes.c_int),
+            "stag_gauge_force": ([P, P, P, ctypes.c_double, P, ctypes.c_double, I32, P], ctypes.c_int),
+            "stag_pseudofermion": ([P, I32, P, P, ctypes.c_double, P], ctypes.c_int),
+            "stag_md_trajectory": ([P, P, P, P, P, ctypes.POINTER(MDParams), P, ctypes.POINTER(MDInfo)],
+                                   ctypes.c_int),
             "stag_submit": ([P, I32, ctypes.POINTER(CGParams), P, P, ctypes.POINTER(U64)], ctypes.c_int),
             "stag_poll": ([P, U64, ctypes.POINTER(CGInfo)], ctypes.c_int),
             "stag_wait": ([P, U64, ctypes.POINTER(CGInfo)], ctypes.c_int),
@@ -134,7 +171,8 @@ def exported_symbols():
         "stag_create", "stag_destroy", "stag_last_error", "stag_arena_usage", "stag_set_gauge",
         "stag_free_gauge", "stag_gauge_dims", "stag_gauge_link_rows", "stag_pack_fermion", "stag_unpack_fermion", "stag_dslash",
         "stag_convert_fermion", "stag_cg_solve", "stag_cg_solve_noalloc", "stag_cg_solve_batch", "stag_submit", "stag_poll", "stag_wait",
-        "stag_release_ticket", "stag_serve_config", "stag_tune_info", "stag_cg_tune_info", "stag_version",
+        "stag_release_ticket", "stag_serve_config", "stag_fermion_force", "stag_gauge_force",
+        "stag_pseudofermion", "stag_md_trajectory", "stag_tune_info", "stag_cg_tune_info", "stag_version",
         "stag_set_gauge_wilson", "stag_pack_spinor", "stag_unpack_spinor", "stag_wilson_dslash",
         "stag_wilson_solve",
     ]
@@ -452,6 +490,74 @@ class Context:
         out = [i.as_dict() for i in infos]
         for d in out:
             d["rc"] = rc
+        return out
+
+    # -- molecular dynamics ----------------------------------------------------
+    def fermion_force(self, field: Field, w, force=None, coeff=1.0, accumulate=False, stream=None):
+        """force (+)= coeff * F, the pseudofermion force from w (device even-odd
+        field: the solution on the even sites, D_oe of it on the odd sites).
+        force: complex128 (V, 4, 3, 3) on the device (allocated if None)."""
+        torch = _torch()
+        self._check_eo(field, w)
+        if force is None:
+            force = torch.zeros((field.volume, 4, 3, 3), dtype=torch.complex128, device=self.torch_device)
+        if not (isinstance(force, torch.Tensor) and force.is_cuda and force.dtype == torch.complex128
+                and force.is_contiguous() and tuple(force.shape) == (field.volume, 4, 3, 3)):
+            raise ValueError("force must be a contiguous complex128 CUDA tensor (V, 4, 3, 3)")
+        s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+        _check(self.lib.stag_fermion_force(self.h, field.gauge_id, ctypes.c_void_p(w.data_ptr()),
+                                           ctypes.c_void_p(force.data_ptr()), float(coeff), int(bool(accumulate)),
+                                           s), "stag_fermion_force")
+        return force
+
+    def _check_links(self, dims, t, what):
+        torch = _torch()
+        V = int(np.prod(dims))
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()
+                and tuple(t.shape) == (V, 4, 3, 3)):
+            raise ValueError("%s must be a contiguous complex128 CUDA tensor (V, 4, 3, 3)" % what)
+
+    def gauge_force(self, dims, links, beta, force=None, coeff=1.0, accumulate=False, stream=None):
+        """force (+)= coeff * F_G for device links (V, 4, 3, 3)."""
+        torch = _torch()
+        d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32))
+        self._check_links(d, links, "links")
+        if force is None:
+            force = torch.zeros_like(links)
+        self._check_links(d, force, "force")
+        s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+        _check(self.lib.stag_gauge_force(self.h, d.ctypes.data, ctypes.c_void_p(links.data_ptr()), float(beta),
+                                         ctypes.c_void_p(force.data_ptr()), float(coeff), int(bool(accumulate)), s),
+               "stag_gauge_force")
+        return force
+
+    def pseudofermion(self, field: Field, chi, mass, phi=None):
+        """phi = m chi - D chi on the even sites (device even-odd fields)."""
+        self._check_eo(field, chi)
+        if phi is None:
+            phi = self.new_fermion(field)
+        self._check_eo(field, phi)
+        _check(self.lib.stag_pseudofermion(self.h, field.gauge_id, ctypes.c_void_p(chi.data_ptr()),
+                                           ctypes.c_void_p(phi.data_ptr()), float(mass), None), "stag_pseudofermion")
+        return phi
+
+    def md_trajectory(self, dims, links, momenta, phi, beta, mass, eps, nsteps, tol=1e-10, maxiter=20000,
+                      precision=FP64, antiperiodic_t=True, check=True):
+        """One leapfrog trajectory; links and momenta (V, 4, 3, 3) device tensors
+        are updated in place; phi a device even-odd pseudofermion."""
+        d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32))
+        self._check_links(d, links, "links")
+        self._check_links(d, momenta, "momenta")
+        p = MDParams(float(beta), float(mass), float(eps), float(tol), int(nsteps), int(maxiter), int(precision),
+                     int(bool(antiperiodic_t)))
+        info = MDInfo()
+        rc = self.lib.stag_md_trajectory(self.h, d.ctypes.data, ctypes.c_void_p(links.data_ptr()),
+                                         ctypes.c_void_p(momenta.data_ptr()), ctypes.c_void_p(phi.data_ptr()),
+                                         ctypes.byref(p), None, ctypes.byref(info))
+        if check:
+            _check(rc, "stag_md_trajectory")
+        out = info.as_dict()
+        out["rc"] = rc
         return out
 
     # -- serving ---------------------------------------------------------------

@@ -556,6 +556,94 @@ int stag_cg_solve(stag_ctx *ctx, int32_t gauge_id, const stag_cg_params *params,
     STAG_GUARD_END
 }
 
+int stag_fermion_force(stag_ctx *ctx, int32_t gauge_id, const double *w, double *force, double coeff,
+                       int32_t accumulate, void *stream)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx || !w || !force)
+        return set_error(STAG_EINVAL, "stag_fermion_force: NULL argument");
+    if (!std::isfinite(coeff))
+        return set_error(STAG_EINVAL, "stag_fermion_force: coefficient must be finite");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    auto f = c->field(gauge_id);
+    if (!f)
+        return set_error(STAG_ENOENT, "unknown gauge id %d", gauge_id);
+    if (f->kind != FIELD_STAGGERED)
+        return set_error(STAG_EINVAL, "gauge id %d holds Wilson-fermion links", gauge_id);
+    const size_t wb = (size_t)2 * 3 * f->g.Vh * 16, fb = (size_t)2 * f->g.Vh * 4 * 9 * 16;
+    const char *a0 = (const char *)w, *b0 = (const char *)force;
+    if (a0 < b0 + fb && b0 < a0 + wb)
+        return set_error(STAG_EINVAL, "stag_fermion_force: w and force must not overlap");
+    DeviceGuard dg(c->device);
+    return fermion_force(f.get(), w, force, coeff, accumulate, pick_stream(ctx, stream));
+    STAG_GUARD_END
+}
+
+int stag_gauge_force(stag_ctx *ctx, const int32_t dims[4], const double *links, double beta, double *force,
+                     double coeff, int32_t accumulate, void *stream)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx || !links || !force)
+        return set_error(STAG_EINVAL, "stag_gauge_force: NULL argument");
+    if (!dims_ok(dims))
+        return set_error(STAG_EINVAL, "stag_gauge_force: every extent must be even and >= 2");
+    if (!std::isfinite(beta) || !std::isfinite(coeff))
+        return set_error(STAG_EINVAL, "stag_gauge_force: beta and coeff must be finite");
+    const size_t n = (size_t)dims[0] * dims[1] * dims[2] * dims[3] * 4 * 9 * 16;
+    const char *a0 = (const char *)links, *b0 = (const char *)force;
+    if (a0 < b0 + n && b0 < a0 + n)
+        return set_error(STAG_EINVAL, "stag_gauge_force: links and force must not overlap");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    DeviceGuard dg(c->device);
+    return gauge_force(dims, links, force, beta, coeff, accumulate, pick_stream(ctx, stream));
+    STAG_GUARD_END
+}
+
+int stag_pseudofermion(stag_ctx *ctx, int32_t gauge_id, const double *chi, double *phi, double mass, void *stream)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx || !chi || !phi)
+        return set_error(STAG_EINVAL, "stag_pseudofermion: NULL argument");
+    if (!std::isfinite(mass))
+        return set_error(STAG_EINVAL, "stag_pseudofermion: mass must be finite");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    auto f = c->field(gauge_id);
+    if (!f)
+        return set_error(STAG_ENOENT, "unknown gauge id %d", gauge_id);
+    if (f->kind != FIELD_STAGGERED)
+        return set_error(STAG_EINVAL, "gauge id %d holds Wilson-fermion links", gauge_id);
+    const size_t n = (size_t)2 * 3 * f->g.Vh * 16;
+    const char *a0 = (const char *)chi, *b0 = (const char *)phi;
+    if (a0 < b0 + n && b0 < a0 + n)
+        return set_error(STAG_EINVAL, "stag_pseudofermion: chi and phi must not overlap");
+    DeviceGuard dg(c->device);
+    return pseudofermion(c, f.get(), chi, phi, mass, pick_stream(ctx, stream));
+    STAG_GUARD_END
+}
+
+int stag_md_trajectory(stag_ctx *ctx, const int32_t dims[4], double *links, double *momenta, const double *phi,
+                       const stag_md_params *params, void *stream, stag_md_info *info)
+{
+    STAG_GUARD_BEGIN
+    clear_error();
+    if (!ctx || !links || !momenta || !phi || !params)
+        return set_error(STAG_EINVAL, "stag_md_trajectory: NULL argument");
+    if (!dims_ok(dims))
+        return set_error(STAG_EINVAL, "stag_md_trajectory: every extent must be even and >= 2");
+    const stag_md_params &p = *params;
+    if (!(p.mass > 0) || !std::isfinite(p.mass) || !(p.eps > 0) || !std::isfinite(p.eps) || !std::isfinite(p.beta) ||
+        !(p.tol > 0) || p.nsteps < 1 || p.maxiter < 1 || p.precision < STAG_FP64 || p.precision > STAG_FP16_RU)
+        return set_error(STAG_EINVAL, "stag_md_trajectory: mass, eps, tol > 0, nsteps, maxiter >= 1, a known "
+                                      "precision and a finite beta are required");
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    DeviceGuard dg(c->device);
+    return md_trajectory(c, dims, links, momenta, phi, p, pick_stream(ctx, stream), info);
+    STAG_GUARD_END
+}
+
 int stag_cg_solve_noalloc(stag_ctx *ctx, int32_t gauge_id, const stag_cg_params *params, const double *b, double *x,
                           double *y, void *stream, stag_cg_info *info)
 {

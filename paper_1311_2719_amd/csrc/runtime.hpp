@@ -164,6 +164,19 @@ int dslash_f64(Ctx *ctx, GaugeField *f, int out_parity, int64_t offset, int64_t 
 // the same with a given kernel shape (no tuning, nothing allocated)
 int dslash_with(const KernelCfg &cfg, GaugeField *f, int prec, int out_parity, int64_t offset, int64_t count,
                 const void *in, void *out, int accumulate, hipStream_t s);
+// force = (accumulate ? force : 0) + coeff F, F the pseudofermion force from
+// w (the CG solution on the even sites, D_oe of it on the odd sites);
+// force complex128 [V][4][3][3] lexicographic
+int fermion_force(GaugeField *f, const double *w, double *force, double coeff, int accumulate, hipStream_t s);
+// molecular dynamics (md.hip): links and momenta complex128 [V][4][3][3]
+int gauge_force(const int32_t dims[4], const double *U, double *force, double beta, double coeff, int accumulate,
+                hipStream_t s);
+int link_update(int64_t V, double *U, const double *Q, double eps, hipStream_t s);
+int pseudofermion(Ctx *ctx, GaugeField *f, const double *chi, double *phi, double mass, hipStream_t s);
+int md_energies(const int32_t dims[4], const double *U, const double *Q, const double *phi, const double *x,
+                double beta, double *scratch, double energies[3], hipStream_t s);
+int md_trajectory(Ctx *ctx, const int32_t dims[4], double *U, double *Q, const double *phi, const stag_md_params &p,
+                  hipStream_t s, stag_md_info *info);
 // full-lattice fermion field from one storage precision to another
 int convert_fermion(const Geom &g, int prec_in, const void *in, int prec_out, void *out, hipStream_t s);
 KernelCfg tune_config(Ctx *ctx, GaugeField *f, int prec, int nrhs, hipStream_t s);

@@ -178,9 +178,13 @@ struct PrecF64 {
     static constexpr int id = 0;
     // spinor storage: [3][Vh] dbl2
     using spin_store = dbl2;
+    // FP64 links are read once per kernel and never again while the kernel
+    // runs: non-temporal loads keep them from evicting the gathered vectors,
+    // which every site reads eight times, from L2 (32^4 D_slash: 170 -> 152
+    // us).  The FP32 and FP16 tiles measured slower with them.
     static __device__ __forceinline__ cplx<real> load_link(const link_t *p)
     {
-        dbl2 v = *p;
+        const dbl2 v = __builtin_nontemporal_load(p);
         return {v.x, v.y};
     }
     static __device__ __forceinline__ void load_spinor(const void *base, int Vh, int s, cplx<real> out[3])

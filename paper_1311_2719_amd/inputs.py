@@ -31,6 +31,7 @@ __all__ = [
     "gaussian_spinor",
     "proj_su3",
     "masses_uniform",
+    "gaussian_momenta",
 ]
 
 
@@ -136,3 +137,25 @@ def random_su3_gauge_transform(dims, seed: int) -> np.ndarray:
     V = volume(dims)
     g = haar_su3((V, 1, 1, 1), seed)  # [V, 4, 3, 3]; use mu = 0
     return np.ascontiguousarray(g[:, 0])
+
+
+def gaussian_momenta(dims, seed: int) -> np.ndarray:
+    """Molecular-dynamics momenta [V, 4, 3, 3]: Q = i sum_a g_a T_a with
+    g_a ~ N(0,1) (eight per link, drawn in the order sites, mu, a) and
+    T_a = lambda_a / 2 the Gell-Mann generators, so Q is anti-Hermitian and
+    traceless with <-tr Q^2> = 4 per link."""
+    V = volume(dims)
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((V, 4, 8))
+    s3 = 1.0 / np.sqrt(3.0)
+    lam = np.array([
+        [[0, 1, 0], [1, 0, 0], [0, 0, 0]],
+        [[0, -1j, 0], [1j, 0, 0], [0, 0, 0]],
+        [[1, 0, 0], [0, -1, 0], [0, 0, 0]],
+        [[0, 0, 1], [0, 0, 0], [1, 0, 0]],
+        [[0, 0, -1j], [0, 0, 0], [1j, 0, 0]],
+        [[0, 0, 0], [0, 0, 1], [0, 1, 0]],
+        [[0, 0, 0], [0, 0, -1j], [0, 1j, 0]],
+        [[s3, 0, 0], [0, s3, 0], [0, 0, -2 * s3]],
+    ], dtype=np.complex128)
+    return np.ascontiguousarray(0.5j * np.einsum("...a,aij->...ij", g, lam), dtype=np.complex128)

@@ -55,8 +55,9 @@ def test_binding_covers_the_header(lib_path):
 def test_struct_layouts_match_header(tmp_path):
     # sizes and field offsets of the ABI structs as a C compiler lays them out
     # from the header, against the binding's ctypes mirrors
-    fields = {"stag_cg_params": [n for n, _ in binding.CGParams._fields_],
-              "stag_cg_info": [n for n, _ in binding.CGInfo._fields_]}
+    structs = {"stag_cg_params": binding.CGParams, "stag_cg_info": binding.CGInfo,
+               "stag_md_params": binding.MDParams, "stag_md_info": binding.MDInfo}
+    fields = {k: [n for n, _ in v._fields_] for k, v in structs.items()}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "stagcg.h"', "int main(void) {"]
     for st, names in fields.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (st, st))
@@ -69,7 +70,7 @@ def test_struct_layouts_match_header(tmp_path):
     subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
                                                        check=True).stdout.splitlines())
-    for st, cls in (("stag_cg_params", binding.CGParams), ("stag_cg_info", binding.CGInfo)):
+    for st, cls in structs.items():
         assert int(got[st]) == ctypes.sizeof(cls), st
         for n, _ in cls._fields_:
             assert int(got["%s.%s" % (st, n)]) == getattr(cls, n).offset, (st, n)
