@@ -443,13 +443,16 @@ int stag_tune_info(stag_ctx *ctx, int32_t gauge_id, int32_t precision,
  * systems per tile, neighbour tables read (1) or computed (0), and whether a
  * reduction kernel sums each step kernel's partial sums (1) or every block of
  * the next kernel does (0).  While fewer systems run than a tile takes, the
- * solve may use smaller tiles tuned alongside.  Does not tune: ENOENT until a
- * solve of that shape has run on the field; EINVAL for a bad precision or
- * count, or a Wilson field.
+ * solve may use smaller tiles tuned alongside.  shared_links = 1: the FP32 /
+ * FP16 tiles that stage each block's links in LDS for all systems of the tile
+ * (one wavefront per system, block = 64 x rhs_tile threads, one lane per
+ * site); 0: register tiles.  Does not tune: ENOENT until a solve of that
+ * shape has run on the field; EINVAL for a bad precision or count, or a
+ * Wilson field.  Any output pointer may be null.
  */
 int stag_cg_tune_info(stag_ctx *ctx, int32_t gauge_id, int32_t precision, int32_t nrhs,
                       int32_t *lanes_per_site, int32_t *block, int32_t *rhs_tile,
-                      int32_t *use_tables, int32_t *reduce);
+                      int32_t *use_tables, int32_t *reduce, int32_t *shared_links);
 
 /* ---- Wilson fermions (the paper's second workload, Sec. 2 and Sec. 6) ------------
  *

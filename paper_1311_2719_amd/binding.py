@@ -148,7 +148,7 @@ def load():
             "stag_serve_config": ([P, I32, I32, I32], ctypes.c_int),
             "stag_tune_info": ([P, I32, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32),
                                 ctypes.POINTER(I32)], ctypes.c_int),
-            "stag_cg_tune_info": ([P, I32, I32, I32] + [ctypes.POINTER(I32)] * 5, ctypes.c_int),
+            "stag_cg_tune_info": ([P, I32, I32, I32] + [ctypes.POINTER(I32)] * 6, ctypes.c_int),
             "stag_version": ([], ctypes.c_char_p),
             "stag_set_gauge_wilson": ([P, P, P, I32, I32, ctypes.POINTER(I32)], ctypes.c_int),
             "stag_pack_spinor": ([P, P, P, P, P], ctypes.c_int),
@@ -609,11 +609,11 @@ class Context:
     def cg_tune_info(self, field: Field, precision=FP64, nrhs=1):
         """The CG step shape tuned for (field, precision, nrhs) once such a
         solve has run (StagError ENOENT before)."""
-        v = [ctypes.c_int32() for _ in range(5)]
+        v = [ctypes.c_int32() for _ in range(6)]
         _check(self.lib.stag_cg_tune_info(self.h, field.gauge_id, int(precision), int(nrhs),
                                           *[ctypes.byref(t) for t in v]), "stag_cg_tune_info")
         return {"lanes_per_site": v[0].value, "block": v[1].value, "rhs_tile": v[2].value,
-                "use_tables": v[3].value, "reduction_kernel": v[4].value}
+                "use_tables": v[3].value, "reduction_kernel": v[4].value, "shared_links": v[5].value}
 
 
 def version() -> str:

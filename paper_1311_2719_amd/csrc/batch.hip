@@ -58,16 +58,28 @@ size_t Batch::workspace_bytes(const Geom &g, int prec, int slots, int pstride)
     return b;
 }
 
+// Blocks that cover the sites of one parity once with shape c: a register
+// tile takes block / lps sites, a shared-link block one chunk of 64.
+static int blocks_needed(const Geom &g, const KernelCfg &c)
+{
+    return c.shared ? (g.Vh + kChunk - 1) / kChunk : blocks_for(g.Vh, c.lps, c.block);
+}
+
+// Largest grid row of a register-tile shape with a reduction kernel; the
+// shared-link shapes may use the whole partial-sum slot.
+constexpr int kTileGridCap = 2048;
+
 // Blocks per tile row of shape c: enough to cover the sites once (the
 // kernels stride over the sites when capped).  Without a reduction kernel the
 // count is capped so that the partial sums every block reads back in the next
-// kernel's prologue stay few; with one, only by the partial buffer.  The tuned
-// shape's count becomes the batch's fixed count (nblk_).
+// kernel's prologue stay few; with one, by kTileGridCap (register tiles) or
+// the partial buffer (shared-link tiles).  The tuned shape's count becomes the
+// batch's fixed count (nblk_).
 int Batch::grid_x(const KernelCfg &c) const
 {
-    const int need = blocks_for(f_->g.Vh, c.lps, c.block);
+    const int need = blocks_needed(f_->g, c);
     if (uses_reduction(c))
-        return std::min(need, pstride_);
+        return std::min(need, c.shared ? pstride_ : std::min(pstride_, kTileGridCap));
     return std::min(need, std::max(128, 2048 / c.rtile));
 }
 
@@ -82,7 +94,7 @@ bool cg_uses_reduction(const Geom &g, const KernelCfg &c)
             return e[0] == '1';
     if (c.reduce >= 0)
         return c.reduce != 0;
-    const int need = blocks_for(g.Vh, c.lps, c.block);
+    const int need = blocks_needed(g, c);
     const int fused = std::min(need, std::max(128, 2048 / c.rtile));
     return (int64_t)fused * c.rtile >= 1024;
 }
@@ -130,9 +142,11 @@ size_t Batch::host_bytes_for(int slots)
     return 3 * nsys * sizeof(SysState) + 2 * nsys * sizeof(void *) + nsys * sizeof(int);
 }
 
+// Partial sums per slot: the widest grid row any shape may use (register
+// tiles: kTileGridCap; shared-link tiles: up to 4096 chunks of 64 sites).
 static int pstride_for(const Geom &g)
 {
-    const int p = std::min(2048, blocks_for(g.Vh, 8, 64));
+    const int p = std::min(4096, std::max(std::min(kTileGridCap, blocks_for(g.Vh, 8, 64)), (g.Vh + kChunk - 1) / kChunk));
     return (p + 63) & ~63;
 }
 
@@ -322,13 +336,15 @@ double Batch::time_cg_config(const KernelCfg &c, int nblk, bool reduce)
     a.psum = reduce ? totals_ : partials_;
     a.psum_stride = reduce ? 1 : pstride_;
     a.nread = reduce ? 1 : nblk;
+    if (c.shared && !t.shared1)
+        return 1e30;
     dim3 grid((unsigned)nblk, (unsigned)(nsys() / c.rtile)), blk(c.block);
     auto step = [&]() {
-        hipError_t e = t.step1(c.lps, c.rtile, grid, blk, s_, a, 0);
+        hipError_t e = c.shared ? t.shared1(c.rtile, grid, s_, a, 0) : t.step1(c.lps, c.rtile, grid, blk, s_, a, 0);
         if (e == hipSuccess && reduce)
             e = launch_reduce(s_, 1, 0, 2, nblk);
         if (e == hipSuccess)
-            e = t.step2(c.lps, c.rtile, grid, blk, s_, a, 0);
+            e = c.shared ? t.shared2(c.rtile, grid, s_, a, 0) : t.step2(c.lps, c.rtile, grid, blk, s_, a, 0);
         if (e == hipSuccess && reduce)
             e = launch_reduce(s_, 1, 2, 1, nblk);
         return e;
@@ -368,6 +384,20 @@ KernelCfg Batch::default_cg_cfg() const
     return best;
 }
 
+// The shared-link shape of tile size R (reduce: as KernelCfg::reduce).
+static KernelCfg shared_shape(int R, int reduce)
+{
+    KernelCfg c;
+    c.lps = 1;
+    c.block = 64 * R;
+    c.rtile = R;
+    c.tables = 0;
+    c.remap = 1;
+    c.reduce = reduce;
+    c.shared = 1;
+    return c;
+}
+
 KernelCfg Batch::tune_cg()
 {
     KernelCfg best = default_cg_cfg();
@@ -375,9 +405,20 @@ KernelCfg Batch::tune_cg()
     const char *env = getenv("STAG_KERNEL_CFG");
     if (env && *env) {
         KernelCfg c;
-        if (sscanf(env, "%d,%d,%d,%d,%d", &c.lps, &c.block, &c.rtile, &c.tables, &c.remap) == 5 &&
-            (c.lps == 1 || c.lps == 2 || c.lps == 4 || c.lps == 8) && c.block >= 64 && c.block <= 256 &&
-            c.block % 64 == 0 && c.rtile > 0 && S_ % c.rtile == 0)
+        const int n = sscanf(env, "%d,%d,%d,%d,%d,%d", &c.lps, &c.block, &c.rtile, &c.tables, &c.remap, &c.shared);
+        if (n < 5 || c.rtile <= 0 || S_ % c.rtile)
+            return best;
+        if (n == 6 && c.shared) {
+            bool have = false;
+            for (int i = 0; i < t.n_stiles; ++i)
+                have |= t.stiles[i] == c.rtile;
+            if (have && c.lps == 1 && c.block == 64 * c.rtile)
+                return c;
+            return best;
+        }
+        c.shared = 0;
+        if ((c.lps == 1 || c.lps == 2 || c.lps == 4 || c.lps == 8) && c.block >= 64 && c.block <= 256 &&
+            c.block % 64 == 0)
             return c;
         return best;
     }
@@ -441,6 +482,25 @@ KernelCfg Batch::tune_cg()
                     }
                 }
     }
+    // shared-link tiles: one shape per tile size (one lane per site, a wavefront per system)
+    for (int i = 0; i < t.n_stiles; ++i) {
+        const int R = t.stiles[i];
+        if (S_ % R)
+            continue;
+        for (int D = 0; D < 2; ++D) {
+            const KernelCfg c = shared_shape(R, D);
+            if (D == 1 && uses_reduction(c) == uses_reduction(shared_shape(R, 0)))
+                continue;  // the mode is forced from the environment
+            const double ms = time_cg_config(c, grid_x(c), uses_reduction(c));
+            if (verbose)
+                fprintf(stderr, "[stag tune cg] V=%d prec=%d slots=%d shared rtile=%d reduce=%d: %.2f us\n",
+                        2 * f_->g.Vh, prec_, S_, R, D, ms * 1e3);
+            if (ms < best_t * 0.99) {
+                best_t = ms;
+                best = c;
+            }
+        }
+    }
     for (int T = 0; T < 2; ++T)
         for (int X = 0; X < 2; ++X) {
             KernelCfg c = best;
@@ -462,15 +522,24 @@ KernelCfg Batch::tune_cg()
     const int nblk = grid_x(best);
     const bool reduce = uses_reduction(best);
     small_.clear();
-    for (int i = 0; i < t.n_rtiles; ++i) {
-        const int R = t.rtiles[i];
-        if (R >= best.rtile || S_ % R)
+    for (int R = 1; R < best.rtile; ++R) {
+        if (S_ % R)
+            continue;
+        bool reg = false, shr = false;
+        for (int i = 0; i < t.n_rtiles; ++i)
+            reg |= t.rtiles[i] == R;
+        for (int i = 0; i < t.n_stiles; ++i)
+            shr |= t.stiles[i] == R;
+        if (!reg && !shr)
             continue;
         KernelCfg sb;
         double sb_t = 1e30;
         for (int L : lps_c)
             for (int B : blk_c) {
+                if (!reg)
+                    break;
                 KernelCfg c = best;
+                c.shared = 0;
                 c.lps = L;
                 c.block = B;
                 c.rtile = R;
@@ -483,7 +552,21 @@ KernelCfg Batch::tune_cg()
                     sb = c;
                 }
             }
-        small_.push_back(sb);
+        if (shr) {
+            KernelCfg c = shared_shape(R, best.reduce);
+            c.tables = best.tables;
+            c.remap = best.remap;
+            const double ms = time_cg_config(c, nblk, reduce);
+            if (verbose)
+                fprintf(stderr, "[stag tune cg] small tile: V=%d prec=%d slots=%d shared rtile=%d blocks=%d: %.2f us\n",
+                        2 * f_->g.Vh, prec_, S_, R, nblk, ms * 1e3);
+            if (ms < sb_t * 0.99) {
+                sb_t = ms;
+                sb = c;
+            }
+        }
+        if (sb_t < 1e29)
+            small_.push_back(sb);
     }
     (void)hipStreamSynchronize(s_);
     (void)hipGetLastError();
@@ -548,7 +631,8 @@ int Batch::upload_and_init(const std::vector<int> &systems)
     const CgArgs a = args();
     const CgLaunchTable &t = cg_table(prec_, f_->rows);
     dim3 grid((unsigned)nblk_, (unsigned)nsys());
-    hipError_t e = t.init(grid, dim3(cfg_.block), s_, a, cfg_.lps);
+    // one thread per site (the init kernel takes any block of up to 256 threads)
+    hipError_t e = cfg_.shared ? t.init(grid, dim3(256), s_, a, 1) : t.init(grid, dim3(cfg_.block), s_, a, cfg_.lps);
     if (e == hipSuccess && reduce_)
         e = launch_reduce(s_, 0, 2, 1, nblk_);
     if (e != hipSuccess)
@@ -593,11 +677,13 @@ int Batch::launch_step(int ver, hipStream_t st, const KernelCfg &c)
     const CgArgs a = args();
     const int R = c.rtile;
     dim3 grid((unsigned)nblk_, (unsigned)(nsys() / R)), blk(c.block);
-    hipError_t e = t.step1(c.lps, R, grid, blk, st, a, ver);
+    if (c.shared && !t.shared1)
+        return set_error(STAG_EINVAL, "no shared-link CG tiles for precision %d", prec_);
+    hipError_t e = c.shared ? t.shared1(R, grid, st, a, ver) : t.step1(c.lps, R, grid, blk, st, a, ver);
     if (e == hipSuccess && reduce_)  // K1's partials: slots 0, 1 of buffer ver ^ 1
         e = launch_reduce(st, ver ^ 1, 0, 2, nblk_);
     if (e == hipSuccess)
-        e = t.step2(c.lps, R, grid, blk, st, a, ver);
+        e = c.shared ? t.shared2(R, grid, st, a, ver) : t.step2(c.lps, R, grid, blk, st, a, ver);
     if (e == hipSuccess && reduce_)  // K2's partials: slot 2 of buffer ver ^ 1
         e = launch_reduce(st, ver ^ 1, 2, 1, nblk_);
     if (e != hipSuccess)
@@ -605,9 +691,12 @@ int Batch::launch_step(int ver, hipStream_t st, const KernelCfg &c)
     return STAG_OK;
 }
 
+// Key of the recorded epoch of `steps` steps with shape c (one shape per tile size).
+static int graph_key(const KernelCfg &c, int steps) { return ((c.shared << 6) | c.rtile) * 1024 + steps; }
+
 int Batch::record_epoch(int steps, const KernelCfg &c)
 {
-    const int key = c.rtile * 1024 + steps;
+    const int key = graph_key(c, steps);
     if (graphs_.count(key))
         return STAG_OK;
     hipGraph_t graph = nullptr;
@@ -658,7 +747,7 @@ int Batch::enqueue_epoch(int steps)
     int rc = record_epoch(steps, c);
     if (rc != STAG_OK)
         return rc;
-    auto it = graphs_.find(c.rtile * 1024 + steps);
+    auto it = graphs_.find(graph_key(c, steps));
     STAG_HIP_CHECK(hipGraphLaunch(it->second, s_));
     return STAG_OK;
 }

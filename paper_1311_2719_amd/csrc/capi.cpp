@@ -724,7 +724,7 @@ int stag_tune_info(stag_ctx *ctx, int32_t gauge_id, int32_t precision, int32_t n
 }
 
 int stag_cg_tune_info(stag_ctx *ctx, int32_t gauge_id, int32_t precision, int32_t nrhs, int32_t *lanes_per_site,
-                      int32_t *block, int32_t *rhs_tile, int32_t *use_tables, int32_t *reduce)
+                      int32_t *block, int32_t *rhs_tile, int32_t *use_tables, int32_t *reduce, int32_t *shared_links)
 {
     STAG_GUARD_BEGIN
     clear_error();
@@ -751,6 +751,8 @@ int stag_cg_tune_info(stag_ctx *ctx, int32_t gauge_id, int32_t precision, int32_
         *use_tables = k.tables;
     if (reduce)
         *reduce = red ? 1 : 0;
+    if (shared_links)
+        *shared_links = k.shared;
     return STAG_OK;
     STAG_GUARD_END
 }

@@ -1,9 +1,12 @@
-// CG step kernels, initialisation and tuning probe for the F16 working
+// CG step kernels, initialisation, tuning probe and shared-link tiles for the F16 working
 // precision, all three link rows stored.
 #include "cg_launch.hpp"
 
 namespace stag {
 
-const CgLaunchTable &cg_table_f16() { return TileTable<PrecF16, 3, 1, 2, 3, 4, 6, 8, 12>::table(); }
+const CgLaunchTable &cg_table_f16()
+{
+    return with_shared<TileTable<PrecF16, 3, 1, 2, 3, 4, 6, 8, 12>, SharedTable<PrecF16, 3, 2, 3, 4, 6, 8, 12, 16>>();
+}
 
 }  // namespace stag

@@ -1,9 +1,12 @@
-// CG step kernels, initialisation and tuning probe for the F32 working
+// CG step kernels, initialisation, tuning probe and shared-link tiles for the F32 working
 // precision, all three link rows stored.
 #include "cg_launch.hpp"
 
 namespace stag {
 
-const CgLaunchTable &cg_table_f32() { return TileTable<PrecF32, 3, 1, 2, 3, 4, 6, 8, 12>::table(); }
+const CgLaunchTable &cg_table_f32()
+{
+    return with_shared<TileTable<PrecF32, 3, 1, 2, 3, 4, 6, 8, 12>, SharedTable<PrecF32, 3, 2, 3, 4, 6, 8, 12, 16>>();
+}
 
 }  // namespace stag

@@ -445,6 +445,74 @@ template <class P, int R, int LPS> struct OwnSite {
     }
 };
 
+// ---- residual recomputation (FP64), one system at one site --------------------------
+// The reliable update of mixed precision and the final true-residual check.
+// K1 side: t = D (x_hi + x_lo) on the other parity.
+template <int LPS, int ROWS, int UNROLL = kRecomputeUnroll>
+__device__ __forceinline__ void recompute_k1(const CgArgs &a, int j, int pout, int s, int sub)
+{
+    const int Vh = a.g.Vh;
+    const dbl2 *xh = a.xhi[j];
+    const flt2 *xl = a.xlo ? a.xlo + (size_t)j * 3 * Vh : nullptr;
+    cplx<double> acc[1][3] = {{czero<double>(), czero<double>(), czero<double>()}};
+    auto load = [&](int, int n, cplx<double> *chi) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            dbl2 v = xh[(int64_t)c * Vh + n];
+            if (xl) {
+                const flt2 w = xl[(int64_t)c * Vh + n];
+                v.x += (double)w.x;
+                v.y += (double)w.y;
+            }
+            chi[c] = {v.x, v.y};
+        }
+    };
+    hop_accumulate<PrecF64, LPS, 1, decltype(load), true, ROWS, UNROLL>(a.g, a.links64[pout], a.nbr[pout],
+                                                                                  pout, s, sub, acc, load);
+    dbl2 *t = a.tmp + (size_t)j * 3 * Vh;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        if (owns_colour<LPS>(sub, c))
+            t[(int64_t)c * Vh + s] = dbl2{acc[0][c].re, acc[0][c].im};
+}
+
+// K2 side: x_hi += x_lo, x_lo = 0, r = b - m^2 x_hi + D t; this lane's
+// terms of <r,r> are added to nrm.
+template <class P, int LPS, int ROWS, int UNROLL = kRecomputeUnroll>
+__device__ __forceinline__ void recompute_k2(const CgArgs &a, int j, int par, int s, int sub, double m2d, double &nrm)
+{
+    using real = typename P::real;
+    using v2 = typename vec2_of<real>::type;
+    const int Vh = a.g.Vh;
+    const dbl2 *t = a.tmp + (size_t)j * 3 * Vh;
+    cplx<double> acc[1][3] = {{czero<double>(), czero<double>(), czero<double>()}};
+    auto load = [&](int, int n, cplx<double> *chi) { PrecF64::load_spinor(t, Vh, n, chi); };
+    hop_accumulate<PrecF64, LPS, 1, decltype(load), true, ROWS, UNROLL>(a.g, a.links64[par], a.nbr[par], par,
+                                                                                  s, sub, acc, load);
+    dbl2 *x = a.xhi[j];
+    const dbl2 *b = a.b[j];
+    v2 *rv = (v2 *)a.r + (size_t)j * 3 * Vh;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (!owns_colour<LPS>(sub, c))
+            continue;
+        const int64_t o = (int64_t)c * Vh + s;
+        dbl2 xv = x[o];
+        if constexpr (P::id != 0) {
+            const flt2 w = a.xlo[(size_t)j * 3 * Vh + o];
+            xv.x += (double)w.x;
+            xv.y += (double)w.y;
+            x[o] = xv;
+            a.xlo[(size_t)j * 3 * Vh + o] = flt2{0.f, 0.f};
+        }
+        const dbl2 bv = b[o];
+        const double rre = bv.x - m2d * xv.x + acc[0][c].re;
+        const double rim = bv.y - m2d * xv.y + acc[0][c].im;
+        rv[o] = v2{(real)rre, (real)rim};
+        nrm += rre * rre + rim * rim;
+    }
+}
+
 // ---- K1 -----------------------------------------------------------------------------
 
 template <class P, int LPS, int R, int ROWS>
@@ -599,35 +667,11 @@ __global__ void __launch_bounds__(256) k_cg_step1(CgArgs a, int ver)
             site_of_thread<LPS>((int)gt, s, sub);
             if (s >= Vh)
                 continue;
-            // residual recomputation: t = D (x_hi + x_lo) in FP64, one system at a time
+            // residual recomputation in FP64, one system at a time
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (!ru[r])
-                    continue;
-                const int j = js[r];
-                const dbl2 *xh = a.xhi[j];
-                const flt2 *xl = a.xlo ? a.xlo + (size_t)j * 3 * Vh : nullptr;
-                cplx<double> acc[1][3] = {{czero<double>(), czero<double>(), czero<double>()}};
-                auto load = [&](int, int n, cplx<double> *chi) {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        dbl2 v = xh[(int64_t)c * Vh + n];
-                        if (xl) {
-                            const flt2 w = xl[(int64_t)c * Vh + n];
-                            v.x += (double)w.x;
-                            v.y += (double)w.y;
-                        }
-                        chi[c] = {v.x, v.y};
-                    }
-                };
-                hop_accumulate<PrecF64, LPS, 1, decltype(load), true, ROWS, kRecomputeUnroll>(
-                    a.g, a.links64[pout], a.nbr[pout], pout, s, sub, acc, load);
-                dbl2 *t = a.tmp + (size_t)j * 3 * Vh;
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    if (owns_colour<LPS>(sub, c))
-                        t[(int64_t)c * Vh + s] = dbl2{acc[0][c].re, acc[0][c].im};
-            }
+            for (int r = 0; r < R; ++r)
+                if (ru[r])
+                    recompute_k1<LPS, ROWS>(a, js[r], pout, s, sub);
         }
     }
     if (!anycg)
@@ -776,41 +820,11 @@ __global__ void __launch_bounds__(256) k_cg_step2(CgArgs a, int ver)
             site_of_thread<LPS>((int)gt, s, sub);
             if (s >= Vh)
                 continue;
-            // residual recomputation: x_hi += x_lo, r = b - m^2 x_hi + D t in FP64
+            // residual recomputation in FP64, one system at a time
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (!ru[r])
-                    continue;
-                const int j = js[r];
-                const dbl2 *t = a.tmp + (size_t)j * 3 * Vh;
-                cplx<double> acc[1][3] = {{czero<double>(), czero<double>(), czero<double>()}};
-                auto load = [&](int, int n, cplx<double> *chi) { PrecF64::load_spinor(t, Vh, n, chi); };
-                hop_accumulate<PrecF64, LPS, 1, decltype(load), true, ROWS, kRecomputeUnroll>(
-                    a.g, a.links64[par], a.nbr[par], par, s, sub, acc, load);
-                const double m2d = uniform(sst[r].mass2);
-                dbl2 *x = a.xhi[j];
-                const dbl2 *b = a.b[j];
-                v2 *rv = (v2 *)a.r + (size_t)j * 3 * Vh;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    if (!owns_colour<LPS>(sub, c))
-                        continue;
-                    const int64_t o = (int64_t)c * Vh + s;
-                    dbl2 xv = x[o];
-                    if constexpr (P::id != 0) {
-                        const flt2 w = a.xlo[(size_t)j * 3 * Vh + o];
-                        xv.x += (double)w.x;
-                        xv.y += (double)w.y;
-                        x[o] = xv;
-                        a.xlo[(size_t)j * 3 * Vh + o] = flt2{0.f, 0.f};
-                    }
-                    const dbl2 bv = b[o];
-                    const double rre = bv.x - m2d * xv.x + acc[0][c].re;
-                    const double rim = bv.y - m2d * xv.y + acc[0][c].im;
-                    rv[o] = v2{(real)rre, (real)rim};
-                    nrm[r] += rre * rre + rim * rim;
-                }
-            }
+            for (int r = 0; r < R; ++r)
+                if (ru[r])
+                    recompute_k2<P, LPS, ROWS>(a, js[r], par, s, sub, uniform(sst[r].mass2), nrm[r]);
         }
     }
     double tot2;

@@ -4,7 +4,7 @@
 // cg_table(prec, rows).
 #pragma once
 
-#include "cg_kernels.hpp"
+#include "cg_shared.hpp"
 
 namespace stag {
 
@@ -19,6 +19,12 @@ struct CgLaunchTable {
                         const int32_t *nbr, const void *in, void *out, int remap);
     const int *rtiles;  // right-hand-side tile sizes compiled for this precision
     int n_rtiles;
+    // shared-link tiles (FP32 / FP16 working precision; null otherwise): R
+    // wavefronts per block, one system each, the block's links staged in LDS
+    hipError_t (*shared1)(int R, dim3 grid, hipStream_t s, const CgArgs &a, int ver);
+    hipError_t (*shared2)(int R, dim3 grid, hipStream_t s, const CgArgs &a, int ver);
+    const int *stiles;
+    int n_stiles;
 };
 
 const CgLaunchTable &cg_table(int prec, int rows);
@@ -88,9 +94,56 @@ template <class P, int ROWS, int... Rs> struct TileTable {
     }
     static const CgLaunchTable &table()
     {
-        static const CgLaunchTable t = {step1, step2, PLaunch<P>::init, probe, tiles, (int)sizeof...(Rs)};
+        static const CgLaunchTable t = {step1, step2, PLaunch<P>::init, probe, tiles, (int)sizeof...(Rs),
+                                        nullptr, nullptr, nullptr, 0};
         return t;
     }
 };
+
+template <class P, int R, int ROWS> struct SLaunch {
+    static hipError_t step1(dim3 grid, hipStream_t s, const CgArgs &a, int ver)
+    {
+        hipLaunchKernelGGL((k_cg_shared1<P, R, ROWS>), grid, dim3(64 * R), 0, s, a, ver);
+        return hipGetLastError();
+    }
+    static hipError_t step2(dim3 grid, hipStream_t s, const CgArgs &a, int ver)
+    {
+        hipLaunchKernelGGL((k_cg_shared2<P, R, ROWS>), grid, dim3(64 * R), 0, s, a, ver);
+        return hipGetLastError();
+    }
+};
+
+// The shared-link kernels of precision P and link rows ROWS for tiles Rs...
+// (block = 64 R threads); a tile size not in Rs is rejected.
+template <class P, int ROWS, int... Rs> struct SharedTable {
+    static constexpr int tiles[] = {Rs...};
+
+    static hipError_t shared1(int R, dim3 grid, hipStream_t s, const CgArgs &a, int ver)
+    {
+        hipError_t e = hipErrorInvalidValue;
+        (void)((R == Rs && ((e = SLaunch<P, Rs, ROWS>::step1(grid, s, a, ver)), true)) || ...);
+        return e;
+    }
+    static hipError_t shared2(int R, dim3 grid, hipStream_t s, const CgArgs &a, int ver)
+    {
+        hipError_t e = hipErrorInvalidValue;
+        (void)((R == Rs && ((e = SLaunch<P, Rs, ROWS>::step2(grid, s, a, ver)), true)) || ...);
+        return e;
+    }
+};
+
+// A register-tile table with the shared-link kernels of S added.
+template <class T, class S> const CgLaunchTable &with_shared()
+{
+    static const CgLaunchTable t = [] {
+        CgLaunchTable x = T::table();
+        x.shared1 = S::shared1;
+        x.shared2 = S::shared2;
+        x.stiles = S::tiles;
+        x.n_stiles = (int)(sizeof(S::tiles) / sizeof(S::tiles[0]));
+        return x;
+    }();
+    return t;
+}
 
 }  // namespace stag

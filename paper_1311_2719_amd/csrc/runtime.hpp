@@ -64,6 +64,7 @@ struct KernelCfg {
     int remap = 1;      // XCD-aware block order
     int reduce = -1;    // CG: 1 reduction kernel between step kernels, 0 prologues sum the
                         // partials, -1 chosen by grid size
+    int shared = 0;     // CG, FP32 / FP16: 1 shared-link tiles (block = 64 rtile, one lane per site)
 };
 
 // ---- gauge field -------------------------------------------------------------
