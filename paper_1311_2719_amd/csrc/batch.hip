@@ -340,11 +340,13 @@ double Batch::time_cg_config(const KernelCfg &c, int nblk, bool reduce)
         return 1e30;
     dim3 grid((unsigned)nblk, (unsigned)(nsys() / c.rtile)), blk(c.block);
     auto step = [&]() {
-        hipError_t e = c.shared ? t.shared1(c.rtile, grid, s_, a, 0) : t.step1(c.lps, c.rtile, grid, blk, s_, a, 0);
+        hipError_t e = c.shared ? t.shared1(c.rtile, c.block / 64, grid, s_, a, 0)
+                                 : t.step1(c.lps, c.rtile, grid, blk, s_, a, 0);
         if (e == hipSuccess && reduce)
             e = launch_reduce(s_, 1, 0, 2, nblk);
         if (e == hipSuccess)
-            e = c.shared ? t.shared2(c.rtile, grid, s_, a, 0) : t.step2(c.lps, c.rtile, grid, blk, s_, a, 0);
+            e = c.shared ? t.shared2(c.rtile, c.block / 64, grid, s_, a, 0)
+                         : t.step2(c.lps, c.rtile, grid, blk, s_, a, 0);
         if (e == hipSuccess && reduce)
             e = launch_reduce(s_, 1, 2, 1, nblk);
         return e;
@@ -384,13 +386,15 @@ KernelCfg Batch::default_cg_cfg() const
     return best;
 }
 
-// The shared-link shape of tile size R (reduce: as KernelCfg::reduce).
-static KernelCfg shared_shape(int R, int reduce)
+// The shared-link shape of compiled shape code `code` (W wavefronts of RR
+// systems, shared_code(W, RR)); reduce: as KernelCfg::reduce.
+static KernelCfg shared_shape(int code, int reduce)
 {
+    const int W = code % 100, RR = code / 100;
     KernelCfg c;
     c.lps = 1;
-    c.block = 64 * R;
-    c.rtile = R;
+    c.block = 64 * W;
+    c.rtile = W * RR;
     c.tables = 0;
     c.remap = 1;
     c.reduce = reduce;
@@ -410,9 +414,10 @@ KernelCfg Batch::tune_cg()
             return best;
         if (n == 6 && c.shared) {
             bool have = false;
+            const int W = c.block / 64;
             for (int i = 0; i < t.n_stiles; ++i)
-                have |= t.stiles[i] == c.rtile;
-            if (have && c.lps == 1 && c.block == 64 * c.rtile)
+                have |= c.block % 64 == 0 && W > 0 && c.rtile % W == 0 && t.stiles[i] == shared_code(W, c.rtile / W);
+            if (have && c.lps == 1)
                 return c;
             return best;
         }
@@ -484,17 +489,17 @@ KernelCfg Batch::tune_cg()
     }
     // shared-link tiles: one shape per tile size (one lane per site, a wavefront per system)
     for (int i = 0; i < t.n_stiles; ++i) {
-        const int R = t.stiles[i];
-        if (S_ % R)
+        const int code = t.stiles[i];
+        if (S_ % shared_shape(code, 0).rtile)
             continue;
         for (int D = 0; D < 2; ++D) {
-            const KernelCfg c = shared_shape(R, D);
-            if (D == 1 && uses_reduction(c) == uses_reduction(shared_shape(R, 0)))
+            const KernelCfg c = shared_shape(code, D);
+            if (D == 1 && uses_reduction(c) == uses_reduction(shared_shape(code, 0)))
                 continue;  // the mode is forced from the environment
             const double ms = time_cg_config(c, grid_x(c), uses_reduction(c));
             if (verbose)
-                fprintf(stderr, "[stag tune cg] V=%d prec=%d slots=%d shared rtile=%d reduce=%d: %.2f us\n",
-                        2 * f_->g.Vh, prec_, S_, R, D, ms * 1e3);
+                fprintf(stderr, "[stag tune cg] V=%d prec=%d slots=%d shared rtile=%d waves=%d reduce=%d: %.2f us\n",
+                        2 * f_->g.Vh, prec_, S_, c.rtile, c.block / 64, D, ms * 1e3);
             if (ms < best_t * 0.99) {
                 best_t = ms;
                 best = c;
@@ -529,7 +534,7 @@ KernelCfg Batch::tune_cg()
         for (int i = 0; i < t.n_rtiles; ++i)
             reg |= t.rtiles[i] == R;
         for (int i = 0; i < t.n_stiles; ++i)
-            shr |= t.stiles[i] == R;
+            shr |= shared_shape(t.stiles[i], 0).rtile == R;
         if (!reg && !shr)
             continue;
         KernelCfg sb;
@@ -552,14 +557,16 @@ KernelCfg Batch::tune_cg()
                     sb = c;
                 }
             }
-        if (shr) {
-            KernelCfg c = shared_shape(R, best.reduce);
+        for (int i = 0; shr && i < t.n_stiles; ++i) {
+            KernelCfg c = shared_shape(t.stiles[i], best.reduce);
+            if (c.rtile != R)
+                continue;
             c.tables = best.tables;
             c.remap = best.remap;
             const double ms = time_cg_config(c, nblk, reduce);
             if (verbose)
-                fprintf(stderr, "[stag tune cg] small tile: V=%d prec=%d slots=%d shared rtile=%d blocks=%d: %.2f us\n",
-                        2 * f_->g.Vh, prec_, S_, R, nblk, ms * 1e3);
+                fprintf(stderr, "[stag tune cg] small tile: V=%d prec=%d slots=%d shared rtile=%d waves=%d blocks=%d: "
+                                "%.2f us\n", 2 * f_->g.Vh, prec_, S_, R, c.block / 64, nblk, ms * 1e3);
             if (ms < sb_t * 0.99) {
                 sb_t = ms;
                 sb = c;
@@ -679,11 +686,11 @@ int Batch::launch_step(int ver, hipStream_t st, const KernelCfg &c)
     dim3 grid((unsigned)nblk_, (unsigned)(nsys() / R)), blk(c.block);
     if (c.shared && !t.shared1)
         return set_error(STAG_EINVAL, "no shared-link CG tiles for precision %d", prec_);
-    hipError_t e = c.shared ? t.shared1(R, grid, st, a, ver) : t.step1(c.lps, R, grid, blk, st, a, ver);
+    hipError_t e = c.shared ? t.shared1(R, c.block / 64, grid, st, a, ver) : t.step1(c.lps, R, grid, blk, st, a, ver);
     if (e == hipSuccess && reduce_)  // K1's partials: slots 0, 1 of buffer ver ^ 1
         e = launch_reduce(st, ver ^ 1, 0, 2, nblk_);
     if (e == hipSuccess)
-        e = c.shared ? t.shared2(R, grid, st, a, ver) : t.step2(c.lps, R, grid, blk, st, a, ver);
+        e = c.shared ? t.shared2(R, c.block / 64, grid, st, a, ver) : t.step2(c.lps, R, grid, blk, st, a, ver);
     if (e == hipSuccess && reduce_)  // K2's partials: slot 2 of buffer ver ^ 1
         e = launch_reduce(st, ver ^ 1, 2, 1, nblk_);
     if (e != hipSuccess)
@@ -692,7 +699,10 @@ int Batch::launch_step(int ver, hipStream_t st, const KernelCfg &c)
 }
 
 // Key of the recorded epoch of `steps` steps with shape c (one shape per tile size).
-static int graph_key(const KernelCfg &c, int steps) { return ((c.shared << 6) | c.rtile) * 1024 + steps; }
+static int graph_key(const KernelCfg &c, int steps)
+{
+    return ((c.shared ? c.block / 64 : 0) * 64 + c.rtile) * 1024 + steps;
+}
 
 int Batch::record_epoch(int steps, const KernelCfg &c)
 {

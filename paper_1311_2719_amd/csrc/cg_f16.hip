@@ -6,7 +6,7 @@ namespace stag {
 
 const CgLaunchTable &cg_table_f16()
 {
-    return with_shared<TileTable<PrecF16, 3, 1, 2, 3, 4, 6, 8, 12>, SharedTable<PrecF16, 3, 2, 3, 4, 6, 8, 12, 16>>();
+    return with_shared<TileTable<PrecF16, 3, 1, 2, 3, 4, 6, 8, 12>, SharedTable<PrecF16, 3, STAG_SHARED_SHAPES>>();
 }
 
 }  // namespace stag

@@ -6,7 +6,7 @@ namespace stag {
 
 const CgLaunchTable &cg_table_f16_r2()
 {
-    return with_shared<TileTable<PrecF16, 2, 1, 2, 3, 4, 6, 8, 12>, SharedTable<PrecF16, 2, 2, 3, 4, 6, 8, 12, 16>>();
+    return with_shared<TileTable<PrecF16, 2, 1, 2, 3, 4, 6, 8, 12>, SharedTable<PrecF16, 2, STAG_SHARED_SHAPES>>();
 }
 
 }  // namespace stag

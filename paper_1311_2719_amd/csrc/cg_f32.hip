@@ -6,7 +6,7 @@ namespace stag {
 
 const CgLaunchTable &cg_table_f32()
 {
-    return with_shared<TileTable<PrecF32, 3, 1, 2, 3, 4, 6, 8, 12>, SharedTable<PrecF32, 3, 2, 3, 4, 6, 8, 12, 16>>();
+    return with_shared<TileTable<PrecF32, 3, 1, 2, 3, 4, 6, 8, 12>, SharedTable<PrecF32, 3, STAG_SHARED_SHAPES>>();
 }
 
 }  // namespace stag

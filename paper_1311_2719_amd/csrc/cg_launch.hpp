@@ -19,10 +19,11 @@ struct CgLaunchTable {
                         const int32_t *nbr, const void *in, void *out, int remap);
     const int *rtiles;  // right-hand-side tile sizes compiled for this precision
     int n_rtiles;
-    // shared-link tiles (FP32 / FP16 working precision; null otherwise): R
-    // wavefronts per block, one system each, the block's links staged in LDS
-    hipError_t (*shared1)(int R, dim3 grid, hipStream_t s, const CgArgs &a, int ver);
-    hipError_t (*shared2)(int R, dim3 grid, hipStream_t s, const CgArgs &a, int ver);
+    // shared-link tiles (FP32 / FP16 working precision; null otherwise): W
+    // wavefronts per block, R / W systems each, the block's links staged in
+    // LDS; stiles lists the compiled shapes as shared_code(W, R / W)
+    hipError_t (*shared1)(int R, int W, dim3 grid, hipStream_t s, const CgArgs &a, int ver);
+    hipError_t (*shared2)(int R, int W, dim3 grid, hipStream_t s, const CgArgs &a, int ver);
     const int *stiles;
     int n_stiles;
 };
@@ -100,37 +101,52 @@ template <class P, int ROWS, int... Rs> struct TileTable {
     }
 };
 
-template <class P, int R, int ROWS> struct SLaunch {
+template <class P, int W, int RR, int ROWS> struct SLaunch {
     static hipError_t step1(dim3 grid, hipStream_t s, const CgArgs &a, int ver)
     {
-        hipLaunchKernelGGL((k_cg_shared1<P, R, ROWS>), grid, dim3(64 * R), 0, s, a, ver);
+        hipLaunchKernelGGL((k_cg_shared1<P, W, RR, ROWS>), grid, dim3(64 * W), 0, s, a, ver);
         return hipGetLastError();
     }
     static hipError_t step2(dim3 grid, hipStream_t s, const CgArgs &a, int ver)
     {
-        hipLaunchKernelGGL((k_cg_shared2<P, R, ROWS>), grid, dim3(64 * R), 0, s, a, ver);
+        hipLaunchKernelGGL((k_cg_shared2<P, W, RR, ROWS>), grid, dim3(64 * W), 0, s, a, ver);
         return hipGetLastError();
     }
 };
 
-// The shared-link kernels of precision P and link rows ROWS for tiles Rs...
-// (block = 64 R threads); a tile size not in Rs is rejected.
-template <class P, int ROWS, int... Rs> struct SharedTable {
-    static constexpr int tiles[] = {Rs...};
+// Shape code of a shared-link tile: RR systems per wavefront, W wavefronts
+// per block (tile R = W RR, block = 64 W threads).
+constexpr int shared_code(int W, int RR) { return RR * 100 + W; }
 
-    static hipError_t shared1(int R, dim3 grid, hipStream_t s, const CgArgs &a, int ver)
+// The shared-link kernels of precision P and link rows ROWS for the shapes
+// Codes... (shared_code values); a shape not in the list is rejected.
+template <class P, int ROWS, int... Codes> struct SharedTable {
+    static constexpr int tiles[] = {Codes...};
+
+    static hipError_t shared1(int R, int W, dim3 grid, hipStream_t s, const CgArgs &a, int ver)
     {
         hipError_t e = hipErrorInvalidValue;
-        (void)((R == Rs && ((e = SLaunch<P, Rs, ROWS>::step1(grid, s, a, ver)), true)) || ...);
+        (void)(((W > 0 && R % W == 0 && shared_code(W, R / W) == Codes) &&
+                ((e = SLaunch<P, Codes % 100, Codes / 100, ROWS>::step1(grid, s, a, ver)), true)) ||
+               ...);
         return e;
     }
-    static hipError_t shared2(int R, dim3 grid, hipStream_t s, const CgArgs &a, int ver)
+    static hipError_t shared2(int R, int W, dim3 grid, hipStream_t s, const CgArgs &a, int ver)
     {
         hipError_t e = hipErrorInvalidValue;
-        (void)((R == Rs && ((e = SLaunch<P, Rs, ROWS>::step2(grid, s, a, ver)), true)) || ...);
+        (void)(((W > 0 && R % W == 0 && shared_code(W, R / W) == Codes) &&
+                ((e = SLaunch<P, Codes % 100, Codes / 100, ROWS>::step2(grid, s, a, ver)), true)) ||
+               ...);
         return e;
     }
 };
+
+// The shapes compiled for FP32 and FP16: one system per wavefront for tiles
+// of 2 to 16, two for tiles of 4 to 16, three for tiles of 3, 6 and 12.
+#define STAG_SHARED_SHAPES                                                                                   \
+    shared_code(2, 1), shared_code(3, 1), shared_code(4, 1), shared_code(6, 1), shared_code(8, 1),            \
+        shared_code(12, 1), shared_code(16, 1), shared_code(2, 2), shared_code(3, 2), shared_code(4, 2),      \
+        shared_code(6, 2), shared_code(8, 2), shared_code(1, 3), shared_code(2, 3), shared_code(4, 3)
 
 // A register-tile table with the shared-link kernels of S added.
 template <class T, class S> const CgLaunchTable &with_shared()

@@ -4,22 +4,22 @@
 // The register tiles of cg_kernels.hpp share a link load between the R
 // systems one thread carries, so their per-thread state grows with R and the
 // tuner settles on R = 2 or 3 at 24^4: every link is then read from HBM
-// S / R times per kernel.  Here a block is R wavefronts; wavefront w runs
-// system w of the block's tile on 64 consecutive output sites, one lane per
-// site.  The block first reads the links of those 64 sites (8 directions,
-// stored rows), rebuilds row 2 where only two are stored, converts them to
-// FP32 and keeps all nine entries in LDS; every wavefront then runs a
-// single-system hop that takes its links from there.  A link thus costs one
-// HBM read per R systems (R up to 16, one tile per parity at 12 or 16
-// systems), the third row and the FP16 conversion are computed once per
-// block instead of once per thread, and a wavefront holds the registers of
-// one system only.
+// S / R times per kernel.  Here a block is W wavefronts, each running RR
+// systems of the block's tile (R = W RR) on 64 consecutive output sites, one
+// lane per site.  The block first reads the links of those 64 sites (8
+// directions, stored rows), rebuilds row 2 where only two are stored,
+// converts them to FP32 and keeps all nine entries in LDS; every wavefront
+// then runs the hop of its RR systems with the links taken from there.  A
+// link thus costs one HBM read per R systems (R up to 16: one tile per parity
+// at 12 or 16 systems), the third row and the FP16 conversion are computed
+// once per block instead of once per thread, and a wavefront holds the
+// registers of RR systems only.
 //
 // The step arithmetic is that of k_cg_step1 / k_cg_step2 (the loop of the
 // paper's Sec. 4 with the mass explicit): same products, same storage
 // formats, same state machine (advance()); only the summation order of the
-// partial sums differs (one system per wavefront: lane sums over the chunks
-// a block visits, then the wavefront sum).
+// partial sums differs (each system's sums stay in one wavefront: lane sums
+// over the chunks a block visits, then the wavefront sum).
 //
 // LDS layout of one chunk: [entry 9][dir 8][site 64 + 8] of FP32 complex.  A
 // wavefront reading one (entry, dir) for its 64 sites touches 512 contiguous
@@ -33,7 +33,7 @@ namespace stag {
 
 constexpr int kChunk = 64;              // output sites per block and round
 constexpr int kLdsRow = kChunk + 8;     // padded row of one (entry, dir)
-constexpr int kSharedMaxR = 16;         // wavefronts (systems) per block
+constexpr int kSharedMaxR = 16;         // systems per tile
 // Directions of the hop whose gathers a wavefront keeps in flight together,
 // and the wavefronts per SIMD the register allocation must allow.  A fully
 // unrolled hop holds the gathers of all eight directions (about 130 VGPRs);
@@ -72,11 +72,12 @@ __device__ __forceinline__ void stage_chunk_links(const Geom &g, const typename 
     }
 }
 
-// acc[a] += sum_d L_d(s)[a][b] chi_d[b], the links from the staged chunk
-// (lane i = site s0 + i), load(n, chi) the input at neighbour n.
-template <bool TABLES, class Load>
+// acc[q][a] += sum_d L_d(s)[a][b] chi_qd[b] for the RR systems of a
+// wavefront, the links from the staged chunk (lane i = site s0 + i),
+// load(q, n, chi) the input of system q at neighbour n.
+template <bool TABLES, int RR, class Load>
 __device__ __forceinline__ void hop_shared_impl(const Geom &g, const int32_t *__restrict__ nbr, int p_out, int s,
-                                                int i, const flt2 *lk, cplx<float> (&acc)[3], Load load)
+                                                int i, const flt2 *lk, cplx<float> (&acc)[RR][3], Load load)
 {
     SiteCoord c;
     if constexpr (!TABLES)
@@ -88,8 +89,10 @@ __device__ __forceinline__ void hop_shared_impl(const Geom &g, const int32_t *__
             n = nbr[(int64_t)d * g.Vh + s];
         else
             n = neighbour(g, c, s, d);
-        cplx<float> chi[3];
-        load(n, chi);
+        cplx<float> chi[RR][3];
+#pragma unroll
+        for (int q = 0; q < RR; ++q)
+            load(q, n, chi[q]);
         cplx<float> U[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
@@ -97,21 +100,23 @@ __device__ __forceinline__ void hop_shared_impl(const Geom &g, const int32_t *__
             U[k] = {v.x, v.y};
         }
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+        for (int q = 0; q < RR; ++q)
 #pragma unroll
-            for (int b = 0; b < 3; ++b)
-                cmac(acc[a], U[a * 3 + b], chi[b]);
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    cmac(acc[q][a], U[a * 3 + b], chi[q][b]);
     }
 }
 
-template <class Load>
+template <int RR, class Load>
 __device__ __forceinline__ void hop_shared(const Geom &g, const int32_t *nbr, int p_out, int s, int i, const flt2 *lk,
-                                           cplx<float> (&acc)[3], Load load)
+                                           cplx<float> (&acc)[RR][3], Load load)
 {
     if (nbr)
-        hop_shared_impl<true>(g, nbr, p_out, s, i, lk, acc, load);
+        hop_shared_impl<true, RR>(g, nbr, p_out, s, i, lk, acc, load);
     else
-        hop_shared_impl<false>(g, nbr, p_out, s, i, lk, acc, load);
+        hop_shared_impl<false, RR>(g, nbr, p_out, s, i, lk, acc, load);
 }
 
 // Totals of slots [0, NS) of system j's partial sums (the previous kernel's
@@ -142,10 +147,15 @@ __device__ __forceinline__ int chunk_start(int it, int Vh, int remap)
 }
 
 // ---- K1 -----------------------------------------------------------------------------
+// A block of W wavefronts runs a tile of R = W RR systems; wavefront w takes
+// places w RR .. w RR + RR - 1.  Like the register tiles, a wavefront gathers
+// for each of its places, also places whose system is not in a CG step (their
+// sums are discarded), so that the direction loop has no per-system branch.
 
-template <class P, int R, int ROWS>
-__global__ void __launch_bounds__(64 * R, kSharedMinWaves) k_cg_shared1(CgArgs a, int ver)
+template <class P, int W, int RR, int ROWS>
+__global__ void __launch_bounds__(64 * W, kSharedMinWaves) k_cg_shared1(CgArgs a, int ver)
 {
+    constexpr int R = W * RR;
     static_assert(P::id != 0 && R <= kSharedMaxR, "shared-link tiles: FP32 / FP16 working precision");
     using real = typename P::real;
     using v2 = typename vec2_of<real>::type;
@@ -154,25 +164,41 @@ __global__ void __launch_bounds__(64 * R, kSharedMinWaves) k_cg_shared1(CgArgs a
     const int tpp = a.S / R;
     const int par = blockIdx.y / tpp, k0 = par * a.S + (blockIdx.y % tpp) * R, pout = 1 - par;
     const int Vh = a.g.Vh;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int j = a.perm[k0 + w];
-    // prologue: this wavefront advances its own system over the previous step
-    SysState st{};
-    int mode = M_IDLE;
-    if (j >= 0) {
-        double t[3];
-        wave_prologue_sums<3>(a, ver, j, t);
-        st = a.st[ver][j];
-        const bool live = st.mode != M_IDLE && st.mode != M_DONE;
-        if (live)
-            advance(st, t);
-        // the state K2 of this step reads: advanced, or the same idle/done state
-        if (blockIdx.x == 0 && lane == 0)
-            a.st[ver ^ 1][j] = st;
-        mode = live ? uniform(st.mode) : (int)M_IDLE;
+    // the wavefront index is the same in every lane: kept in a scalar register,
+    // so that its systems, their states and pointers stay scalar too
+    const int w = uniform((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    // prologue: this wavefront advances its own systems over the previous step
+    int js[RR];
+    bool cg[RR], ru[RR];
+    real beta[RR];
+    int pc[RR];
+#pragma unroll
+    for (int q = 0; q < RR; ++q) {
+        const int j = a.perm[k0 + w * RR + q];
+        int mode = M_IDLE, p = 0;
+        double b = 0.0;
+        if (j >= 0) {
+            double t[3];
+            wave_prologue_sums<3>(a, ver, j, t);
+            SysState st = a.st[ver][j];
+            const bool live = st.mode != M_IDLE && st.mode != M_DONE;
+            if (live)
+                advance(st, t);
+            // the state K2 of this step reads: advanced, or the same idle/done state
+            if (blockIdx.x == 0 && lane == 0)
+                a.st[ver ^ 1][j] = st;
+            mode = live ? uniform(st.mode) : (int)M_IDLE;
+            b = uniform(st.beta);
+            p = uniform(st.pcur);
+        }
+        js[q] = j;
+        cg[q] = mode == M_CG;
+        ru[q] = mode == M_RU;
+        beta[q] = (real)b;
+        pc[q] = p;
+        if (lane == 0)
+            modes[w * RR + q] = mode;
     }
-    if (lane == 0)
-        modes[w] = mode;
     __syncthreads();
     bool anycg = false, anyru = false;
 #pragma unroll
@@ -182,15 +208,23 @@ __global__ void __launch_bounds__(64 * R, kSharedMinWaves) k_cg_shared1(CgArgs a
     }
     if (!anycg && !anyru)
         return;
-    const bool cg = mode == M_CG, ru = mode == M_RU;
-    const real beta = (real)uniform(st.beta);
-    const int pc = uniform(st.pcur);
-    const int jj = j >= 0 ? j : 0;
-    const v2 *rv = (const v2 *)a.r + (size_t)jj * 3 * Vh;
-    const void *pold = spin_at<P>(a.p[pc], jj, Vh);
-    void *pnew = spin_at<P>(a.p[pc ^ 1], jj, Vh);
-    void *apv = spin_at<P>(a.ap, jj, Vh);
-    double nrm_ap = 0.0, nrm_p = 0.0;
+    bool wcg = false;
+#pragma unroll
+    for (int q = 0; q < RR; ++q)
+        wcg |= cg[q];
+    // every place gathers in bounds: an empty place reads system 0's vectors
+    const v2 *rv[RR];
+    const void *pold[RR];
+#pragma unroll
+    for (int q = 0; q < RR; ++q) {
+        const int jj = js[q] >= 0 ? js[q] : 0;
+        rv[q] = (const v2 *)a.r + (size_t)jj * 3 * Vh;
+        pold[q] = spin_at<P>(a.p[pc[q]], jj, Vh);
+    }
+    double nrm_ap[RR], nrm_p[RR];
+#pragma unroll
+    for (int q = 0; q < RR; ++q)
+        nrm_ap[q] = nrm_p[q] = 0.0;
     for (int it = 0;; ++it) {
         const int s0 = chunk_start(it, Vh, a.remap);
         if (s0 < 0)
@@ -204,60 +238,90 @@ __global__ void __launch_bounds__(64 * R, kSharedMinWaves) k_cg_shared1(CgArgs a
         const int s = s0 + lane;
         if (s >= Vh)
             continue;
-        if (cg) {
-            cplx<float> acc[3] = {czero<float>(), czero<float>(), czero<float>()};
-            // the partner site's p and r (same index, parity par), loaded before the gathers
-            cplx<real> po[3];
-            v2 ro[3];
-            P::load_spinor(pold, Vh, s, po);
+        if (wcg) {
+            cplx<float> acc[RR][3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                ro[c] = rv[(int64_t)c * Vh + s];
-            auto load = [&](int n, cplx<float> *chi) {
-                cplx<real> pv[3];
-                P::load_spinor(pold, Vh, n, pv);
+            for (int q = 0; q < RR; ++q)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const v2 t = rv[(int64_t)c * Vh + n];
-                    chi[c].re = fma(beta, pv[c].re, t.x);
-                    chi[c].im = fma(beta, pv[c].im, t.y);
+                for (int c = 0; c < 3; ++c)
+                    acc[q][c] = czero<float>();
+            // the partner site's p and r (same index, parity par): before the
+            // gathers for a single system, after them for several
+            cplx<real> po[RR][3];
+            v2 ro[RR][3];
+            auto own = [&]() {
+#pragma unroll
+                for (int q = 0; q < RR; ++q) {
+                    P::load_spinor(pold[q], Vh, s, po[q]);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        ro[q][c] = rv[q][(int64_t)c * Vh + s];
                 }
             };
-            hop_shared(a.g, a.nbr[pout], pout, s, lane, lk, acc, load);
-            cplx<real> pn[3];
+            if constexpr (RR == 1)
+                own();
+            auto load = [&](int q, int n, cplx<float> *chi) {
+                cplx<real> pv[3];
+                P::load_spinor(pold[q], Vh, n, pv);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                pn[c].re = fma(beta, po[c].re, ro[c].x);
-                pn[c].im = fma(beta, po[c].im, ro[c].y);
-            }
-            P::store_spinor(apv, Vh, s, acc);
-            if constexpr (P::id == 2)
-                P::store_spinor_read_back(pnew, Vh, s, pn);  // pn: the value D will read
-            else
-                P::store_spinor(pnew, Vh, s, pn);
+                for (int c = 0; c < 3; ++c) {
+                    const v2 t = rv[q][(int64_t)c * Vh + n];
+                    chi[c].re = fma(beta[q], pv[c].re, t.x);
+                    chi[c].im = fma(beta[q], pv[c].im, t.y);
+                }
+            };
+            hop_shared<RR>(a.g, a.nbr[pout], pout, s, lane, lk, acc, load);
+            if constexpr (RR > 1)
+                own();
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                nrm_p += (double)pn[c].re * pn[c].re + (double)pn[c].im * pn[c].im;
-                nrm_ap += (double)acc[c].re * acc[c].re + (double)acc[c].im * acc[c].im;
+            for (int q = 0; q < RR; ++q) {
+                if (!cg[q])
+                    continue;
+                const int j = js[q];
+                cplx<real> pn[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    pn[c].re = fma(beta[q], po[q][c].re, ro[q][c].x);
+                    pn[c].im = fma(beta[q], po[q][c].im, ro[q][c].y);
+                }
+                P::store_spinor(spin_at<P>(a.ap, j, Vh), Vh, s, acc[q]);
+                void *pnew = spin_at<P>(a.p[pc[q] ^ 1], j, Vh);
+                if constexpr (P::id == 2)
+                    P::store_spinor_read_back(pnew, Vh, s, pn);  // pn: the value D will read
+                else
+                    P::store_spinor(pnew, Vh, s, pn);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    nrm_p[q] += (double)pn[c].re * pn[c].re + (double)pn[c].im * pn[c].im;
+                    nrm_ap[q] += (double)acc[q][c].re * acc[q][c].re + (double)acc[q][c].im * acc[q][c].im;
+                }
             }
-        } else if (ru) {
-            recompute_k1<1, ROWS, 1>(a, j, pout, s, 0);
         }
+#pragma unroll
+        for (int q = 0; q < RR; ++q)
+            if (ru[q])
+                recompute_k1<1, ROWS, 1>(a, js[q], pout, s, 0);
     }
-    if (!anycg || j < 0)
+    if (!anycg)
         return;
-    const double tap = wave_sum(nrm_ap), tpp2 = wave_sum(nrm_p);
-    if (lane == 0) {
-        partial_slot(a, ver ^ 1, j, 0)[blockIdx.x] = tap;
-        partial_slot(a, ver ^ 1, j, 1)[blockIdx.x] = tpp2;
+#pragma unroll
+    for (int q = 0; q < RR; ++q) {
+        if (js[q] < 0)
+            continue;
+        const double tap = wave_sum(nrm_ap[q]), tpp2 = wave_sum(nrm_p[q]);
+        if (lane == 0) {
+            partial_slot(a, ver ^ 1, js[q], 0)[blockIdx.x] = tap;
+            partial_slot(a, ver ^ 1, js[q], 1)[blockIdx.x] = tpp2;
+        }
     }
 }
 
 // ---- K2 -----------------------------------------------------------------------------
 
-template <class P, int R, int ROWS>
-__global__ void __launch_bounds__(64 * R, kSharedMinWaves) k_cg_shared2(CgArgs a, int ver)
+template <class P, int W, int RR, int ROWS>
+__global__ void __launch_bounds__(64 * W, kSharedMinWaves) k_cg_shared2(CgArgs a, int ver)
 {
+    constexpr int R = W * RR;
     static_assert(P::id != 0 && R <= kSharedMaxR, "shared-link tiles: FP32 / FP16 working precision");
     using real = typename P::real;
     using v2 = typename vec2_of<real>::type;
@@ -267,35 +331,51 @@ __global__ void __launch_bounds__(64 * R, kSharedMinWaves) k_cg_shared2(CgArgs a
     const int par = blockIdx.y / tpp, k0 = par * a.S + (blockIdx.y % tpp) * R;
     const int Vh = a.g.Vh;
     const int cur = ver ^ 1;  // the state K1 of this step wrote
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int j = a.perm[k0 + w];
+    // the wavefront index is the same in every lane: kept in a scalar register,
+    // so that its systems, their states and pointers stay scalar too
+    const int w = uniform((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     // alpha from K1's partial sums (slots 0 and 1)
-    int mode = M_IDLE;
-    double alpha = 0.0, m2 = 0.0;
-    int pn_buf = 0;
-    if (j >= 0) {
-        const SysState &st = a.st[cur][j];
-        const int smode = st.mode;
-        const double mass2 = st.mass2, rr = st.rr;
-        const int pcur = st.pcur;
-        double t[2];
-        wave_prologue_sums<2>(a, cur, j, t);
-        if (smode == M_CG) {
-            const double pap = mass2 * t[1] + t[0];
-            if (finite_pos(pap)) {  // otherwise K1 of the next step reports the breakdown
-                mode = M_CG;
-                alpha = rr / pap;
+    int js[RR], pn_buf[RR];
+    bool cg[RR], ru[RR];
+    real al[RR], m2r[RR];
+    double m2[RR];
+#pragma unroll
+    for (int q = 0; q < RR; ++q) {
+        const int j = a.perm[k0 + w * RR + q];
+        int mode = M_IDLE, pb = 0;
+        double alpha = 0.0, mass2 = 0.0;
+        if (j >= 0) {
+            const SysState &st = a.st[cur][j];
+            const int smode = st.mode;
+            const double rr = st.rr;
+            const int pcur = st.pcur;
+            mass2 = st.mass2;
+            double t[2];
+            wave_prologue_sums<2>(a, cur, j, t);
+            if (smode == M_CG) {
+                const double pap = mass2 * t[1] + t[0];
+                if (finite_pos(pap)) {  // otherwise K1 of the next step reports the breakdown
+                    mode = M_CG;
+                    alpha = rr / pap;
+                }
+            } else if (smode == M_RU) {
+                mode = M_RU;
             }
-        } else if (smode == M_RU) {
-            mode = M_RU;
+            mode = uniform(mode);
+            alpha = uniform(alpha);
+            mass2 = uniform(mass2);
+            pb = uniform(pcur) ^ 1;  // p' written by K1 of this step
         }
-        mode = uniform(mode);
-        alpha = uniform(alpha);
-        m2 = uniform(mass2);
-        pn_buf = uniform(pcur) ^ 1;  // p' written by K1 of this step
+        js[q] = j;
+        cg[q] = mode == M_CG;
+        ru[q] = mode == M_RU;
+        al[q] = (real)alpha;
+        m2[q] = mass2;
+        m2r[q] = (real)mass2;
+        pn_buf[q] = pb;
+        if (lane == 0)
+            modes[w * RR + q] = mode;
     }
-    if (lane == 0)
-        modes[w] = mode;
     __syncthreads();
     bool anycg = false, anyru = false;
 #pragma unroll
@@ -305,14 +385,18 @@ __global__ void __launch_bounds__(64 * R, kSharedMinWaves) k_cg_shared2(CgArgs a
     }
     if (!anycg && !anyru)
         return;
-    const bool cg = mode == M_CG, ru = mode == M_RU;
-    const real al = (real)alpha, m2r = (real)m2;
-    const int jj = j >= 0 ? j : 0;
-    const void *apv = spin_at<P>(a.ap, jj, Vh);
-    const void *pb = spin_at<P>(a.p[pn_buf], jj, Vh);
-    v2 *rv = (v2 *)a.r + (size_t)jj * 3 * Vh;
-    flt2 *xl = a.xlo + (size_t)jj * 3 * Vh;
-    double nrm = 0.0;
+    bool wcg = false;
+#pragma unroll
+    for (int q = 0; q < RR; ++q)
+        wcg |= cg[q];
+    const void *apv[RR];
+#pragma unroll
+    for (int q = 0; q < RR; ++q)
+        apv[q] = spin_at<P>(a.ap, js[q] >= 0 ? js[q] : 0, Vh);
+    double nrm[RR];
+#pragma unroll
+    for (int q = 0; q < RR; ++q)
+        nrm[q] = 0.0;
     for (int it = 0;; ++it) {
         const int s0 = chunk_start(it, Vh, a.remap);
         if (s0 < 0)
@@ -326,41 +410,72 @@ __global__ void __launch_bounds__(64 * R, kSharedMinWaves) k_cg_shared2(CgArgs a
         const int s = s0 + lane;
         if (s >= Vh)
             continue;
-        if (cg) {
-            // this site's p', x and r, loaded before the gathers
-            cplx<real> pv[3];
-            flt2 xv[3];
-            v2 ro[3];
-            P::load_spinor(pb, Vh, s, pv);
+        if (wcg) {
+            // this site's p', x and r: before the gathers for a single system,
+            // after them for several
+            cplx<real> pv[RR][3];
+            flt2 xv[RR][3];
+            v2 ro[RR][3];
+            auto own = [&]() {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                xv[c] = xl[(int64_t)c * Vh + s];
-                ro[c] = rv[(int64_t)c * Vh + s];
-            }
-            cplx<float> acc[3] = {czero<float>(), czero<float>(), czero<float>()};
-            auto load = [&](int n, cplx<float> *chi) { P::load_spinor(apv, Vh, n, chi); };
-            hop_shared(a.g, a.nbr[par], par, s, lane, lk, acc, load);
+                for (int q = 0; q < RR; ++q) {
+                    if (!cg[q])
+                        continue;
+                    const int j = js[q];
+                    P::load_spinor(spin_at<P>(a.p[pn_buf[q]], j, Vh), Vh, s, pv[q]);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const int64_t o = (int64_t)c * Vh + s;
-                xl[o] = flt2{fmaf(al, pv[c].re, xv[c].x), fmaf(al, pv[c].im, xv[c].y)};
-                const real apr = m2r * pv[c].re - acc[c].re;
-                const real api = m2r * pv[c].im - acc[c].im;
-                v2 rn = ro[c];
-                rn.x = fma(-al, apr, rn.x);
-                rn.y = fma(-al, api, rn.y);
-                rv[o] = rn;
-                nrm += (double)rn.x * rn.x + (double)rn.y * rn.y;
+                    for (int c = 0; c < 3; ++c) {
+                        xv[q][c] = a.xlo[(size_t)j * 3 * Vh + (int64_t)c * Vh + s];
+                        ro[q][c] = ((const v2 *)a.r)[(size_t)j * 3 * Vh + (int64_t)c * Vh + s];
+                    }
+                }
+            };
+            if constexpr (RR == 1)
+                own();
+            cplx<float> acc[RR][3];
+#pragma unroll
+            for (int q = 0; q < RR; ++q)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    acc[q][c] = czero<float>();
+            auto load = [&](int q, int n, cplx<float> *chi) { P::load_spinor(apv[q], Vh, n, chi); };
+            hop_shared<RR>(a.g, a.nbr[par], par, s, lane, lk, acc, load);
+            if constexpr (RR > 1)
+                own();
+#pragma unroll
+            for (int q = 0; q < RR; ++q) {
+                if (!cg[q])
+                    continue;
+                const int j = js[q];
+                v2 *rv = (v2 *)a.r + (size_t)j * 3 * Vh;
+                flt2 *xl = a.xlo + (size_t)j * 3 * Vh;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int64_t o = (int64_t)c * Vh + s;
+                    xl[o] = flt2{fmaf(al[q], pv[q][c].re, xv[q][c].x), fmaf(al[q], pv[q][c].im, xv[q][c].y)};
+                    const real apr = m2r[q] * pv[q][c].re - acc[q][c].re;
+                    const real api = m2r[q] * pv[q][c].im - acc[q][c].im;
+                    v2 rn = ro[q][c];
+                    rn.x = fma(-al[q], apr, rn.x);
+                    rn.y = fma(-al[q], api, rn.y);
+                    rv[o] = rn;
+                    nrm[q] += (double)rn.x * rn.x + (double)rn.y * rn.y;
+                }
             }
-        } else if (ru) {
-            recompute_k2<P, 1, ROWS, 1>(a, j, par, s, 0, m2, nrm);
         }
+#pragma unroll
+        for (int q = 0; q < RR; ++q)
+            if (ru[q])
+                recompute_k2<P, 1, ROWS, 1>(a, js[q], par, s, 0, m2[q], nrm[q]);
     }
-    if (j < 0)
-        return;
-    const double tot = wave_sum(nrm);
-    if (lane == 0)
-        partial_slot(a, cur, j, 2)[blockIdx.x] = tot;
+#pragma unroll
+    for (int q = 0; q < RR; ++q) {
+        if (js[q] < 0)
+            continue;
+        const double tot = wave_sum(nrm[q]);
+        if (lane == 0)
+            partial_slot(a, cur, js[q], 2)[blockIdx.x] = tot;
+    }
 }
 
 }  // namespace stag

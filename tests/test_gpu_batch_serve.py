@@ -48,7 +48,8 @@ def test_batch_matches_single_solves(gpu_ctx, monkeypatch, prec, reduce):
         assert n % shape["rhs_tile"] == 0 and shape["lanes_per_site"] in (1, 2, 4, 8)
         assert shape["reduction_kernel"] in (0, 1) and shape["shared_links"] in (0, 1)
         if shape["shared_links"]:
-            assert prec != binding.FP64 and shape["lanes_per_site"] == 1 and shape["block"] == 64 * shape["rhs_tile"]
+            W = shape["block"] // 64
+            assert prec != binding.FP64 and shape["lanes_per_site"] == 1 and shape["rhs_tile"] % W == 0
         else:
             assert shape["block"] in (64, 128, 256)
         if reduce is not None:
@@ -82,18 +83,19 @@ def test_batch_matches_single_solves(gpu_ctx, monkeypatch, prec, reduce):
         gpu_ctx.free_gauge(f)
 
 
-@pytest.mark.parametrize("prec,dims,n,R,tables,reduce", [
-    (binding.FP32_RU, (8, 8, 8, 8), 12, 12, 0, None),
-    (binding.FP16_RU, (8, 8, 8, 8), 12, 4, 0, None),
-    (binding.FP32_RU, (6, 6, 6, 6), 6, 3, 1, "0"),     # 648 sites per parity: a ragged last chunk
-    (binding.FP16_RU, (6, 6, 6, 6), 6, 6, 0, "1"),
-    (binding.FP32_RU, (4, 6, 4, 6), 4, 2, 0, "0"),     # 144 sites per parity
+@pytest.mark.parametrize("prec,dims,n,R,W,tables,reduce", [
+    (binding.FP32_RU, (8, 8, 8, 8), 12, 12, 12, 0, None),
+    (binding.FP16_RU, (8, 8, 8, 8), 12, 4, 4, 0, None),
+    (binding.FP16_RU, (8, 8, 8, 8), 12, 12, 4, 0, None),   # three systems per wavefront
+    (binding.FP32_RU, (6, 6, 6, 6), 6, 3, 3, 1, "0"),      # 648 sites per parity: a ragged last chunk
+    (binding.FP16_RU, (6, 6, 6, 6), 6, 6, 3, 0, "1"),      # two systems per wavefront
+    (binding.FP32_RU, (4, 6, 4, 6), 4, 2, 2, 0, "0"),      # 144 sites per parity
 ])
-def test_batch_shared_link_tiles(gpu_ctx, monkeypatch, prec, dims, n, R, tables, reduce):
-    # the shared-link tiles forced (one wavefront per system, the block's links
-    # staged in LDS): every system meets the true residual and agrees with its
-    # solve alone (register tiles) within the error the residuals allow
-    monkeypatch.setenv("STAG_KERNEL_CFG", "1,%d,%d,%d,1,1" % (64 * R, R, tables))
+def test_batch_shared_link_tiles(gpu_ctx, monkeypatch, prec, dims, n, R, W, tables, reduce):
+    # the shared-link tiles forced (W wavefronts of R / W systems, the block's
+    # links staged in LDS): every system meets the true residual and agrees
+    # with its solve alone (register tiles) within the error the residuals allow
+    monkeypatch.setenv("STAG_KERNEL_CFG", "1,%d,%d,%d,1,1" % (64 * W, R, tables))
     if reduce is not None:
         monkeypatch.setenv("STAG_CG_REDUCE", reduce)
     tol = 1e-10
@@ -108,7 +110,7 @@ def test_batch_shared_link_tiles(gpu_ctx, monkeypatch, prec, dims, n, R, tables,
         infos = gpu_ctx.cg_solve_batch(f, bs, xs, plist)
         torch.cuda.synchronize()
         shape = gpu_ctx.cg_tune_info(f, precision=prec, nrhs=n)
-        assert shape["shared_links"] == 1 and shape["rhs_tile"] == R and shape["block"] == 64 * R
+        assert shape["shared_links"] == 1 and shape["rhs_tile"] == R and shape["block"] == 64 * W
         monkeypatch.delenv("STAG_KERNEL_CFG")
         for i in range(n):
             assert infos[i]["status"] == 0
@@ -121,7 +123,7 @@ def test_batch_shared_link_tiles(gpu_ctx, monkeypatch, prec, dims, n, R, tables,
             tra = oracle.true_residual(dims, U, masses[i], srcs[i], xa)
             _, _, kappa = oracle.kappa_estimate(dims, U, masses[i], srcs[i], parity=0)
             assert rel(x, xa) <= kappa * (tr + tra), (i, rel(x, xa), kappa, tr, tra)
-        print("shared tiles %s R=%d: iterations %s" % (dims, R, [i["iters"] for i in infos]))
+        print("shared tiles %s R=%d W=%d: iterations %s" % (dims, R, W, [i["iters"] for i in infos]))
     finally:
         gpu_ctx.free_gauge(f)
 
