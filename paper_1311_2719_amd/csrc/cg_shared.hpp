@@ -297,10 +297,17 @@ __global__ void __launch_bounds__(64 * W, kSharedMinWaves) k_cg_shared1(CgArgs a
                 }
             }
         }
+    }
+    // residual recomputations after the block's CG work: a wavefront that has
+    // one no longer holds the others at the chunk barriers
+    for (int it = 0; anyru; ++it) {
+        const int s0 = chunk_start(it, Vh, a.remap);
+        if (s0 < 0 || s0 + lane >= Vh)
+            break;
 #pragma unroll
         for (int q = 0; q < RR; ++q)
             if (ru[q])
-                recompute_k1<1, ROWS, 1>(a, js[q], pout, s, 0);
+                recompute_k1<1, ROWS, 1>(a, js[q], pout, s0 + lane, 0);
     }
     if (!anycg)
         return;
@@ -463,10 +470,16 @@ __global__ void __launch_bounds__(64 * W, kSharedMinWaves) k_cg_shared2(CgArgs a
                 }
             }
         }
+    }
+    // residual recomputations after the block's CG work (see K1)
+    for (int it = 0; anyru; ++it) {
+        const int s0 = chunk_start(it, Vh, a.remap);
+        if (s0 < 0 || s0 + lane >= Vh)
+            break;
 #pragma unroll
         for (int q = 0; q < RR; ++q)
             if (ru[q])
-                recompute_k2<P, 1, ROWS, 1>(a, js[q], par, s, 0, m2[q], nrm[q]);
+                recompute_k2<P, 1, ROWS, 1>(a, js[q], par, s0 + lane, 0, m2[q], nrm[q]);
     }
 #pragma unroll
     for (int q = 0; q < RR; ++q) {
