@@ -298,16 +298,23 @@ __global__ void __launch_bounds__(64 * W, kSharedMinWaves) k_cg_shared1(CgArgs a
             }
         }
     }
-    // residual recomputations after the block's CG work: a wavefront that has
-    // one no longer holds the others at the chunk barriers
-    for (int it = 0; anyru; ++it) {
-        const int s0 = chunk_start(it, Vh, a.remap);
-        if (s0 < 0 || s0 + lane >= Vh)
-            break;
-#pragma unroll
-        for (int q = 0; q < RR; ++q)
-            if (ru[q])
-                recompute_k1<1, ROWS, 1>(a, js[q], pout, s0 + lane, 0);
+    // residual recomputations (FP64, rare) after the CG work, by the whole
+    // block: eight lanes per site, one direction each
+    for (int r = 0; anyru && r < R; ++r) {
+        if (modes[r] != M_RU)
+            continue;
+        const int j = a.perm[k0 + r];
+        for (int it = 0;; ++it) {
+            const int s0 = chunk_start(it, Vh, a.remap);
+            if (s0 < 0)
+                break;
+            for (int t = threadIdx.x; t < kChunk * 8; t += blockDim.x) {  // whole wavefronts
+                int sl, sub;
+                site_of_thread<8>(t, sl, sub);
+                if (s0 + sl < Vh)
+                    recompute_k1<8, ROWS, 1>(a, j, pout, s0 + sl, sub);
+            }
+        }
     }
     if (!anycg)
         return;
@@ -334,6 +341,7 @@ __global__ void __launch_bounds__(64 * W, kSharedMinWaves) k_cg_shared2(CgArgs a
     using v2 = typename vec2_of<real>::type;
     __shared__ flt2 lk[9 * 8 * kLdsRow];
     __shared__ int modes[R];
+    __shared__ double red[W];
     const int tpp = a.S / R;
     const int par = blockIdx.y / tpp, k0 = par * a.S + (blockIdx.y % tpp) * R;
     const int Vh = a.g.Vh;
@@ -471,19 +479,33 @@ __global__ void __launch_bounds__(64 * W, kSharedMinWaves) k_cg_shared2(CgArgs a
             }
         }
     }
-    // residual recomputations after the block's CG work (see K1)
-    for (int it = 0; anyru; ++it) {
-        const int s0 = chunk_start(it, Vh, a.remap);
-        if (s0 < 0 || s0 + lane >= Vh)
-            break;
-#pragma unroll
-        for (int q = 0; q < RR; ++q)
-            if (ru[q])
-                recompute_k2<P, 1, ROWS, 1>(a, js[q], par, s0 + lane, 0, m2[q], nrm[q]);
+    // residual recomputations (FP64, rare) after the CG work, by the whole
+    // block (see K1); each one's partial sum is the block's total
+    for (int r = 0; anyru && r < R; ++r) {
+        if (modes[r] != M_RU)
+            continue;
+        const int j = a.perm[k0 + r];
+        const double m2d = a.st[cur][j].mass2;
+        double nr[1] = {0.0};
+        for (int it = 0;; ++it) {
+            const int s0 = chunk_start(it, Vh, a.remap);
+            if (s0 < 0)
+                break;
+            for (int t = threadIdx.x; t < kChunk * 8; t += blockDim.x) {  // whole wavefronts
+                int sl, sub;
+                site_of_thread<8>(t, sl, sub);
+                if (s0 + sl < Vh)
+                    recompute_k2<P, 8, ROWS, 1>(a, j, par, s0 + sl, sub, m2d, nr[0]);
+            }
+        }
+        double tot;
+        block_sum_multi<1>(nr, red, tot);
+        if (threadIdx.x == 0)
+            partial_slot(a, cur, j, 2)[blockIdx.x] = tot;
     }
 #pragma unroll
     for (int q = 0; q < RR; ++q) {
-        if (js[q] < 0)
+        if (js[q] < 0 || ru[q])
             continue;
         const double tot = wave_sum(nrm[q]);
         if (lane == 0)
