@@ -620,9 +620,24 @@ def run_md(args):
                             "frac": fbytes * V / tf / 1e9 / HBM_PEAK_GBS,
                             "note": "working set about 0.2 GB at 16^4, partly Infinity-Cache resident"}
     res["gauge_force"] = {"mean_us": tg * 1e6, "links": 4 * V}
+    ctx.free_gauge(f)
+    # the fermion force on the 32^4 workload's field (off the Infinity Cache:
+    # links 0.6 GB, momenta 0.6 GB); W a Gaussian field, the kernel's work
+    # does not depend on the values
+    dims3 = (32, 32, 32, 32)
+    V3 = int(np.prod(dims3))
+    stage("md: fermion force 32^4")
+    f3 = ctx.set_gauge(dims3, inputs.smooth_su3(dims3, 0.5, 103))
+    w3 = ctx.pack(f3, inputs.gaussian_source(dims3, 203))
+    Q3 = torch.zeros((V3, 4, 3, 3), dtype=torch.complex128, device="cuda")
+    tf3 = timed(lambda: ctx.fermion_force(f3, w3, force=Q3, coeff=1e-9, accumulate=True), reps=20)
+    fbytes3 = 4 * 3 * ctx.link_rows(f3) * 16 + 48 + 48 + 2 * 4 * 144
+    res["fermion_force_32"] = {"mean_us": tf3 * 1e6, "bytes_per_site": fbytes3, "gbs": fbytes3 * V3 / tf3 / 1e9,
+                               "frac": fbytes3 * V3 / tf3 / 1e9 / HBM_PEAK_GBS}
     ctx.close()
     _emit({"suite": "md", "workload": "16^4 eps 0.3 links seed 102, momenta seed 702, chi seed 703, beta 5.6, "
-                                      "m 0.05, leapfrog 10 x 0.02, CG 1e-10", "results": res})
+                                      "m 0.05, leapfrog 10 x 0.02, CG 1e-10; force kernel also at 32^4 "
+                                      "(eps 0.5 links seed 103)", "results": res})
 
 
 def run_kernels32(args):
