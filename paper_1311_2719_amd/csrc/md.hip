@@ -75,31 +75,39 @@ __device__ __forceinline__ void add_to(Mat &A, const Mat &B)
     }
 }
 
+// Lexicographic sites s = x + Lx (y + Ly (z + Lz t)); every lattice the
+// library holds has fewer than 2^31 sites, so coordinates and indices are
+// 32-bit (64-bit division is many times the cost on the GPU).
 struct Lex {
     int32_t L[4];
-    __device__ __forceinline__ int64_t shift(int64_t s, int mu, int step) const
+    __device__ __forceinline__ void coords(int s, int (&c)[4]) const
     {
-        // coordinates, one move along mu (periodic), back to the index
-        int c[4];
-        int64_t r = s;
 #pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            c[d] = (int)(r % L[d]);
-            r /= L[d];
+        for (int d = 0; d < 3; ++d) {
+            c[d] = s % L[d];
+            s /= L[d];
         }
-        int v = 0, n = 0;
+        c[3] = s;
+    }
+    __device__ __forceinline__ int stride(int d) const
+    {
+        int st = 1;
 #pragma unroll
-        for (int d = 0; d < 4; ++d)
-            if (d == mu) {
-                v = c[d] + step;
-                n = L[d];
-            }
-        v = v < 0 ? v + n : (v >= n ? v - n : v);
-#pragma unroll
-        for (int d = 0; d < 4; ++d)
-            if (d == mu)
-                c[d] = v;
-        return c[0] + (int64_t)L[0] * (c[1] + (int64_t)L[1] * (c[2] + (int64_t)L[2] * c[3]));
+        for (int k = 0; k < 3; ++k)
+            st *= k < d ? L[k] : 1;
+        return st;
+    }
+    // site s (coordinates c) moved by `step` (+-1) along d, periodically
+    __device__ __forceinline__ int step(int s, const int (&c)[4], int d, int step) const
+    {
+        const int st = stride(d), n = L[d], v = c[d] + step;
+        return s + step * st + (v < 0 ? n * st : (v >= n ? -n * st : 0));
+    }
+    __device__ __forceinline__ int shift(int s, int mu, int step) const
+    {
+        int c[4];
+        coords(s, c);
+        return this->step(s, c, mu, step);
     }
 };
 
@@ -110,10 +118,12 @@ k_gauge_force(Lex g, int64_t V, const dbl2 *__restrict__ U, dbl2 *__restrict__ f
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= V * 4)
         return;
-    const int64_t x = gid >> 2;
+    const int x = (int)(gid >> 2);
     const int mu = (int)(gid & 3);
-    const int64_t xpm = g.shift(x, mu, 1);
-    auto link = [&](int64_t s, int nu) { return load_mat(U + (s * 4 + nu) * 9); };
+    int c[4];
+    g.coords(x, c);
+    const int xpm = g.step(x, c, mu, 1);
+    auto link = [&](int s, int nu) { return load_mat(U + ((int64_t)s * 4 + nu) * 9); };
     Mat S;
 #pragma unroll
     for (int k = 0; k < 9; ++k)
@@ -122,7 +132,8 @@ k_gauge_force(Lex g, int64_t V, const dbl2 *__restrict__ U, dbl2 *__restrict__ f
     for (int nu = 0; nu < 4; ++nu) {
         if (nu == mu)
             continue;
-        const int64_t xpn = g.shift(x, nu, 1), xmn = g.shift(x, nu, -1), xpm_mn = g.shift(xpm, nu, -1);
+        // x + mu - nu: the nu coordinate of x + mu is that of x
+        const int xpn = g.step(x, c, nu, 1), xmn = g.step(x, c, nu, -1), xpm_mn = g.step(xpm, c, nu, -1);
         // U_nu(x+mu) U_mu(x+nu)^dagger U_nu(x)^dagger
         add_to(S, mul<false, true>(mul<false, true>(link(xpm, nu), link(xpn, mu)), link(x, nu)));
         // U_nu(x+mu-nu)^dagger U_mu(x-nu)^dagger U_nu(x-nu)
@@ -272,8 +283,8 @@ k_energy_partials(int which, Lex g, int64_t n, const dbl2 *__restrict__ A, const
             for (int k = 0; k < 9; ++k)
                 v += q[k].x * q[k].x + q[k].y * q[k].y;
         } else if (which == 1) {
-            const int64_t x = i;
-            auto link = [&](int64_t s, int nu) { return load_mat(A + (s * 4 + nu) * 9); };
+            const int x = (int)i;
+            auto link = [&](int s, int nu) { return load_mat(A + ((int64_t)s * 4 + nu) * 9); };
             for (int mu = 0; mu < 4; ++mu)
                 for (int nu = mu + 1; nu < 4; ++nu) {
                     const Mat P = mul<false, true>(
