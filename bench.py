@@ -491,7 +491,7 @@ def run_default(args):
                    "lattice": list(c3_dims), "mass": c3_m, "tol": tol, "precision": "fp64", "parity": "all"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(V3),
-                     "kernel": "k_dslash<PrecF64> (full lattice, FP64, 32^4 on the same field)",
+                     "kernel": "k_dslash<PrecF64NT> (full lattice, FP64 with non-temporal link loads, 32^4 on the same field)",
                      "algorithmic_bytes_per_launch": algo_bytes, "bytes_per_site": dslash_bytes_per_site(rows3),
                      "link_rows": rows3, "mean_us": mean * 1e6, "p50_us": float(np.percentile(durs, 50) * 1e6),
                      "p99_us": float(np.percentile(durs, 99) * 1e6), "config": tune,

@@ -328,7 +328,7 @@ double Batch::time_cg_config(const KernelCfg &c, int nblk, bool reduce)
 {
     if (nblk < 1 || nblk > pstride_)  // partial sums are indexed by block: never past a slot
         return 1e30;
-    const CgLaunchTable &t = cg_table(prec_, f_->rows);
+    const CgLaunchTable &t = cg_table(prec_, f_->rows, f_->nt_links);
     CgArgs a = args();
     for (int par = 0; par < 2; ++par)
         a.nbr[par] = c.tables ? f_->nbr_for(par) : nullptr;
@@ -379,7 +379,7 @@ KernelCfg Batch::default_cg_cfg() const
     best.rtile = 1;
     best.tables = 0;
     best.remap = 1;
-    const CgLaunchTable &t = cg_table(prec_, f_->rows);
+    const CgLaunchTable &t = cg_table(prec_, f_->rows, f_->nt_links);
     for (int i = 0; i < t.n_rtiles; ++i)
         if (S_ % t.rtiles[i] == 0)
             best.rtile = std::max(best.rtile, t.rtiles[i]);
@@ -405,7 +405,7 @@ static KernelCfg shared_shape(int code, int reduce)
 KernelCfg Batch::tune_cg()
 {
     KernelCfg best = default_cg_cfg();
-    const CgLaunchTable &t = cg_table(prec_, f_->rows);
+    const CgLaunchTable &t = cg_table(prec_, f_->rows, f_->nt_links);
     const char *env = getenv("STAG_KERNEL_CFG");
     if (env && *env) {
         KernelCfg c;
@@ -636,7 +636,7 @@ int Batch::upload_and_init(const std::vector<int> &systems)
     if (rc != STAG_OK)
         return rc;
     const CgArgs a = args();
-    const CgLaunchTable &t = cg_table(prec_, f_->rows);
+    const CgLaunchTable &t = cg_table(prec_, f_->rows, f_->nt_links);
     dim3 grid((unsigned)nblk_, (unsigned)nsys());
     // one thread per site (the init kernel takes any block of up to 256 threads)
     hipError_t e = cfg_.shared ? t.init(grid, dim3(256), s_, a, 1) : t.init(grid, dim3(cfg_.block), s_, a, cfg_.lps);
@@ -680,7 +680,7 @@ CgArgs Batch::args() const
 
 int Batch::launch_step(int ver, hipStream_t st, const KernelCfg &c)
 {
-    const CgLaunchTable &t = cg_table(prec_, f_->rows);
+    const CgLaunchTable &t = cg_table(prec_, f_->rows, f_->nt_links);
     const CgArgs a = args();
     const int R = c.rtile;
     dim3 grid((unsigned)nblk_, (unsigned)(nsys() / R)), blk(c.block);

@@ -152,6 +152,7 @@ int stag_set_gauge(stag_ctx *ctx, const int32_t dims[4], const double *links, in
         return rc;
     const char *rows_env = getenv("STAG_LINK_ROWS");
     f->rows = two_rows && !(rows_env && atoi(rows_env) == 3) ? 2 : 3;
+    f->nt_links = nt_links_for(*f);
     for (int p = 0; p < 3; ++p) {
         const size_t lb = (size_t)2 * link_parity_entries(f->rows, (int)Vh) * link_entry_bytes_of(p);
         f->links[p] = c->arena.alloc(lb);

@@ -1,7 +1,7 @@
 // Launch tables for the CG / hop kernels of one working precision and link
 // format.  Each (precision, link rows) pair is instantiated in its own
 // translation unit (cg_f64.hip, cg_f64_r2.hip, ...) and reached through
-// cg_table(prec, rows).
+// cg_table(prec, rows, nt_links).
 #pragma once
 
 #include "cg_shared.hpp"
@@ -28,7 +28,7 @@ struct CgLaunchTable {
     int n_stiles;
 };
 
-const CgLaunchTable &cg_table(int prec, int rows);
+const CgLaunchTable &cg_table(int prec, int rows, int nt_links);
 
 // One kernel of the table for every lanes-per-site value.
 #define STAG_LPS_SWITCH(KERNEL, P, R, ROWS, ...)                                                    \

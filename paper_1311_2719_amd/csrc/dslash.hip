@@ -19,9 +19,13 @@ const CgLaunchTable &cg_table_f16();
 const CgLaunchTable &cg_table_f64_r2();
 const CgLaunchTable &cg_table_f32_r2();
 const CgLaunchTable &cg_table_f16_r2();
+const CgLaunchTable &cg_table_f64nt();
+const CgLaunchTable &cg_table_f64nt_r2();
 
-const CgLaunchTable &cg_table(int prec, int rows)
+const CgLaunchTable &cg_table(int prec, int rows, int nt_links)
 {
+    if (prec == 0 && nt_links)
+        return rows == 2 ? cg_table_f64nt_r2() : cg_table_f64nt();
     if (rows == 2)
         return prec == 0 ? cg_table_f64_r2() : prec == 1 ? cg_table_f32_r2() : cg_table_f16_r2();
     return prec == 0 ? cg_table_f64() : prec == 1 ? cg_table_f32() : cg_table_f16();
@@ -152,7 +156,10 @@ int dslash_with(const KernelCfg &cfg, GaugeField *f, int prec, int out_parity, i
     const int cnt = out_parity == STAG_ALL ? Vh : (int)count;
     hipError_t e;
     switch (prec) {
-    case 0: e = launch_dslash_p<PrecF64>(cfg, f, par_fixed, nparity, off, cnt, in, out, accumulate, s); break;
+    case 0:
+        e = f->nt_links ? launch_dslash_p<PrecF64NT>(cfg, f, par_fixed, nparity, off, cnt, in, out, accumulate, s)
+                        : launch_dslash_p<PrecF64>(cfg, f, par_fixed, nparity, off, cnt, in, out, accumulate, s);
+        break;
     case 1: e = launch_dslash_p<PrecF32>(cfg, f, par_fixed, nparity, off, cnt, in, out, accumulate, s); break;
     case 2: e = launch_dslash_p<PrecF16>(cfg, f, par_fixed, nparity, off, cnt, in, out, accumulate, s); break;
     default: return set_error(STAG_EINVAL, "dslash: unknown precision %d", prec);
@@ -226,7 +233,7 @@ static KernelCfg default_config(const GaugeField *f, int prec, int nrhs)
     KernelCfg best;
     best.lps = prec == 0 ? 2 : 1;
     best.block = 256;
-    best.rtile = default_rtile(cg_table(prec, f->rows), nrhs);
+    best.rtile = default_rtile(cg_table(prec, f->rows, f->nt_links), nrhs);
     best.tables = 0;
     best.remap = 1;
     return best;
@@ -249,7 +256,7 @@ KernelCfg tune_config(Ctx *ctx, GaugeField *f, int prec, int nrhs, hipStream_t s
         if (it != f->tuned.end())
             return it->second;
     }
-    const CgLaunchTable &tab = cg_table(prec, f->rows);
+    const CgLaunchTable &tab = cg_table(prec, f->rows, f->nt_links);
     KernelCfg best = default_config(f, prec, nrhs);
     KernelCfg forced;
     const char *tune_env = getenv("STAG_TUNE");

@@ -31,7 +31,7 @@ namespace {
 
 constexpr int kForceSites = 64;  // lexicographic sites per block
 
-template <int ROWS>
+template <class P64, int ROWS>
 __global__ void __launch_bounds__(256)
 k_fermion_force(Geom g, const dbl2 *__restrict__ links, const dbl2 *__restrict__ w, dbl2 *__restrict__ force,
                 double coeff, int accumulate)
@@ -62,7 +62,7 @@ k_fermion_force(Geom g, const dbl2 *__restrict__ links, const dbl2 *__restrict__
         cplx<double> L[9];
 #pragma unroll
         for (int k = 0; k < 3 * ROWS; ++k)
-            L[k] = PrecF64::load_link(lk + link_offset(Vh, mu, k, s));
+            L[k] = P64::load_link(lk + link_offset(Vh, mu, k, s));
         if constexpr (ROWS == 2)
             third_row(L, folded_negative(g, c, mu) ? -2.0 : 2.0);
         // B = L (W(z+mu) W(z)^dagger): B_ab = (L wf)_a conj(wz_b)
@@ -115,12 +115,21 @@ int fermion_force(GaugeField *f, const double *w, double *force, double coeff, i
     const int64_t V = (int64_t)2 * g.Vh;
     const dim3 grid((unsigned)((V + kForceSites - 1) / kForceSites));
     const dim3 block(kForceSites * 4);
-    if (f->rows == 2)
-        hipLaunchKernelGGL((k_fermion_force<2>), grid, block, 0, s, g, (const dbl2 *)f->links[0], (const dbl2 *)w,
-                           (dbl2 *)force, coeff, accumulate);
-    else
-        hipLaunchKernelGGL((k_fermion_force<3>), grid, block, 0, s, g, (const dbl2 *)f->links[0], (const dbl2 *)w,
-                           (dbl2 *)force, coeff, accumulate);
+#define STAG_FORCE_CASE(P64, ROWS)                                                                                   \
+    hipLaunchKernelGGL((k_fermion_force<P64, ROWS>), grid, block, 0, s, g, (const dbl2 *)f->links[0],              \
+                       (const dbl2 *)w, (dbl2 *)force, coeff, accumulate)
+    if (f->nt_links) {
+        if (f->rows == 2)
+            STAG_FORCE_CASE(PrecF64NT, 2);
+        else
+            STAG_FORCE_CASE(PrecF64NT, 3);
+    } else {
+        if (f->rows == 2)
+            STAG_FORCE_CASE(PrecF64, 2);
+        else
+            STAG_FORCE_CASE(PrecF64, 3);
+    }
+#undef STAG_FORCE_CASE
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return set_error(STAG_EHIP, "fermion force launch failed: %s", hipGetErrorString(e));

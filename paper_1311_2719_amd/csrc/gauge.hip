@@ -13,6 +13,8 @@
 // of these matrices is 1/2 (with a sign) times a special unitary matrix, only
 // their first two rows are stored and the kernels rebuild the third
 // (two-row form, 2/3 of the link bytes).
+#include <cstdlib>
+
 #include "runtime.hpp"
 
 namespace stag {
@@ -140,6 +142,15 @@ k_pack(Geom g, dbl2 *__restrict__ lex, dbl2 *__restrict__ eo, int to_eo)
 }
 
 }  // namespace
+
+int nt_links_for(const GaugeField &f)
+{
+    if (const char *e = getenv("STAG_NT_LINKS"))
+        if (e[0] == '0' || e[0] == '1')
+            return e[0] == '1';
+    const size_t fp64_link_bytes = (size_t)2 * link_parity_entries(f.rows, f.g.Vh) * link_entry_bytes_of(0);
+    return fp64_link_bytes > ((size_t)256 << 20);
+}
 
 int gauge_check(Ctx *ctx, const Geom &g, const double *links_dev, hipStream_t s, bool &two_rows)
 {

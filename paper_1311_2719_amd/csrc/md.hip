@@ -410,6 +410,7 @@ int md_trajectory(Ctx *ctx, const int32_t dims[4], double *U, double *Q, const d
         return set_error(STAG_EINVAL, "stag_md_trajectory: the links are not special unitary");
     const char *rows_env = getenv("STAG_LINK_ROWS");
     f->rows = rows_env && atoi(rows_env) == 3 ? 3 : 2;
+    f->nt_links = nt_links_for(*f);
     const size_t vbytes = (size_t)2 * 3 * g0.Vh * 16;
     struct Owned {
         Ctx *c;

@@ -78,6 +78,7 @@ struct GaugeField {
     int32_t tap = 1;
     Geom g{};
     int32_t rows = 3;                                // link rows stored (2: third row rebuilt)
+    int32_t nt_links = 0;                            // 1: FP64 kernels read links non-temporally
     void *links[3] = {nullptr, nullptr, nullptr};  // per precision id: [2 parities][3 * rows][Vh / 8][8][8]
     int32_t *nbr = nullptr;                          // [2][8][Vh]
     std::atomic<int> users{0};                       // serving requests queued / running
@@ -142,6 +143,9 @@ constexpr double kTwoRowTolerance = 1e-14;
 // Check the lexicographic links on the device: ENONFINITE for NaN/Inf;
 // two_rows = whether every folded link admits the two-row form.
 int gauge_check(Ctx *ctx, const Geom &g, const double *links_dev, hipStream_t s, bool &two_rows);
+// Whether the FP64 kernels of field f read its links non-temporally: when its
+// FP64 links do not fit the Infinity Cache (STAG_NT_LINKS=0/1 forces it).
+int nt_links_for(const GaugeField &f);
 // Fill f->links (f->rows rows, every precision) and f->nbr from the links.
 int gauge_prepare(GaugeField *f, const double *links_dev, hipStream_t s);
 

@@ -178,13 +178,9 @@ struct PrecF64 {
     static constexpr int id = 0;
     // spinor storage: [3][Vh] dbl2
     using spin_store = dbl2;
-    // FP64 links are read once per kernel and never again while the kernel
-    // runs: non-temporal loads keep them from evicting the gathered vectors,
-    // which every site reads eight times, from L2 (32^4 D_slash: 170 -> 152
-    // us).  The FP32 and FP16 tiles measured slower with them.
     static __device__ __forceinline__ cplx<real> load_link(const link_t *p)
     {
-        const dbl2 v = __builtin_nontemporal_load(p);
+        const dbl2 v = *p;
         return {v.x, v.y};
     }
     static __device__ __forceinline__ void load_spinor(const void *base, int Vh, int s, cplx<real> out[3])
@@ -205,6 +201,22 @@ struct PrecF64 {
     }
     static constexpr size_t spinor_bytes = 48;  // per site
     static constexpr size_t link_bytes = 16;     // per complex entry
+};
+
+// FP64 with non-temporal link loads, for fields whose FP64 links do not fit
+// the 256 MB Infinity Cache.  A kernel reads each link once and never again
+// while it runs; non-temporal loads keep the links from evicting the
+// gathered vectors, which every site reads eight times (32^4 D_slash:
+// 170 -> 152 us, FP64 CG 4.14 -> 4.80 solves/s).  Where the links do fit,
+// the cache serves them across the CG's kernels and plain loads are faster
+// (16^4 CG: 238 against 213 solves/s; 24^4: 22.6 against 21.6).  The FP32
+// and FP16 tiles measured slower with them at every size.
+struct PrecF64NT : PrecF64 {
+    static __device__ __forceinline__ cplx<real> load_link(const link_t *p)
+    {
+        const dbl2 v = __builtin_nontemporal_load(p);
+        return {v.x, v.y};
+    }
 };
 
 struct PrecF32 {

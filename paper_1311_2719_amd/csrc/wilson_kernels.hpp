@@ -123,7 +123,7 @@ __device__ __forceinline__ void wilson_hop(const Geom &g, const dbl2 *__restrict
         const dbl2 *lp = links + link_offset(g.Vh, d, 0, s);
 #pragma unroll
         for (int k = 0; k < 3 * ROWS; ++k)
-            U[k] = PrecF64::load_link(lp + (int64_t)k * 8 * g.Vh);  // non-temporal: the spinors keep L2
+            U[k] = PrecF64::load_link(lp + (int64_t)k * 8 * g.Vh);
         if constexpr (ROWS == 2)
             third_row(U, wilson_link_negative(g, c, d) ? -1.0 : 1.0);
         cplx<double> h[2][3];

@@ -263,3 +263,32 @@ def test_links_from_device_and_arena_accounting(gpu_ctx):
     assert site_err(apply(gpu_ctx, f, chi), oracle.dslash(dims, U, chi)) <= TOL
     gpu_ctx.free_gauge(f)
     assert gpu_ctx.arena_usage()[0] == used0
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 6), (8, 8, 8, 8)])
+def test_nontemporal_link_loads_give_the_same_bits(gpu_ctx, monkeypatch, dims):
+    # fields beyond the Infinity Cache read their FP64 links with
+    # non-temporal loads (STAG_NT_LINKS forces either kind): the values, and
+    # so D, the CG iterates and the force, are the same to the bit
+    U = inputs.smooth_su3(dims, 0.5, 31)
+    chi = inputs.gaussian_source(dims, 32)
+    res = {}
+    for nt in ("0", "1"):
+        monkeypatch.setenv("STAG_NT_LINKS", nt)
+        f = gpu_ctx.set_gauge(dims, U)
+        try:
+            d = apply(gpu_ctx, f, chi)
+            b = gpu_ctx.pack(f, chi)
+            x = gpu_ctx.new_fermion(f)
+            y = gpu_ctx.new_fermion(f)
+            info = gpu_ctx.cg_solve(f, b, x, y=y, mass=0.1, tol=1e-10, parity=binding.EVEN)
+            w = x.clone()
+            w[1] = y[1]
+            force = gpu_ctx.fermion_force(f, w).cpu().numpy()
+            res[nt] = (d, gpu_ctx.unpack(f, x).cpu().numpy(), info["iters"], force)
+        finally:
+            gpu_ctx.free_gauge(f)
+    assert np.array_equal(res["0"][0], res["1"][0])
+    assert np.array_equal(res["0"][1], res["1"][1]) and res["0"][2] == res["1"][2]
+    assert np.array_equal(res["0"][3], res["1"][3])
+    assert site_err(res["1"][0], oracle.dslash(dims, U, chi)) <= TOL
