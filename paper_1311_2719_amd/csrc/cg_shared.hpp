@@ -47,7 +47,9 @@ __device__ __forceinline__ int chunk_link_index(int k, int d, int i) { return (k
 
 // Stage the links of output sites [s0, s0 + 64) (parity p_out) into lk.
 // Consecutive threads take consecutive stored entries (site tile, direction,
-// site), so every global load of a wavefront reads 512 contiguous bytes.
+// site), so every global load of a wavefront reads 512 contiguous bytes.  A
+// block reads its links once: non-temporal loads leave the L2 to the
+// gathered vectors (24^4, 12 systems per parity: 2% per step).
 template <class P, int ROWS>
 __device__ __forceinline__ void stage_chunk_links(const Geom &g, const typename P::link_t *__restrict__ links,
                                                   int p_out, int s0, flt2 *lk)
@@ -60,8 +62,10 @@ __device__ __forceinline__ void stage_chunk_links(const Geom &g, const typename 
         const int i = (it >> 6) * 8 + (it & 7);
         cplx<float> U[9];
 #pragma unroll
-        for (int k = 0; k < 3 * ROWS; ++k)
-            U[k] = P::load_link(base + (int64_t)k * 8 * Vh + it);
+        for (int k = 0; k < 3 * ROWS; ++k) {
+            const auto v = __builtin_nontemporal_load(base + (int64_t)k * 8 * Vh + it);
+            U[k] = {(float)v.x, (float)v.y};
+        }
         if constexpr (ROWS == 2) {
             const SiteCoord c = decode_site(g, p_out, s0 + i);
             third_row(U, folded_negative(g, c, d) ? -2.f : 2.f);
