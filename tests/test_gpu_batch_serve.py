@@ -90,6 +90,7 @@ def test_batch_matches_single_solves(gpu_ctx, monkeypatch, prec, reduce):
     (binding.FP32_RU, (6, 6, 6, 6), 6, 3, 3, 1, "0"),      # 648 sites per parity: a ragged last chunk
     (binding.FP16_RU, (6, 6, 6, 6), 6, 6, 3, 0, "1"),      # two systems per wavefront
     (binding.FP32_RU, (4, 6, 4, 6), 4, 2, 2, 0, "0"),      # 144 sites per parity
+    (binding.FP16_RU, (2, 2, 2, 4), 4, 4, 2, 0, None),     # 16 sites per parity: one partial chunk
 ])
 def test_batch_shared_link_tiles(gpu_ctx, monkeypatch, prec, dims, n, R, W, tables, reduce):
     # the shared-link tiles forced (W wavefronts of R / W systems, the block's
@@ -124,6 +125,36 @@ def test_batch_shared_link_tiles(gpu_ctx, monkeypatch, prec, dims, n, R, W, tabl
             _, _, kappa = oracle.kappa_estimate(dims, U, masses[i], srcs[i], parity=0)
             assert rel(x, xa) <= kappa * (tr + tra), (i, rel(x, xa), kappa, tr, tra)
         print("shared tiles %s R=%d W=%d: iterations %s" % (dims, R, W, [i["iters"] for i in infos]))
+    finally:
+        gpu_ctx.free_gauge(f)
+
+
+@pytest.mark.parametrize("prec,tap", [(binding.FP32_RU, True), (binding.FP16_RU, False)])
+def test_batch_shared_link_tiles_three_rows(gpu_ctx, monkeypatch, prec, tap):
+    # the shared-link staging of fields stored with all three link rows
+    # (STAG_LINK_ROWS=3: no row rebuilt), periodic and antiperiodic t
+    dims, n, tol = (6, 4, 4, 8), 6, 1e-10
+    U = inputs.smooth_su3(dims, 0.5, 181)
+    masses = inputs.masses_uniform(0.05, 0.2, n)
+    srcs = [inputs.gaussian_source(dims, 1810 + i) for i in range(n)]
+    monkeypatch.setenv("STAG_LINK_ROWS", "3")
+    f = gpu_ctx.set_gauge(dims, U, antiperiodic_t=tap)
+    monkeypatch.delenv("STAG_LINK_ROWS")
+    try:
+        assert gpu_ctx.link_rows(f) == 3
+        monkeypatch.setenv("STAG_KERNEL_CFG", "1,192,6,0,1,1")  # three wavefronts of two systems
+        bs = [gpu_ctx.pack(f, s) for s in srcs]
+        xs = [gpu_ctx.new_fermion(f) for _ in range(n)]
+        plist = [binding.params(float(mm), tol=tol, precision=prec) for mm in masses]
+        infos = gpu_ctx.cg_solve_batch(f, bs, xs, plist)
+        torch.cuda.synchronize()
+        shape = gpu_ctx.cg_tune_info(f, precision=prec, nrhs=n)
+        assert shape["shared_links"] == 1 and shape["block"] == 192
+        for i in range(n):
+            assert infos[i]["status"] == 0
+            x = gpu_ctx.unpack(f, xs[i]).cpu().numpy()
+            tr = oracle.true_residual(dims, U, masses[i], srcs[i], x, antiperiodic_t=tap)
+            assert tr <= tol, (i, tr)
     finally:
         gpu_ctx.free_gauge(f)
 
