@@ -960,7 +960,7 @@ SUITES = {"mixed32": run_mixed32, "batch24": run_batch24, "serve": run_serve, "c
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     if args.suite == "default":
