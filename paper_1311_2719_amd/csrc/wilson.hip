@@ -156,6 +156,7 @@ int wilson_prepare(Ctx *ctx, GaugeField *f, const double *links_dev, hipStream_t
     if (!f->links[0])
         return set_error(STAG_ENOMEM, "arena exhausted (%zu bytes of Wilson links)", lb);
     f->bytes = lb;
+    f->nt_links = nt_links_for(*f);
     if (f->rows == 2)
         hipLaunchKernelGGL((k_wprepare_links<2>), grid, block, 0, s, g, links_dev, (dbl2 *)f->links[0]);
     else
@@ -184,109 +185,124 @@ namespace {
 
 // The launches of the hop and of one solve, for one link format and one
 // number of lanes per site.
-template <int ROWS, int LPS> struct WLaunch {
+template <int ROWS, int LPS, class LP> struct WLaunch {
     static dim3 grid(int Vh, int ny = 1) { return dim3((unsigned)(((int64_t)Vh * LPS + kWBlock - 1) / kWBlock), ny); }
-    static void hop(const GaugeField *f, int pf, const double *in, double *out, hipStream_t s)
+    static void hop(const GaugeField *f, int pf, const double *in, double *out, int remap, hipStream_t s)
     {
-        hipLaunchKernelGGL((wil::k_wilson_dslash<ROWS, LPS>), grid(f->g.Vh, pf < 0 ? 2 : 1), dim3(kWBlock), 0, s, f->g,
-                           (const dbl2 *)f->links[0], (const dbl2 *)in, (dbl2 *)out, pf);
+        hipLaunchKernelGGL((wil::k_wilson_dslash<ROWS, LPS, LP>), grid(f->g.Vh, pf < 0 ? 2 : 1), dim3(kWBlock), 0, s, f->g,
+                           (const dbl2 *)f->links[0], (const dbl2 *)in, (dbl2 *)out, pf, remap);
     }
     static void init(const wil::WArgs &a, hipStream_t s)
     {
         const dim3 g = grid(a.g.Vh);
-        hipLaunchKernelGGL((wil::k_wil_bhat<ROWS, LPS>), g, dim3(kWBlock), 0, s, a);
-        hipLaunchKernelGGL((wil::k_wil_odd_g5<ROWS, LPS>), g, dim3(kWBlock), 0, s, a, (const dbl2 *)a.bh, 0, 0);
-        hipLaunchKernelGGL((wil::k_wil_init<ROWS, LPS>), g, dim3(kWBlock), 0, s, a);
+        hipLaunchKernelGGL((wil::k_wil_bhat<ROWS, LPS, LP>), g, dim3(kWBlock), 0, s, a);
+        hipLaunchKernelGGL((wil::k_wil_odd_g5<ROWS, LPS, LP>), g, dim3(kWBlock), 0, s, a, (const dbl2 *)a.bh, 0, 0);
+        hipLaunchKernelGGL((wil::k_wil_init<ROWS, LPS, LP>), g, dim3(kWBlock), 0, s, a);
     }
     static void step(const wil::WArgs &a, hipStream_t s, int ver)
     {
         const dim3 g = grid(a.g.Vh);
-        hipLaunchKernelGGL((wil::k_wil_step1<ROWS, LPS>), g, dim3(kWBlock), 0, s, a, ver);
-        hipLaunchKernelGGL((wil::k_wil_step2<ROWS, LPS>), g, dim3(kWBlock), 0, s, a, ver);
-        hipLaunchKernelGGL((wil::k_wil_odd_g5<ROWS, LPS>), g, dim3(kWBlock), 0, s, a, (const dbl2 *)a.ap, ver, 1);
-        hipLaunchKernelGGL((wil::k_wil_step4<ROWS, LPS>), g, dim3(kWBlock), 0, s, a, ver);
+        hipLaunchKernelGGL((wil::k_wil_step1<ROWS, LPS, LP>), g, dim3(kWBlock), 0, s, a, ver);
+        hipLaunchKernelGGL((wil::k_wil_step2<ROWS, LPS, LP>), g, dim3(kWBlock), 0, s, a, ver);
+        hipLaunchKernelGGL((wil::k_wil_odd_g5<ROWS, LPS, LP>), g, dim3(kWBlock), 0, s, a, (const dbl2 *)a.ap, ver, 1);
+        hipLaunchKernelGGL((wil::k_wil_step4<ROWS, LPS, LP>), g, dim3(kWBlock), 0, s, a, ver);
     }
     static void finish(const wil::WArgs &a, hipStream_t s)
     {
         const dim3 g = grid(a.g.Vh);
-        hipLaunchKernelGGL((wil::k_wil_xodd<ROWS, LPS>), g, dim3(kWBlock), 0, s, a);
-        hipLaunchKernelGGL((wil::k_wil_resid<ROWS, LPS>), g, dim3(kWBlock), 0, s, a, 0);
-        hipLaunchKernelGGL((wil::k_wil_resid<ROWS, LPS>), g, dim3(kWBlock), 0, s, a, 1);
+        hipLaunchKernelGGL((wil::k_wil_xodd<ROWS, LPS, LP>), g, dim3(kWBlock), 0, s, a);
+        hipLaunchKernelGGL((wil::k_wil_resid<ROWS, LPS, LP>), g, dim3(kWBlock), 0, s, a, 0);
+        hipLaunchKernelGGL((wil::k_wil_resid<ROWS, LPS, LP>), g, dim3(kWBlock), 0, s, a, 1);
     }
 };
 
 struct WTable {
-    void (*hop)(const GaugeField *, int, const double *, double *, hipStream_t);
+    void (*hop)(const GaugeField *, int, const double *, double *, int, hipStream_t);
     void (*init)(const wil::WArgs &, hipStream_t);
     void (*step)(const wil::WArgs &, hipStream_t, int);
     void (*finish)(const wil::WArgs &, hipStream_t);
 };
 
-template <int ROWS, int LPS> constexpr WTable wtable()
+template <int ROWS, int LPS, class LP> constexpr WTable wtable()
 {
-    return {WLaunch<ROWS, LPS>::hop, WLaunch<ROWS, LPS>::init, WLaunch<ROWS, LPS>::step, WLaunch<ROWS, LPS>::finish};
+    using W = WLaunch<ROWS, LPS, LP>;
+    return {W::hop, W::init, W::step, W::finish};
 }
 
 constexpr int kWLps[4] = {1, 2, 4, 8};
 
-const WTable &wilson_table(int rows, int lps)
+template <class LP> const WTable &wilson_table_of(int rows, int lps)
 {
-    static const WTable t[2][4] = {{wtable<2, 1>(), wtable<2, 2>(), wtable<2, 4>(), wtable<2, 8>()},
-                                   {wtable<3, 1>(), wtable<3, 2>(), wtable<3, 4>(), wtable<3, 8>()}};
+    static const WTable t[2][4] = {{wtable<2, 1, LP>(), wtable<2, 2, LP>(), wtable<2, 4, LP>(), wtable<2, 8, LP>()},
+                                   {wtable<3, 1, LP>(), wtable<3, 2, LP>(), wtable<3, 4, LP>(), wtable<3, 8, LP>()}};
     return t[rows == 2 ? 0 : 1][lps == 1 ? 0 : lps == 2 ? 1 : lps == 4 ? 2 : 3];
 }
 
-// Lanes per site for the Wilson kernels of a field: STAG_WILSON_LPS, else the
-// fastest hop on two full-field vectors of scratch (`in`, `out`, each
-// [2][12][Vh]), timed once per field; 4 when no scratch is given.
-int wilson_lps(Ctx *ctx, GaugeField *f, const double *in, double *out, hipStream_t s)
+// The launches for a field: its link format, the lanes per site and its
+// choice of link loads (nt_links)
+const WTable &wilson_table(const GaugeField *f, int lps)
+{
+    return f->nt_links ? wilson_table_of<PrecF64NT>(f->rows, lps) : wilson_table_of<PrecF64>(f->rows, lps);
+}
+
+// Lanes per site and block order (XCD-contiguous or not) for the Wilson
+// kernels of a field: STAG_WILSON_LPS fixes the lanes, else the fastest hop
+// on two full-field vectors of scratch (`in`, `out`, each [2][12][Vh]), timed
+// once per field; 4 lanes and the XCD order when no scratch is given.
+KernelCfg wilson_cfg(Ctx *ctx, GaugeField *f, const double *in, double *out, hipStream_t s)
 {
     const uint64_t key = (uint64_t)3 << 40;
+    int lps_env = 0;
     if (const char *e = getenv("STAG_WILSON_LPS")) {
         const int v = atoi(e);
         if (v == 1 || v == 2 || v == 4 || v == 8)
-            return v;
+            lps_env = v;
     }
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         auto it = f->tuned.find(key);
-        if (it != f->tuned.end())
-            return it->second.lps;
+        if (it != f->tuned.end() && (!lps_env || it->second.lps == lps_env))
+            return it->second;
     }
+    KernelCfg best;
+    best.lps = lps_env ? lps_env : 4;
+    best.remap = 1;
     if (!in || !out)
-        return 4;
+        return best;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-        return 4;
+        return best;
     // timed on one parity (half the sites), the work of each CG kernel: a
     // count that fills the GPU for the whole lattice can leave it half idle
     // there
-    int best = 4;
     float best_ms = 1e30f;
     const int reps = 5;
     for (int L : kWLps) {
-        const WTable &t = wilson_table(f->rows, L);
-        t.hop(f, 0, in, out, s);
-        (void)hipEventRecord(e0, s);
-        for (int i = 0; i < reps; ++i)
-            t.hop(f, 0, in, out, s);
-        (void)hipEventRecord(e1, s);
-        float ms = 0.f;
-        if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
-            ms < best_ms * 0.97f) {
-            best_ms = ms;
-            best = L;
+        if (lps_env && L != lps_env)
+            continue;
+        for (int remap = 1; remap >= 0; --remap) {
+            const WTable &t = wilson_table(f, L);
+            t.hop(f, 0, in, out, remap, s);
+            (void)hipEventRecord(e0, s);
+            for (int i = 0; i < reps; ++i)
+                t.hop(f, 0, in, out, remap, s);
+            (void)hipEventRecord(e1, s);
+            float ms = 0.f;
+            if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
+                ms < best_ms * 0.97f) {
+                best_ms = ms;
+                best.lps = L;
+                best.remap = remap;
+            }
+            if (getenv("STAG_TUNE_VERBOSE"))
+                fprintf(stderr, "[stag tune wilson] V=%d lps=%d remap=%d: %.2f us per parity\n", 2 * f->g.Vh, L,
+                        remap, ms * 1e3 / reps);
         }
-        if (getenv("STAG_TUNE_VERBOSE"))
-            fprintf(stderr, "[stag tune wilson] V=%d lps=%d: %.2f us per parity\n", 2 * f->g.Vh, L,
-                    ms * 1e3 / reps);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    KernelCfg c;
-    c.lps = best;
     std::lock_guard<std::mutex> lk(ctx->mu);
-    f->tuned[key] = c;
+    f->tuned[key] = best;
     return best;
 }
 
@@ -294,8 +310,8 @@ int wilson_lps(Ctx *ctx, GaugeField *f, const double *in, double *out, hipStream
 
 int wilson_dslash(Ctx *ctx, GaugeField *f, int out_parity, const double *in, double *out, hipStream_t s)
 {
-    const int lps = wilson_lps(ctx, f, nullptr, nullptr, s);
-    wilson_table(f->rows, lps).hop(f, out_parity == STAG_ALL ? -1 : out_parity, in, out, s);
+    const KernelCfg c = wilson_cfg(ctx, f, nullptr, nullptr, s);
+    wilson_table(f, c.lps).hop(f, out_parity == STAG_ALL ? -1 : out_parity, in, out, c.remap, s);
     STAG_HIP_CHECK(hipGetLastError());
     return STAG_OK;
 }
@@ -367,8 +383,10 @@ int wilson_cg_solve(Ctx *ctx, GaugeField *f, double kappa, double tol, int maxit
 
     // lanes per site: tuned on this workspace (bh|r and p[0]|p[1] are two
     // adjacent full-field vectors) before the solve uses it
-    const int lps = wilson_lps(ctx, f, (const double *)a.bh, (double *)a.p[0], s);
-    const WTable &tab = wilson_table(f->rows, lps);
+    const KernelCfg cfg = wilson_cfg(ctx, f, (const double *)a.bh, (double *)a.p[0], s);
+    const int lps = cfg.lps;
+    a.remap = cfg.remap;
+    const WTable &tab = wilson_table(f, lps);
     const int nblk = (int)(((int64_t)Vh * lps + kWBlock - 1) / kWBlock);
     tab.init(a, s);
     STAG_HIP_CHECK(hipGetLastError());

@@ -14,7 +14,10 @@
 //
 // Layout: links as for the staggered operator ([entry][tile][dir][site], FP64,
 // two or three stored rows); spinors of one parity as 12 planes of Vh complex
-// (plane = 3 * spin + colour), a full field as [parity][12][Vh].
+// (plane = 3 * spin + colour), a full field as [parity][12][Vh].  The template
+// parameter LP reads the links: PrecF64 with plain loads, PrecF64NT with
+// non-temporal ones (fields whose links do not fit the Infinity Cache, where
+// each link, read once per launch, would otherwise evict gathered spinors).
 #pragma once
 
 #include "hop.hpp"
@@ -105,7 +108,7 @@ __device__ __forceinline__ bool wilson_link_negative(const Geom &g, const SiteCo
 // ...) and summed over them, so every lane of the site ends with the total.
 // load(n, sp, col) returns component (sp, col) of the input at site n of the
 // other parity (with gamma_5 or any fused combination applied by the caller).
-template <int ROWS, int LPS, class Load>
+template <int ROWS, int LPS, class LP, class Load>
 __device__ __forceinline__ void wilson_hop(const Geom &g, const dbl2 *__restrict__ links, int p_out, int s, int sub,
                                            cplx<double> (&acc)[4][3], Load load)
 {
@@ -123,7 +126,7 @@ __device__ __forceinline__ void wilson_hop(const Geom &g, const dbl2 *__restrict
         const dbl2 *lp = links + link_offset(g.Vh, d, 0, s);
 #pragma unroll
         for (int k = 0; k < 3 * ROWS; ++k)
-            U[k] = PrecF64::load_link(lp + (int64_t)k * 8 * g.Vh);
+            U[k] = LP::load_link(lp + (int64_t)k * 8 * g.Vh);
         if constexpr (ROWS == 2)
             third_row(U, wilson_link_negative(g, c, d) ? -1.0 : 1.0);
         cplx<double> h[2][3];
@@ -197,28 +200,29 @@ __device__ __forceinline__ void put(dbl2 *v, int Vh, int n, int sp, int col, con
 }
 
 // Site and lane-within-site of this thread (LPS lanes per site, sub-major
-// within a wavefront), false for threads past the last site.
-template <int LPS> __device__ __forceinline__ bool wsite(int Vh, int &s, int &sub)
+// within a wavefront), false for threads past the last site.  With remap, the
+// blocks of each XCD cover one contiguous range of sites (logical_block).
+template <int LPS> __device__ __forceinline__ bool wsite(int Vh, int remap, int &s, int &sub)
 {
-    site_of_thread<LPS>((int)(blockIdx.x * blockDim.x + threadIdx.x), s, sub);
+    site_of_thread<LPS>((int)(logical_block(blockIdx.x, gridDim.x, remap) * blockDim.x + threadIdx.x), s, sub);
     return s < Vh;
 }
 
 // ---- the standalone hop: out_p = H_p in (one parity, or both with blockIdx.y) -------
 
-template <int ROWS, int LPS>
+template <int ROWS, int LPS, class LP>
 __global__ void __launch_bounds__(128)
 k_wilson_dslash(Geom g, const dbl2 *__restrict__ links, const dbl2 *__restrict__ in, dbl2 *__restrict__ out,
-                int par_fixed)
+                int par_fixed, int remap)
 {
     const int p = par_fixed >= 0 ? par_fixed : (int)blockIdx.y;
     const int Vh = g.Vh;
     int s, sub;
-    if (!wsite<LPS>(Vh, s, sub))
+    if (!wsite<LPS>(Vh, remap, s, sub))
         return;
     const dbl2 *src = in + (size_t)(1 - p) * 12 * Vh;
     cplx<double> acc[4][3];
-    wilson_hop<ROWS, LPS>(g, links + link_parity_entries(ROWS, Vh) * p, p, s, sub, acc,
+    wilson_hop<ROWS, LPS, LP>(g, links + link_parity_entries(ROWS, Vh) * p, p, s, sub, acc,
                           [&](int n, int sp, int col) { return comp(src, Vh, n, sp, col); });
     dbl2 *o = out + (size_t)p * 12 * Vh;
 #pragma unroll
@@ -264,6 +268,7 @@ struct WArgs {
     WState *st[2];
     double *partials;      // [2 buffers][2 slots: 0 <ap,ap>, 1 <r,r>][pstride]
     int pstride;
+    int remap;             // 1: XCD-contiguous site ranges (logical_block)
 };
 
 __device__ __forceinline__ double *wslot(const WArgs &a, int buf, int slot)
@@ -338,15 +343,15 @@ __device__ __forceinline__ double wuniform(double v)
 }
 
 // init 1 (even outputs): bh = b_e + kappa (H b)_e
-template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_bhat(WArgs a)
+template <int ROWS, int LPS, class LP> __global__ void __launch_bounds__(128) k_wil_bhat(WArgs a)
 {
     const int Vh = a.g.Vh;
     int s, sub;
-    if (!wsite<LPS>(Vh, s, sub))
+    if (!wsite<LPS>(Vh, a.remap, s, sub))
         return;
     const dbl2 *bo = a.b + (size_t)12 * Vh;
     cplx<double> acc[4][3];
-    wilson_hop<ROWS, LPS>(a.g, a.links[0], 0, s, sub, acc,
+    wilson_hop<ROWS, LPS, LP>(a.g, a.links[0], 0, s, sub, acc,
                           [&](int n, int sp, int col) { return comp(bo, Vh, n, sp, col); });
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
@@ -360,17 +365,17 @@ template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_bhat(W
 
 // odd outputs: t = H_oe (gamma_5 src).  With a state (K3 of a step) it runs
 // only while the system iterates; without one (initialisation) always.
-template <int ROWS, int LPS>
+template <int ROWS, int LPS, class LP>
 __global__ void __launch_bounds__(128) k_wil_odd_g5(WArgs a, const dbl2 *__restrict__ src, int ver, int check)
 {
     if (check && a.st[ver ^ 1]->mode != W_CG)
         return;
     const int Vh = a.g.Vh;
     int s, sub;
-    if (!wsite<LPS>(Vh, s, sub))
+    if (!wsite<LPS>(Vh, a.remap, s, sub))
         return;
     cplx<double> acc[4][3];
-    wilson_hop<ROWS, LPS>(a.g, a.links[1], 1, s, sub, acc, [&](int n, int sp, int col) {
+    wilson_hop<ROWS, LPS, LP>(a.g, a.links[1], 1, s, sub, acc, [&](int n, int sp, int col) {
         const cplx<double> z = comp(src, Vh, n, sp, col);
         return sp < 2 ? z : cplx<double>{-z.re, -z.im};
     });
@@ -384,15 +389,15 @@ __global__ void __launch_bounds__(128) k_wil_odd_g5(WArgs a, const dbl2 *__restr
 
 // init 3 (even outputs): r = bh - kappa^2 gamma_5 (H t)_e = Mhat^dagger bh;
 // p[0] = r; x_e = 0; <r,r> into slot 1 of buffer 0
-template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_init(WArgs a)
+template <int ROWS, int LPS, class LP> __global__ void __launch_bounds__(128) k_wil_init(WArgs a)
 {
     __shared__ double lds[4];
     const int Vh = a.g.Vh;
     int s, sub;
     double nrm = 0.0;
-    if (wsite<LPS>(Vh, s, sub)) {
+    if (wsite<LPS>(Vh, a.remap, s, sub)) {
         cplx<double> acc[4][3];
-        wilson_hop<ROWS, LPS>(a.g, a.links[0], 0, s, sub, acc,
+        wilson_hop<ROWS, LPS, LP>(a.g, a.links[0], 0, s, sub, acc,
                               [&](int n, int sp, int col) { return comp(a.t, Vh, n, sp, col); });
         const double k2 = a.kappa * a.kappa;
 #pragma unroll
@@ -416,7 +421,7 @@ template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_init(W
 // K1 (odd outputs): advance the state over the previous step, then
 // t = H_oe p' with p' = r + beta p formed at every gathered neighbour; p' is
 // also stored at the partner site (same index, even parity).
-template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_step1(WArgs a, int ver)
+template <int ROWS, int LPS, class LP> __global__ void __launch_bounds__(128) k_wil_step1(WArgs a, int ver)
 {
     __shared__ double lds[8];
     __shared__ __align__(16) WState sst;
@@ -483,10 +488,10 @@ template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_step1(
     const dbl2 *pold = a.p[pn ^ 1];
     dbl2 *pnew = a.p[pn];
     int s, sub;
-    if (!wsite<LPS>(Vh, s, sub))
+    if (!wsite<LPS>(Vh, a.remap, s, sub))
         return;
     cplx<double> acc[4][3];
-    wilson_hop<ROWS, LPS>(a.g, a.links[1], 1, s, sub, acc, [&](int n, int sp, int col) {
+    wilson_hop<ROWS, LPS, LP>(a.g, a.links[1], 1, s, sub, acc, [&](int n, int sp, int col) {
         const cplx<double> r = comp(a.r, Vh, n, sp, col), p = comp(pold, Vh, n, sp, col);
         return cplx<double>{fma(beta, p.re, r.re), fma(beta, p.im, r.im)};
     });
@@ -504,7 +509,7 @@ template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_step1(
 
 // K2 (even outputs): ap = p' - kappa^2 (H t)_e = Mhat p'; <ap,ap> into slot 0
 // of buffer ver^1
-template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_step2(WArgs a, int ver)
+template <int ROWS, int LPS, class LP> __global__ void __launch_bounds__(128) k_wil_step2(WArgs a, int ver)
 {
     __shared__ double lds[4];
     const WState *st = a.st[ver ^ 1];
@@ -514,9 +519,9 @@ template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_step2(
     const int Vh = a.g.Vh;
     int s, sub;
     double nrm = 0.0;
-    if (wsite<LPS>(Vh, s, sub)) {
+    if (wsite<LPS>(Vh, a.remap, s, sub)) {
         cplx<double> acc[4][3];
-        wilson_hop<ROWS, LPS>(a.g, a.links[0], 0, s, sub, acc,
+        wilson_hop<ROWS, LPS, LP>(a.g, a.links[0], 0, s, sub, acc,
                               [&](int n, int sp, int col) { return comp(a.t, Vh, n, sp, col); });
         const double k2 = a.kappa * a.kappa;
 #pragma unroll
@@ -537,7 +542,7 @@ template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_step2(
 // K4 (even outputs): alpha = rr / <ap,ap>; atap = ap - kappa^2 gamma_5 (H t)_e
 // (= Mhat^dagger Mhat p'); x += alpha p'; r -= alpha atap; <r,r> into slot 1 of
 // buffer ver^1
-template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_step4(WArgs a, int ver)
+template <int ROWS, int LPS, class LP> __global__ void __launch_bounds__(128) k_wil_step4(WArgs a, int ver)
 {
     __shared__ double lds[8];
     const WState *st = a.st[ver ^ 1];
@@ -552,9 +557,9 @@ template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_step4(
     const int Vh = a.g.Vh;
     int s, sub;
     double nrm = 0.0;
-    if (wsite<LPS>(Vh, s, sub)) {
+    if (wsite<LPS>(Vh, a.remap, s, sub)) {
         cplx<double> acc[4][3];
-        wilson_hop<ROWS, LPS>(a.g, a.links[0], 0, s, sub, acc,
+        wilson_hop<ROWS, LPS, LP>(a.g, a.links[0], 0, s, sub, acc,
                               [&](int n, int sp, int col) { return comp(a.t, Vh, n, sp, col); });
         const double k2 = a.kappa * a.kappa;
 #pragma unroll
@@ -579,14 +584,14 @@ template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_step4(
 }
 
 // x_o = b_o + kappa (H x_e)_o
-template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_xodd(WArgs a)
+template <int ROWS, int LPS, class LP> __global__ void __launch_bounds__(128) k_wil_xodd(WArgs a)
 {
     const int Vh = a.g.Vh;
     int s, sub;
-    if (!wsite<LPS>(Vh, s, sub))
+    if (!wsite<LPS>(Vh, a.remap, s, sub))
         return;
     cplx<double> acc[4][3];
-    wilson_hop<ROWS, LPS>(a.g, a.links[1], 1, s, sub, acc,
+    wilson_hop<ROWS, LPS, LP>(a.g, a.links[1], 1, s, sub, acc,
                           [&](int n, int sp, int col) { return comp(a.x, Vh, n, sp, col); });
     const dbl2 *bo = a.b + (size_t)12 * Vh;
     dbl2 *xo = a.x + (size_t)12 * Vh;
@@ -602,16 +607,16 @@ template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_xodd(W
 
 // |b - M x|^2 on the sites of parity `par`, per block into slot `par` of
 // buffer 0 (the solve is over when this runs)
-template <int ROWS, int LPS> __global__ void __launch_bounds__(128) k_wil_resid(WArgs a, int par)
+template <int ROWS, int LPS, class LP> __global__ void __launch_bounds__(128) k_wil_resid(WArgs a, int par)
 {
     __shared__ double lds[4];
     const int Vh = a.g.Vh;
     int s, sub;
     double nrm = 0.0;
-    if (wsite<LPS>(Vh, s, sub)) {
+    if (wsite<LPS>(Vh, a.remap, s, sub)) {
         const dbl2 *xin = a.x + (size_t)(1 - par) * 12 * Vh;
         cplx<double> acc[4][3];
-        wilson_hop<ROWS, LPS>(a.g, a.links[par], par, s, sub, acc,
+        wilson_hop<ROWS, LPS, LP>(a.g, a.links[par], par, s, sub, acc,
                               [&](int n, int sp, int col) { return comp(xin, Vh, n, sp, col); });
         const dbl2 *bp = a.b + (size_t)par * 12 * Vh;
         const dbl2 *xp = a.x + (size_t)par * 12 * Vh;

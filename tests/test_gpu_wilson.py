@@ -228,3 +228,24 @@ def test_every_lanes_per_site(lps):
                             label="Wilson lanes per site %s" % lps)
     finally:
         del os.environ["STAG_WILSON_LPS"]
+
+
+@pytest.mark.parametrize("lps", ["1", "4"])
+def test_nontemporal_link_loads_give_the_same_bits(monkeypatch, lps):
+    # fields whose links exceed the Infinity Cache read them with non-temporal
+    # loads (STAG_NT_LINKS forces either kind): the hop and every CG iterate
+    # are the same to the bit
+    dims = (6, 4, 2, 10)
+    U = inputs.haar_su3(dims, 71)
+    psi = inputs.gaussian_spinor(dims, 72)
+    monkeypatch.setenv("STAG_WILSON_LPS", lps)
+    res = {}
+    for nt in ("0", "1"):
+        monkeypatch.setenv("STAG_NT_LINKS", nt)
+        with binding.Context(device=0, arena_bytes=64 << 20) as ctx:
+            f = ctx.set_gauge_wilson(dims, U)
+            x, info = solve(ctx, f, psi, 0.11, tol=1e-10)
+            res[nt] = (hop(ctx, f, psi), x, info["iters"])
+    assert np.array_equal(res["0"][0], res["1"][0])
+    assert np.array_equal(res["0"][1], res["1"][1]) and res["0"][2] == res["1"][2]
+    assert site_err(res["1"][0], oracle.wilson_hop(dims, U, psi)) <= TOL
