@@ -9,6 +9,9 @@ configuration the benchmark times (the tuned kernels).
   * FP32 / FP16 reliable updates: the oracle's true residual <= 1e-10, and
     the error against the oracle's tight solve (O4, 1e-13) stated and bounded
     by kappa * true residual, kappa from the extreme Ritz values of O3.
+Wilson fermions on the same 32^4 links (the largest field of the hop
+benchmark, links read non-temporally): the hop on every site to 1e-13 and a
+CG solve at kappa = 0.12 checked by the oracle's true residual.
 24^4 twelve sources (seed 104, sources 2040-2051, m = linspace(0.01, 0.2)):
   the batched FP32 and FP16 reliable-update solves, every system checked by
   the oracle's true residual and its error against the tight solve stated
@@ -186,3 +189,32 @@ def test_config4_serving_full_size_fields(gpu_ctx):
     finally:
         for _, _, f in fields:
             gpu_ctx.free_gauge(f)
+
+
+def test_wilson_32_full_size(gpu_ctx, c3):
+    dims, _, U, _, _ = c3
+    psi = inputs.gaussian_spinor(dims, 204)
+    f = gpu_ctx.set_gauge_wilson(dims, U)
+    try:
+        note("32^4 Wilson hop")
+        pin = gpu_ctx.pack_spinor(f, psi)
+        out = gpu_ctx.new_spinor(f)
+        gpu_ctx.wilson_dslash(f, pin, out)
+        got = gpu_ctx.unpack_spinor(f, out).cpu().numpy().reshape(len(psi), -1)
+        ref = oracle.wilson_hop(dims, U, psi).reshape(len(psi), -1)
+        n = np.linalg.norm(ref, axis=1)
+        assert np.max(np.linalg.norm(got - ref, axis=1) / n) <= 1e-13
+        del got, ref
+        note("32^4 Wilson solve")
+        x = gpu_ctx.new_spinor(f)
+        info = gpu_ctx.wilson_solve(f, pin, x, 0.12, tol=1e-10, check=False)
+        torch.cuda.synchronize()
+        xl = gpu_ctx.unpack_spinor(f, x).cpu().numpy()
+        tr = np.linalg.norm(psi - oracle.wilson_apply(dims, U, 0.12, xl)) / np.linalg.norm(psi)
+        note("32^4 Wilson: %d iterations, true residual %.3g (GPU %.3g)" % (
+            info["iters"], tr, info["true_rel_resid"]))
+        assert info["status"] == 0
+        assert abs(info["true_rel_resid"] - tr) <= 1e-3 * tr + 1e-15
+        assert tr <= 1e-8
+    finally:
+        gpu_ctx.free_gauge(f)
