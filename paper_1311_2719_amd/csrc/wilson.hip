@@ -270,8 +270,11 @@ KernelCfg wilson_cfg(Ctx *ctx, GaugeField *f, const double *in, double *out, hip
     if (!in || !out)
         return best;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0)
+            (void)hipEventDestroy(e0);
         return best;
+    }
     // timed on one parity (half the sites), the work of each CG kernel: a
     // count that fills the GPU for the whole lattice can leave it half idle
     // there
