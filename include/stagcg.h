@@ -206,7 +206,9 @@ int stag_unpack_fermion(stag_ctx *ctx, const int32_t dims[4], const double *eo,
  * Only the other parity of `in` is read.  Sites outside the range are
  * untouched.
  * on_device = 1: in and out are device pointers; the call is asynchronous
- *   on `stream` (NULL = the context's stream); they must not overlap.
+ *   on `stream` (NULL = the context's stream); they must not overlap.  The
+ *   first call for a field and precision times the kernel shapes on scratch
+ *   from the arena and waits for that.
  * on_device = 0: in and out are host pointers (the paper's copyin / copyout
  *   of Sec. 4): the input half is copied to the device, D applied there, the
  *   output range copied back into `out` (and first copied in when
@@ -493,7 +495,9 @@ int stag_unpack_spinor(stag_ctx *ctx, const int32_t dims[4], const double *eo,
 /* out = H in on the sites of out_parity (STAG_EVEN / STAG_ODD: the other
  * parity of `out` is not written; STAG_ALL: every site).  in, out: device
  * even-odd spin-colour vectors, not overlapping.  Errors: EINVAL, ENOENT.
- * Asynchronous on `stream`. */
+ * Asynchronous on `stream`, except that the first hop or solve of a field
+ * times the kernel shapes on scratch vectors from the arena (the defaults if
+ * they do not fit) and waits for that. */
 int stag_wilson_dslash(stag_ctx *ctx, int32_t gauge_id, int32_t out_parity,
                        const double *in, double *out, void *stream);
 

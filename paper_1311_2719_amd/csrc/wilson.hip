@@ -248,7 +248,8 @@ const WTable &wilson_table(const GaugeField *f, int lps)
 // Lanes per site and block order (XCD-contiguous or not) for the Wilson
 // kernels of a field: STAG_WILSON_LPS fixes the lanes, else the fastest hop
 // on two full-field vectors of scratch (`in`, `out`, each [2][12][Vh]), timed
-// once per field; 4 lanes and the XCD order when no scratch is given.
+// once per field (by its first solve or first standalone hop); 4 lanes and
+// the XCD order when no scratch is given.
 KernelCfg wilson_cfg(Ctx *ctx, GaugeField *f, const double *in, double *out, hipStream_t s)
 {
     const uint64_t key = (uint64_t)3 << 40;
@@ -313,7 +314,25 @@ KernelCfg wilson_cfg(Ctx *ctx, GaugeField *f, const double *in, double *out, hip
 
 int wilson_dslash(Ctx *ctx, GaugeField *f, int out_parity, const double *in, double *out, hipStream_t s)
 {
-    const KernelCfg c = wilson_cfg(ctx, f, nullptr, nullptr, s);
+    bool tuned;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        tuned = f->tuned.count((uint64_t)3 << 40) != 0;
+    }
+    KernelCfg c = wilson_cfg(ctx, f, nullptr, nullptr, s);
+    if (!tuned) {
+        // the first hop of a field times the shapes on two scratch vectors
+        // from the arena (as the first solve does on its workspace); without
+        // the room, the defaults
+        const size_t full = (size_t)2 * 12 * f->g.Vh * sizeof(dbl2);
+        char *scratch = (char *)ctx->arena.alloc(2 * full);
+        if (scratch) {
+            if (hipMemsetAsync(scratch, 0, full, s) == hipSuccess)
+                c = wilson_cfg(ctx, f, (const double *)scratch, (double *)(scratch + full), s);
+            (void)hipStreamSynchronize(s);
+            ctx->arena.release(scratch);
+        }
+    }
     wilson_table(f, c.lps).hop(f, out_parity == STAG_ALL ? -1 : out_parity, in, out, c.remap, s);
     STAG_HIP_CHECK(hipGetLastError());
     return STAG_OK;
